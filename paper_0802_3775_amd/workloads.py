@@ -1,0 +1,214 @@
+"""Seeded synthetic workloads: plain configuration dicts shared by the GPU
+library's tests and benchmark and by the CPU oracle.
+
+This module only lays out inputs (grid sizes, seeds, material parameters,
+source and probe placement, random initial fields).  It holds none of the
+method's arithmetic: coefficients, time steps, CPML profiles, waveforms and
+geometry all live on each side of the comparison separately.
+
+Paper context (arXiv:0802.3775, section "Sample and numerical approach"):
+inverted opal with eps_r = 12 (here 11.9), lattice constant a = 480 nm, air
+spheres at fcc sites, r0 = a/(2 sqrt 2) (here 0.35 a), 200^3 grids, 10^5 steps;
+a Rhodamine-like gain medium (n = 1.3) fills the spheres for the lasing runs.
+
+Config dict schema::
+
+    {"grid": {"n": (nx, ny, nz), "periodic": (px, py, pz), "pml_lo": (..), "pml_hi": (..),
+              "cpml": {"m", "sigma_max", "kappa_max", "alpha_max"},
+              "res": cells per a, "courant": dt/dx, "a_meters": .., "seed": .., "realization": ..},
+     "materials": [{"eps": .., "gain": 0/1, "n_total", "tau32", "tau21", "tau10", "pump",
+                    "f_a", "df_a", "noise", "n_init"}, ...],
+     "opal": {"cells", "origin", "r0", "disorder": none|uniform|gauss, "strength",
+              "mat_bg", "mat_void", "mat_out"} or None,
+     "map": optional uint8 [nz, ny, nx],
+     "sources": [{"kind": dipole|plane, "comp", "i", "j", "k", "f0",
+                  "width_kind": fwhm_power|fwhm_intensity|sigma_t, "width", "delay", "amp"}],
+     "probes": [(comp, i, j, k)], "flux": [{"k", "freqs", "decim"}],
+     "energy_interval": int, "steps": int, "init_fields": {comp: array}}
+"""
+import numpy as np
+
+A_METERS = 480e-9                      # lattice constant, paper value
+PULSE_30FS_A_OVER_C = 18.737028625     # 30 fs in units of a/c at a = 480 nm
+ALPHA_MAX = 0.3141592653589793         # CPML alpha_max = 2 pi * 0.05 (c/a)
+CPML = {"m": 3.0, "sigma_max": -1.0, "kappa_max": 1.0, "alpha_max": ALPHA_MAX}
+EPS_BG = 11.9
+EPS_DYE = 1.69                         # n = 1.3 dye in the voids
+PML = 12
+
+FLUX_FREQS = tuple(float(f) for f in np.linspace(0.6, 1.0, 100))
+
+
+def gain_material(pump=1e10, noise=1e-6, n_total=1e24, n_init=(1.0, 0.0, 0.0, 0.0),
+                  tau32=1e-13, tau21=1e-9, tau10=1e-13, f_a=0.75, df_a=0.02, eps=EPS_DYE):
+    return {"eps": eps, "gain": 1, "n_total": n_total, "tau32": tau32, "tau21": tau21,
+            "tau10": tau10, "pump": pump, "f_a": f_a, "df_a": df_a, "noise": noise,
+            "n_init": tuple(n_init)}
+
+
+def _grid(n, periodic, res, pml=(0, 0, 0), seed=0, realization=0, courant=0.5):
+    lo = tuple(p if not per else 0 for p, per in zip(pml, periodic))
+    return {"n": tuple(int(v) for v in n), "periodic": tuple(int(v) for v in periodic),
+            "pml_lo": lo, "pml_hi": lo, "cpml": dict(CPML), "res": int(res),
+            "courant": courant, "a_meters": A_METERS, "seed": int(seed),
+            "realization": int(realization)}
+
+
+def periodic_cell(res=32, seed=1, steps=2000, cells=1):
+    """One cubic fcc cell of the inverted opal, periodic box, Ez dipole at a seeded
+    random cell (centre 0.8 c/a, power-spectrum FWHM 0.3 c/a), Ez probe at a second
+    seeded cell."""
+    n = cells * res
+    rng = np.random.default_rng(seed)
+    src = rng.integers(0, n, 3)
+    prb = src
+    while np.array_equal(prb, src):
+        prb = rng.integers(0, n, 3)
+    return {
+        "name": "periodic_cell_%d" % n,
+        "grid": _grid((n, n, n), (1, 1, 1), res, seed=seed),
+        "materials": [{"eps": EPS_BG}, {"eps": 1.0}],
+        "opal": {"cells": (cells,) * 3, "origin": (0, 0, 0), "r0": 0.35, "disorder": "none",
+                 "strength": 0.0, "mat_bg": 0, "mat_void": 1, "mat_out": 1},
+        "sources": [{"kind": "dipole", "comp": 2, "i": int(src[0]), "j": int(src[1]),
+                     "k": int(src[2]), "f0": 0.8, "width_kind": "fwhm_power", "width": 0.3,
+                     "delay": 6.0, "amp": 1.0}],
+        "probes": [(2, int(prb[0]), int(prb[1]), int(prb[2]))],
+        "flux": [],
+        "energy_interval": 0,
+        "steps": steps,
+    }
+
+
+def slab(delta=0.05, seed=11, res=20, cells=(4, 4, 8), steps=20000, nf=100, decim=8,
+         energy_interval=0, empty=False, realization=0, margin_cells=None, pml=PML):
+    """Disordered inverted-opal slab for pulse transmission: periodic x, y; along z
+    CPML | vacuum margin (1 a) | crystal | vacuum margin | CPML.  Ey plane-wave pulse
+    (30 fs intensity FWHM, 0.8 c/a) launched from the middle of the front margin;
+    transmission plane in the middle of the back margin; reflection plane between
+    the source and the front CPML; Ey probe at a seeded point inside the crystal."""
+    nx, ny = cells[0] * res, cells[1] * res
+    margin = res if margin_cells is None else margin_cells
+    ncz = cells[2] * res
+    nz = 2 * pml + 2 * margin + ncz
+    z0 = pml + margin
+    k_src = pml + margin // 2
+    k_tr = z0 + ncz + margin // 2
+    k_ref = pml + max(1, margin // 4)
+    rng = np.random.default_rng(seed + 7919)
+    pi_, pj_, pk_ = rng.integers(0, nx), rng.integers(0, ny), z0 + rng.integers(0, ncz)
+    freqs = tuple(float(f) for f in np.linspace(0.6, 1.0, nf)) if nf > 0 else ()
+    return {
+        "name": "slab_%dx%dx%d_R%d_d%.3f%s" % (cells + (res, delta, "_empty" if empty else "")),
+        "grid": _grid((nx, ny, nz), (1, 1, 0), res, pml=(0, 0, pml), seed=seed,
+                      realization=realization),
+        "materials": [{"eps": EPS_BG}, {"eps": 1.0}],
+        "opal": None if empty else {
+            "cells": tuple(cells), "origin": (0, 0, z0), "r0": 0.35,
+            "disorder": "gauss" if delta > 0 else "none", "strength": float(delta),
+            "mat_bg": 0, "mat_void": 1, "mat_out": 1},
+        "map": np.ones((nz, ny, nx), dtype=np.uint8) if empty else None,
+        "sources": [{"kind": "plane", "comp": 1, "k": int(k_src), "f0": 0.8,
+                     "width_kind": "fwhm_intensity", "width": PULSE_30FS_A_OVER_C,
+                     "delay": 5.0, "amp": 1.0}],
+        "probes": [(1, int(pi_), int(pj_), int(pk_))],
+        "flux": ([{"k": int(k_tr), "freqs": freqs, "decim": decim},
+                  {"k": int(k_ref), "freqs": freqs, "decim": decim}] if nf > 0 else []),
+        "energy_interval": energy_interval,
+        "steps": steps,
+        "layout": {"z0": z0, "k_src": k_src, "k_tr": k_tr, "k_ref": k_ref},
+    }
+
+
+def ensemble(count=64, seed0=1000, steps=10000, max_cells=1_400_000, n_range=(4, 6),
+             res_range=(16, 24)):
+    """Uneven disorder realizations: delta ~ U[0, 0.12] a, n^3 cubic cells with
+    n in {4, 5, 6} and res in {16..24}, redrawn while (n res)^3 exceeds max_cells;
+    slab layout (vacuum margins, z-CPML), same pulse in physical time."""
+    if (n_range[0] * res_range[0]) ** 3 > max_cells:
+        raise ValueError("no (n, res) pair fits max_cells")
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng(seed0 + i)
+        delta = float(rng.uniform(0.0, 0.12))
+        while True:
+            n = int(rng.integers(n_range[0], n_range[1] + 1))
+            res = int(rng.integers(res_range[0], res_range[1] + 1))
+            if (n * res) ** 3 <= max_cells:
+                break
+        c = slab(delta=delta, seed=seed0 + i, res=res, cells=(n, n, n), steps=steps)
+        c["name"] = "ens%02d_n%d_R%d_d%.3f" % (i, n, res, delta)
+        out.append(c)
+    return out
+
+
+def lasing(pump=1e10, delta=0.05, seed=7, res=24, cells=(6, 6, 6), steps=100000, noise=1e-6,
+           n_init=(1.0, 0.0, 0.0, 0.0), energy_interval=100, pml=PML, tau21=1e-9):
+    """Maxwell-Bloch lasing box: the crystal flush with a CPML on all six faces, gain
+    medium in the voids, vacuum in the PML, seeded polarization noise, Ez probe at a
+    seeded cell inside the crystal, energy every energy_interval steps."""
+    n = [c * res + 2 * pml for c in cells]
+    rng = np.random.default_rng(seed + 104729)
+    p = [int(pml + rng.integers(0, c * res)) for c in cells]
+    return {
+        "name": "lasing_%dx%dx%d_R%d_P%.0e" % (tuple(cells) + (res, pump)),
+        "grid": _grid(n, (0, 0, 0), res, pml=(pml, pml, pml), seed=seed),
+        "materials": [{"eps": EPS_BG},
+                      gain_material(pump=pump, noise=noise, n_init=n_init, tau21=tau21),
+                      {"eps": 1.0}],
+        "opal": {"cells": tuple(cells), "origin": (pml, pml, pml), "r0": 0.35,
+                 "disorder": "gauss" if delta > 0 else "none", "strength": float(delta),
+                 "mat_bg": 0, "mat_void": 1, "mat_out": 2},
+        "sources": [],
+        "probes": [(2, p[0], p[1], p[2])],
+        "flux": [],
+        "energy_interval": energy_interval,
+        "steps": steps,
+    }
+
+
+def serving_trace(count=200, seed=42, rho=0.9, capacity_per_s=1.0, linear_frac=0.7,
+                  n_range=(4, 10), res_range=(16, 32), cell_range=(1_000_000, 33_000_000),
+                  linear_steps=10000, lasing_steps=20000):
+    """Poisson stream of mixed requests: (arrival_s, kind, n, res, delta, seed, steps).
+    Arrival rate = rho * capacity_per_s requests per second."""
+    rng = np.random.default_rng(seed)
+    pairs = [(n, r) for n in range(n_range[0], n_range[1] + 1)
+             for r in range(res_range[0], res_range[1] + 1)
+             if cell_range[0] <= (n * r) ** 3 <= cell_range[1]]
+    t = 0.0
+    reqs = []
+    for q in range(count):
+        t += float(rng.exponential(1.0 / (rho * capacity_per_s)))
+        n, r = pairs[int(rng.integers(0, len(pairs)))]
+        kind = "linear" if rng.uniform() < linear_frac else "lasing"
+        reqs.append({"id": q, "arrival": t, "kind": kind, "n": n, "res": r,
+                     "delta": float(rng.uniform(0.0, 0.12)), "seed": int(seed * 1000 + q),
+                     "steps": linear_steps if kind == "linear" else lasing_steps})
+    return reqs
+
+
+def homogeneous_box(n=(8, 8, 8), periodic=(1, 1, 1), res=16, eps=1.0, pml=(0, 0, 0), seed=0,
+                    materials=None, steps=100):
+    """Uniform medium (material 0 everywhere), no sources: for closed-form checks."""
+    nx, ny, nz = n
+    return {
+        "name": "box_%dx%dx%d" % n,
+        "grid": _grid(n, periodic, res, pml=pml, seed=seed),
+        "materials": materials if materials is not None else [{"eps": eps}],
+        "opal": None,
+        "map": np.zeros((nz, ny, nx), dtype=np.uint8),
+        "sources": [], "probes": [], "flux": [], "energy_interval": 0, "steps": steps,
+    }
+
+
+def random_map(n, nmat, seed):
+    nx, ny, nz = n
+    return np.random.default_rng(seed).integers(0, nmat, (nz, ny, nx)).astype(np.uint8)
+
+
+def random_fields(n, seed, scale=1.0):
+    """Six random field arrays (Ex..Hz), [nz, ny, nx], normal with std `scale`."""
+    nx, ny, nz = n
+    rng = np.random.default_rng(seed)
+    return {c: scale * rng.standard_normal((nz, ny, nx)) for c in range(6)}
