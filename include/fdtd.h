@@ -1,0 +1,223 @@
+/*
+ * libfdtd — MI355X (gfx950) Yee-FDTD stepper for gain-filled disordered
+ * inverted opals.  C ABI: plain pointers, sizes and status codes.
+ *
+ * Method (C. Conti and A. Fratalocchi, arXiv:0802.3775):
+ *   - Yee leapfrog FDTD with absorbing walls and an inverted-opal index
+ *     profile: section "Sample and numerical approach".
+ *   - Disorder r = r0 (1 + gamma xi), xi uniform in [-1/2, 1/2]: same section.
+ *   - Pumped gain medium in the spheres with a stochastic spontaneous-emission
+ *     source: same section and the lasing section ("3+1D simulation of lasing").
+ *   - Transmitted power T(t), the transversely integrated Poynting vector at the
+ *     output face: section "Dynamical diffusion and localization".
+ * The gain medium is a Lorentz polarization driven by four-level rate equations
+ * (not the paper's su(4) density-matrix form).
+ *
+ * Units: c = eps0 = mu0 = 1; lengths in a (cubic lattice constant), time in
+ * a/c, frequency in c/a.  dx = 1/res, dt = courant * dx.  SI enters only through
+ * the gain parameters, converted with a_meters.
+ *
+ * Layout: every per-cell array is [nz][ny][nx], x fastest, FP32 fields.  Yee
+ * positions in units of dx: Ex (i+1/2,j,k) Ey (i,j+1/2,k) Ez (i,j,k+1/2)
+ * Hx (i,j+1/2,k+1/2) Hy (i+1/2,j,k+1/2) Hz (i+1/2,j+1/2,k).  Voxel (i,j,k) owns
+ * Ex, Ey, Ez at index (i,j,k): its material index sets their permittivity and
+ * gain.  After n steps, E holds E^n and H holds H^{n-1/2}.
+ *
+ * Ownership: the library owns host metadata and the opaque handles.  Device
+ * memory is owned by the caller: one arena per plan, at least
+ * fdtd_required_bytes() bytes, 256-byte aligned, alive until the plan is
+ * destroyed; the library never allocates device memory on the stepping path.
+ * Host buffers passed in or out are the caller's and are not retained.
+ *
+ * Streams: device work is ordered on the caller's stream (a hipStream_t passed
+ * as void*; NULL is the null stream).  fdtd_read_* and fdtd_write_* synchronize
+ * that stream before returning.  A plan is not thread-safe; distinct plans are
+ * independent.
+ *
+ * Errors: no exception crosses the ABI.  Every int-returning call returns
+ * FDTD_OK (0) or a negative FDTD_E* code and records a message retrievable with
+ * fdtd_last_error() (thread-local).
+ */
+#ifndef FDTD_H
+#define FDTD_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FDTD_OK 0
+#define FDTD_EINVAL (-1)       /* bad argument or configuration */
+#define FDTD_ENOMEM (-2)       /* arena too small / host allocation failed */
+#define FDTD_EHIP (-3)         /* a HIP runtime call failed */
+#define FDTD_ESTATE (-4)       /* call not allowed in the plan's current state */
+#define FDTD_EUNSTABLE (-5)    /* courant >= 1/sqrt(3) or an unstable oscillator */
+#define FDTD_EUNSUPPORTED (-6) /* valid request outside what this build implements */
+
+#define FDTD_MAX_MATERIALS 16
+#define FDTD_MAX_SOURCES 4
+#define FDTD_MAX_PROBES 16
+#define FDTD_MAX_FLUX 4
+
+enum { FDTD_BC_PERIODIC = 0, FDTD_BC_PEC = 1 };
+enum { FDTD_SRC_DIPOLE = 0, FDTD_SRC_PLANE = 1 };
+enum { FDTD_WIDTH_FWHM_POWER = 0, FDTD_WIDTH_FWHM_INTENSITY = 1, FDTD_WIDTH_SIGMA_T = 2 };
+enum { FDTD_DISORDER_NONE = 0, FDTD_DISORDER_UNIFORM_RADIUS = 1, FDTD_DISORDER_GAUSS_JITTER = 2 };
+
+typedef struct fdtd_plan fdtd_plan;
+typedef struct fdtd_batch fdtd_batch;
+
+/* Grid.  bc[d]: FDTD_BC_PERIODIC or FDTD_BC_PEC (PEC walls at both ends of axis
+   d, optionally lined with pml_lo[d] / pml_hi[d] CPML layers).  CPML grading:
+   sigma = sigma_max (rho/d)^m, kappa = 1 + (kappa_max - 1)(rho/d)^m,
+   alpha = alpha_max (1 - rho/d); sigma_max <= 0 selects 0.8 (m + 1) / dx.
+   seed / realization key the counter-based generator (geometry and noise). */
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t bc[3];
+  int32_t pml_lo[3], pml_hi[3];
+  double cpml_m, cpml_sigma_max, cpml_kappa_max, cpml_alpha_max;
+  int32_t res;        /* cells per lattice constant a */
+  double courant;     /* dt / dx, must be < 1/sqrt(3) */
+  double a_meters;    /* lattice constant in metres */
+  uint32_t seed, realization;
+} fdtd_grid_desc;
+
+/* Material.  eps: relative permittivity (host permittivity of a gain medium).
+   gain = 1: four-level medium with total density n_total (m^-3), lifetimes
+   tau32, tau21, tau10 (s), pump rate 0->3 (s^-1), Lorentz transition f_a and
+   FWHM linewidth df_a (c/a), noise amplitude, initial fractions n_init[0..3]. */
+typedef struct {
+  double eps;
+  int32_t gain;
+  double n_total, tau32, tau21, tau10, pump, f_a, df_a, noise;
+  double n_init[4];
+} fdtd_material;
+
+/* Source: s(t) = amp sin(2 pi f0 (t - t0)) exp(-(t - t0)^2 / (2 sigma_t^2)),
+   t0 = delay * sigma_t.  Width: FWHM of the power spectrum (c/a), FWHM of the
+   intensity envelope (a/c), or sigma_t (a/c).  DIPOLE: current s/dx^3 on E_comp
+   of cell (i,j,k).  PLANE: sheet current s on E_comp over the whole z = k plane. */
+typedef struct {
+  int32_t kind, comp, i, j, k;
+  double f0;
+  int32_t width_kind;
+  double width, delay, amp;
+} fdtd_source_desc;
+
+/* Inverted opal: cells[3] cubic fcc cells starting at grid index origin[3];
+   air-sphere radius r0 (units of a); disorder with strength gamma (uniform
+   radius) or delta/a (Gaussian jitter of radii and centres, truncated at
+   4 delta).  Voxels inside any sphere get mat_void, the rest of the crystal
+   mat_bg, everything outside the crystal mat_out.  A periodic axis must be
+   spanned exactly by the crystal. */
+typedef struct {
+  int32_t cells[3], origin[3];
+  double r0;
+  int32_t disorder;
+  double strength;
+  int32_t mat_bg, mat_void, mat_out;
+} fdtd_opal_desc;
+
+/* Launch tuning (per plan).  block: threads per workgroup, one (i,j) column per
+   thread (64..256, multiple of 64); tile_x: tile width along x (16, 32 or 64;
+   the tile is tile_x x block/tile_x columns); zchunk: z-planes per tile (>= 1);
+   graph_steps: steps captured per hipGraph (0: no graph); max_blocks: upper
+   bound on resident workgroups for the tile loop (0: one per tile). */
+typedef struct {
+  int32_t block, zchunk, graph_steps, max_blocks, tile_x;
+} fdtd_tuning;
+
+const char* fdtd_last_error(void);
+const char* fdtd_version(void);
+
+/* Create a plan (host only).  Checks sizes, boundaries and the Courant limit. */
+int fdtd_plan_create(const fdtd_grid_desc* g, fdtd_plan** out);
+void fdtd_plan_destroy(fdtd_plan* p);
+
+/* Material table (n <= FDTD_MAX_MATERIALS).  Coefficients are built in FP64 and
+   rounded once to FP32. */
+int fdtd_set_materials(fdtd_plan* p, const fdtd_material* tab, int32_t n);
+
+/* Build the opal: the sphere list on the host (FP64, Philox key (seed,
+   realization), counter (site id, 0, 0, 0)) quantized to integers, then the
+   integer-exact voxelization on the device at bind.  Site id = h + (2nx+1)(k +
+   (2ny+1) l) for fcc sites (h, k, l)/2.  Alternatively give the map directly. */
+int fdtd_build_opal(fdtd_plan* p, const fdtd_opal_desc* d);
+int fdtd_set_material_map(fdtd_plan* p, const uint8_t* host_map);
+/* Quantized spheres: rows (site id, Cx, Cy, Cz, rho) in units of a/(2 res 2^16)
+   relative to the crystal origin.  out may be NULL to query n. */
+int fdtd_get_spheres(const fdtd_plan* p, int64_t* out, int64_t* n);
+/* Voxelized material map (after bind), [nz][ny][nx]. */
+int fdtd_get_material_map(fdtd_plan* p, uint8_t* host_map, void* stream);
+
+int fdtd_add_source(fdtd_plan* p, const fdtd_source_desc* s, int32_t* id);
+/* Probe of component comp (0..5 = Ex Ey Ez Hx Hy Hz) at (i,j,k), recorded after
+   every step (E^{n+1}, H^{n+1/2}). */
+int fdtd_add_probe(fdtd_plan* p, int32_t comp, int32_t i, int32_t j, int32_t k, int32_t* id);
+/* Flux plane normal to z at index k: T(t_{n+1/2}) = sum over the plane of the
+   time-centred S_z dx^2 every step, and the running DFT of Ex, Ey (time n) and
+   the z-averaged Hx, Hy (time n+1/2) at nf frequencies f (c/a) every decim steps,
+   FP64 accumulators. */
+int fdtd_add_flux_plane(fdtd_plan* p, int32_t k, const double* f, int32_t nf, int32_t decim,
+                        int32_t* id);
+/* Energy W^n = 1/2 sum (eps |E^n|^2 + H^{n-1/2} . H^{n+1/2}) dx^3 every ke steps. */
+int fdtd_set_energy_interval(fdtd_plan* p, int32_t ke);
+/* Tuning is fixed at bind: call before fdtd_required_bytes / fdtd_bind_arena. */
+int fdtd_set_tuning(fdtd_plan* p, const fdtd_tuning* t);
+int fdtd_get_tuning(const fdtd_plan* p, fdtd_tuning* t);
+
+/* Device bytes the plan needs for up to max_steps steps. */
+int fdtd_required_bytes(fdtd_plan* p, int64_t max_steps, size_t* bytes);
+/* Bind the caller's device arena (fixes the layout, zero-fills, uploads tables,
+   voxelizes).  After this the plan's configuration is frozen. */
+int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, void* stream);
+
+/* Advance n steps on the stream (asynchronous). */
+int fdtd_step(fdtd_plan* p, int64_t n, void* stream);
+int64_t fdtd_step_count(const fdtd_plan* p);
+int64_t fdtd_cell_count(const fdtd_plan* p);
+double fdtd_dt(const fdtd_plan* p);
+
+/* Field component comp (0..5), nx*ny*nz floats, host memory. */
+int fdtd_read_field(fdtd_plan* p, int32_t comp, float* host, void* stream);
+int fdtd_write_field(fdtd_plan* p, int32_t comp, const float* host, void* stream);
+/* Probe samples 0..n-1 (n = steps taken). */
+int fdtd_read_probe(fdtd_plan* p, int32_t id, float* host, int64_t* n, void* stream);
+/* T(t) samples (n = steps taken, may be NULL) and the flux spectrum
+   P(f) = Re sum (Ex Hy* - Ey Hx*) dx^2 (nf values, may be NULL). */
+int fdtd_read_flux(fdtd_plan* p, int32_t id, double* T, double* spec, int64_t* n, void* stream);
+/* Populations n0..n3 (4 * cells floats; zero outside gain cells). */
+int fdtd_read_populations(fdtd_plan* p, float* host, void* stream);
+/* Polarization P^n, 3 * cells floats. */
+int fdtd_read_polarization(fdtd_plan* p, float* host, void* stream);
+/* Energy samples W^0, W^ke, ... (n returned). */
+int fdtd_read_energy(fdtd_plan* p, double* host, int64_t* n, void* stream);
+
+/* Batches: bound plans that step together, one launch per tile class per step
+   over all plans' tiles (uneven sizes, each plan's own tuning and step count).
+   Stepping a batch advances every member; members must stay alive. */
+int fdtd_batch_create(fdtd_plan* const* plans, int32_t n, fdtd_batch** out);
+int fdtd_batch_step(fdtd_batch* b, int64_t n, void* stream);
+void fdtd_batch_destroy(fdtd_batch* b);
+
+/* Time n steps of the bound plan (hipEvents recorded on the stream around the
+   launches; the plan's state advances).  Milliseconds in *ms. */
+int fdtd_time_steps(fdtd_plan* p, int64_t n, void* stream, double* ms);
+/* Same for a batch. */
+int fdtd_batch_time_steps(fdtd_batch* b, int64_t n, void* stream, double* ms);
+
+/* Kernel classes of a step: 0 plain tiles, 1 tiles with CPML, 2 tiles with gain
+   cells, 3 both; 4 is the running-DFT update.  cells[c] = cells covered by the
+   plan's tiles of class c (c < 4), cells[4] = flux-plane points. */
+int fdtd_class_cells(const fdtd_plan* p, int64_t* cells /* 5 */);
+/* Advance n steps without graphs, bracketing every kernel launch with a pair of
+   hipEvents on the stream; ms[c] = summed milliseconds and launches[c] = number of
+   launches of class c (5 entries each, as above). */
+int fdtd_time_kernels(fdtd_plan* p, int64_t n, void* stream, double* ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1301 @@
+// Host runtime of libfdtd: plans, coefficient tables, arena layout, tile
+// tables, graph capture, batches and read-back.  The C ABI is include/fdtd.h.
+//
+// Method: C. Conti and A. Fratalocchi, arXiv:0802.3775 (Yee FDTD in a
+// disordered inverted opal with a pumped gain medium; sections "Sample and
+// numerical approach", "Dynamical diffusion and localization", lasing section).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/fdtd.h"
+#include "fd_internal.h"
+#include "geometry.h"
+
+namespace {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr double kC = 299792458.0;
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) return fail(FDTD_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Flux {
+  int k, nf, decim;
+  std::vector<double> f;
+};
+
+struct Layout {
+  size_t total = 0;
+  size_t desc, mats, ninit;
+  size_t E[2][3], H[2][3];
+  size_t map;
+  size_t P[2][3], pop;
+  size_t prof[3], psiE[3][2], psiH[2][3][2];
+  size_t src[FD_MAXSRC];
+  size_t probe;
+  size_t fluxT[FD_MAXFLUX], fluxf[FD_MAXFLUX], fluxacc[FD_MAXFLUX];
+  size_t energy;
+  size_t tiles[FD_NCLASS];
+  size_t dft;
+  size_t sites;
+};
+
+struct GraphEntry {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct fdtd_plan {
+  fdtd_grid_desc g{};
+  double dx = 0, dt = 0;
+  int64_t ncell = 0;
+  std::vector<fdtd_material> mats;
+  bool have_opal = false;
+  fdtd_opal_desc opal{};
+  std::vector<int64_t> spheres;  // rows of 5
+  std::vector<uint8_t> host_map; // given map, or read back after bind
+  bool map_given = false;
+  std::vector<fdtd_source_desc> sources;
+  std::vector<std::array<int, 4>> probes;
+  std::vector<Flux> flux;
+  int ke = 0;
+  fdtd_tuning tune{256, 4, 64, 0, 32};
+  // bound state
+  bool bound = false;
+  uint8_t* arena = nullptr;
+  size_t arena_bytes = 0;
+  int64_t max_steps = 0;
+  Layout L;
+  fd_desc hdesc{};
+  fd_desc* ddesc = nullptr;
+  int64_t step = 0;
+  int nblk = 0, ntiles = 0;
+  std::vector<fd_tile> tiles[FD_NCLASS];
+  fd_tile* dtiles[FD_NCLASS] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<fd_dft_tile> dft;
+  fd_dft_tile* ddft = nullptr;
+  int maxnf = 0;
+  int src_len[FD_MAXSRC] = {0, 0, 0, 0};
+  bool has_gain = false;
+  hipStream_t cap = nullptr;
+  std::map<int64_t, GraphEntry> graphs;
+};
+
+struct fdtd_batch {
+  std::vector<fdtd_plan*> plans;
+  int block = 256;
+  int tile_x = 32;
+  int max_blocks = 0;
+  int graph_steps = 0;
+  std::vector<fd_tile> tiles[FD_NCLASS];
+  std::vector<fd_dft_tile> dft;
+  int maxnf = 0;
+  void* dmem = nullptr;  // tile tables + desc pointer list (setup-time allocation)
+  fd_tile* dtiles[FD_NCLASS] = {nullptr, nullptr, nullptr, nullptr};
+  fd_dft_tile* ddft = nullptr;
+  fd_desc** ddescs = nullptr;
+  hipStream_t cap = nullptr;
+  std::map<std::vector<int64_t>, GraphEntry> graphs;
+};
+
+namespace {
+
+// ------------------------------------------------------------ coefficients
+
+int build_material(const fdtd_plan* p, const fdtd_material& m, fd_mat& out) {
+  std::memset(&out, 0, sizeof out);
+  const double dt = p->dt, dx = p->dx;
+  out.cb = (float)(dt / (m.eps * dx));
+  out.inv_eps = (float)(1.0 / m.eps);
+  out.eps = (float)m.eps;
+  out.inv_dt = (float)(1.0 / dt);
+  if (!m.gain) return FDTD_OK;
+  out.is_gain = 1;
+  // Lorentz ADE by central differences:
+  // (P+ - 2P + P-)/dt^2 + dw (P+ - P-)/(2dt) + w^2 P = kappa' dn E + F
+  const double w = 2.0 * kPi * m.f_a, dw = 2.0 * kPi * m.df_a;
+  if (w * dt >= 2.0) return fail(FDTD_EUNSTABLE, "Lorentz transition too fast for dt (w dt = %g)", w * dt);
+  const double den = 1.0 + 0.5 * dw * dt;
+  const double c3 = dt * dt / den;
+  const double a = p->g.a_meters;
+  // classical-oscillator coupling from the radiative lifetime tau21, normalised units
+  const double kap = 6.0 * kPi * m.n_total * a * a * a * a / (w * w * kC * m.tau21);
+  out.C1 = (float)((2.0 - w * w * dt * dt) / den);
+  out.C2 = (float)((0.5 * dw * dt - 1.0) / den);
+  out.C3 = (float)c3;
+  out.C3k = (float)(c3 * kap);
+  out.noise = (float)(m.noise / std::sqrt(dt * dx * dx * dx));
+  // four-level rates in units of c/a: 0 ->3 pump, 3->2, 2->1, 1->0
+  const double tu = a / kC;
+  const double pr = m.pump * tu, r32 = tu / m.tau32, r21 = tu / m.tau21, r10 = tu / m.tau10;
+  double A[4][4] = {};
+  A[0][0] = -pr; A[3][0] = pr;
+  A[3][3] = -r32; A[2][3] = r32;
+  A[2][2] = -r21; A[1][2] = r21;
+  A[1][1] = -r10; A[0][1] = r10;
+  // Crank-Nicolson: (I - dt/2 A) N+ = (I + dt/2 A) N + dt s
+  double lhs[4][8];
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) {
+      lhs[r][c] = (r == c ? 1.0 : 0.0) - 0.5 * dt * A[r][c];
+      lhs[r][4 + c] = r == c ? 1.0 : 0.0;
+    }
+  for (int c = 0; c < 4; ++c) {  // Gauss-Jordan, partial pivoting
+    int pv = c;
+    for (int r = c + 1; r < 4; ++r)
+      if (std::fabs(lhs[r][c]) > std::fabs(lhs[pv][c])) pv = r;
+    if (lhs[pv][c] == 0.0) return fail(FDTD_EINVAL, "singular population system");
+    if (pv != c)
+      for (int q = 0; q < 8; ++q) std::swap(lhs[c][q], lhs[pv][q]);
+    const double inv = 1.0 / lhs[c][c];
+    for (int q = 0; q < 8; ++q) lhs[c][q] *= inv;
+    for (int r = 0; r < 4; ++r) {
+      if (r == c) continue;
+      const double f = lhs[r][c];
+      for (int q = 0; q < 8; ++q) lhs[r][q] -= f * lhs[c][q];
+    }
+  }
+  double Minv[4][4], M[4][4];
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) Minv[r][c] = lhs[r][4 + c];
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) {
+      double acc = 0.0;
+      for (int q = 0; q < 4; ++q) acc += Minv[r][q] * ((q == c ? 1.0 : 0.0) + 0.5 * dt * A[q][c]);
+      M[r][c] = acc;
+    }
+  for (int r = 1; r < 4; ++r) {
+    for (int c = 0; c < 4; ++c) out.MI[r - 1][c] = (float)(M[r][c] - (r == c ? 1.0 : 0.0));
+    out.Bu[r - 1] = (float)(dt * (Minv[r][2] - Minv[r][1]));
+  }
+  return FDTD_OK;
+}
+
+// CFS-CPML grading (Roden and Gedney) at position pos (in cells) along axis w.
+void cpml_point(const fdtd_plan* p, int w, double pos, float& kinv, float& b, float& c) {
+  const int n = w == 0 ? p->g.nx : (w == 1 ? p->g.ny : p->g.nz);
+  const double lo = p->g.pml_lo[w], hi = p->g.pml_hi[w];
+  double depth = 0.0, width = 1.0;
+  if (lo > 0 && pos < lo) {
+    depth = lo - pos;
+    width = lo;
+  } else if (hi > 0 && pos > n - hi) {
+    depth = pos - (n - hi);
+    width = hi;
+  }
+  const double m = p->g.cpml_m;
+  const double smax = p->g.cpml_sigma_max > 0.0 ? p->g.cpml_sigma_max : 0.8 * (m + 1.0) / p->dx;
+  const double x = depth / width;
+  const double sig = smax * std::pow(x, m);
+  const double kap = 1.0 + (p->g.cpml_kappa_max - 1.0) * std::pow(x, m);
+  const double alp = p->g.cpml_alpha_max * (1.0 - x);
+  const double bb = std::exp(-(sig / kap + alp) * p->dt);
+  kinv = (float)(1.0 / kap);
+  b = (float)bb;
+  c = (float)(sig > 0.0 ? sig * (bb - 1.0) / (sig * kap + kap * kap * alp) : 0.0);
+}
+
+double source_sigma_t(const fdtd_source_desc& s) {
+  const double sl = std::sqrt(std::log(2.0));
+  switch (s.width_kind) {
+    case FDTD_WIDTH_FWHM_POWER: return 1.0 / (2.0 * kPi * (s.width / (2.0 * sl)));
+    case FDTD_WIDTH_FWHM_INTENSITY: return s.width / (2.0 * sl);
+    default: return s.width;
+  }
+}
+
+int axis_n(const fdtd_plan* p, int w) { return w == 0 ? p->g.nx : (w == 1 ? p->g.ny : p->g.nz); }
+int pml_t(const fdtd_plan* p, int w) {
+  return p->g.bc[w] == FDTD_BC_PEC ? p->g.pml_lo[w] + p->g.pml_hi[w] : 0;
+}
+size_t psi_elems(const fdtd_plan* p, int w) {
+  const size_t t = (size_t)pml_t(p, w);
+  const size_t nx = p->g.nx, ny = p->g.ny, nz = p->g.nz;
+  if (w == 2) return t * nx * ny;
+  if (w == 0) return nz * ny * t;
+  return nz * t * nx;
+}
+
+// z ranges of the tiles: split at the CPML slab interfaces, then into chunks.
+std::vector<std::pair<int, int>> z_chunks(const fdtd_plan* p, int zchunk) {
+  std::vector<int> cuts = {0};
+  const int nz = p->g.nz;
+  if (pml_t(p, 2) > 0) {
+    // the first interior plane still reads H of the last low-side slab plane
+    if (p->g.pml_lo[2] > 0 && p->g.pml_lo[2] + 1 < nz) cuts.push_back(p->g.pml_lo[2] + 1);
+    if (p->g.pml_hi[2] > 0 && nz - p->g.pml_hi[2] > cuts.back()) cuts.push_back(nz - p->g.pml_hi[2]);
+  }
+  cuts.push_back(nz);
+  std::vector<std::pair<int, int>> out;
+  for (size_t s = 0; s + 1 < cuts.size(); ++s) {
+    const int a = cuts[s], b = cuts[s + 1];
+    if (b <= a) continue;
+    const int pieces = (b - a + zchunk - 1) / zchunk;
+    for (int q = 0; q < pieces; ++q) {
+      const int k0 = a + (int)((int64_t)(b - a) * q / pieces);
+      const int k1 = a + (int)((int64_t)(b - a) * (q + 1) / pieces);
+      if (k1 > k0) out.push_back({k0, k1});
+    }
+  }
+  return out;
+}
+
+int compute_layout(fdtd_plan* p, int64_t max_steps, Layout& L) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align256(off + bytes);
+    return at;
+  };
+  const size_t nc = (size_t)p->ncell;
+  const bool gain = std::any_of(p->mats.begin(), p->mats.end(), [](const fdtd_material& m) { return m.gain != 0; });
+  L.desc = take(sizeof(fd_desc));
+  L.mats = take(sizeof(fd_mat) * FD_MAXMAT);
+  L.ninit = take(sizeof(float) * 4 * FD_MAXMAT);
+  for (int b = 0; b < 2; ++b)
+    for (int c = 0; c < 3; ++c) L.E[b][c] = take(nc * 4);
+  for (int b = 0; b < 2; ++b)
+    for (int c = 0; c < 3; ++c) L.H[b][c] = take(nc * 4);
+  L.map = take(nc);
+  for (int b = 0; b < 2; ++b)
+    for (int c = 0; c < 3; ++c) L.P[b][c] = gain ? take(nc * 4) : 0;
+  L.pop = gain ? take(nc * 4 * 6) : 0;
+  for (int w = 0; w < 3; ++w) {
+    const bool on = pml_t(p, w) > 0;
+    L.prof[w] = on ? take(sizeof(float) * 6 * axis_n(p, w)) : 0;
+    for (int f = 0; f < 2; ++f) {
+      L.psiE[w][f] = on ? take(4 * psi_elems(p, w)) : 0;
+      for (int b = 0; b < 2; ++b) L.psiH[b][w][f] = on ? take(4 * psi_elems(p, w)) : 0;
+    }
+  }
+  for (size_t q = 0; q < FD_MAXSRC; ++q) {
+    if (q < p->sources.size()) {
+      const fdtd_source_desc& s = p->sources[q];
+      const double sig = source_sigma_t(s);
+      const double tend = s.delay * sig + 12.0 * sig;
+      int64_t len = (int64_t)std::ceil(tend / p->dt) + 1;
+      len = std::min<int64_t>(std::max<int64_t>(len, 1), std::max<int64_t>(max_steps, 1));
+      p->src_len[q] = (int)len;
+      L.src[q] = take(sizeof(float) * (size_t)len);
+    } else {
+      p->src_len[q] = 0;
+      L.src[q] = 0;
+    }
+  }
+  const int plane = p->g.nx * p->g.ny;
+  const int TX = p->tune.tile_x, TY = p->tune.block / p->tune.tile_x;
+  p->nblk = ((p->g.nx + TX - 1) / TX) * ((p->g.ny + TY - 1) / TY);
+  const auto chunks = z_chunks(p, std::max(1, p->tune.zchunk));
+  p->ntiles = p->nblk * (int)chunks.size();
+  L.probe = take(sizeof(float) * p->probes.size() * (size_t)std::max<int64_t>(max_steps, 1));
+  for (size_t f = 0; f < FD_MAXFLUX; ++f) {
+    if (f < p->flux.size()) {
+      L.fluxT[f] = take(sizeof(double) * (size_t)p->nblk * (size_t)std::max<int64_t>(max_steps, 1));
+      L.fluxf[f] = take(sizeof(double) * std::max<size_t>(p->flux[f].f.size(), 1));
+      L.fluxacc[f] = take(sizeof(double) * 2 * 4 * p->flux[f].f.size() * (size_t)plane);
+    } else {
+      L.fluxT[f] = L.fluxf[f] = L.fluxacc[f] = 0;
+    }
+  }
+  L.energy = p->ke > 0 ? take(sizeof(double) * (size_t)(max_steps / p->ke + 1) * (size_t)p->ntiles) : 0;
+  for (int c = 0; c < FD_NCLASS; ++c) L.tiles[c] = take(sizeof(fd_tile) * (size_t)p->ntiles);
+  size_t ndft = 0;
+  for (const Flux& f : p->flux)
+    if (f.nf > 0) ndft += (size_t)((plane + 255) / 256);
+  L.dft = take(sizeof(fd_dft_tile) * std::max<size_t>(ndft, 1));
+  if (p->have_opal) {
+    size_t ns = 1;
+    for (int a = 0; a < 3; ++a) ns *= (size_t)(2 * p->opal.cells[a] + 1);
+    L.sites = take(sizeof(int64_t) * 4 * ns);
+  } else {
+    L.sites = 0;
+  }
+  L.total = off;
+  return FDTD_OK;
+}
+
+template <class T>
+T* at(fdtd_plan* p, size_t off) {
+  return reinterpret_cast<T*>(p->arena + off);
+}
+
+// Enqueue one step (batch-relative index s) of the given tile sets.
+int enqueue_step(fd_tile* const dtiles[FD_NCLASS], const std::vector<fd_tile>* tiles, int tile_x, int block,
+                 int max_blocks, const fd_dft_tile* ddft, int ndft, int maxnf, bool dft_due, int s, hipStream_t st) {
+  for (int c = 0; c < FD_NCLASS; ++c) {
+    const int nt = (int)tiles[c].size();
+    if (nt == 0) continue;
+    const int grid = max_blocks > 0 ? std::min(nt, max_blocks) : nt;
+    HIPCHK(fd_launch_step(c, dtiles[c], nt, tile_x, block, grid, s, st));
+  }
+  if (dft_due && ndft > 0) HIPCHK(fd_launch_dft(ddft, ndft, maxnf, 256, s, st));
+  return FDTD_OK;
+}
+
+bool plan_dft_due(const fdtd_plan* p, int64_t n) {
+  for (const Flux& f : p->flux)
+    if (f.nf > 0 && n % f.decim == 0) return true;
+  return false;
+}
+
+int64_t plan_phase_key(const fdtd_plan* p, int64_t n0) {
+  int64_t l = 1;
+  for (const Flux& f : p->flux)
+    if (f.nf > 0) l = std::lcm(l, (int64_t)f.decim);
+  return n0 % l;
+}
+
+int plan_enqueue(fdtd_plan* p, int64_t n, hipStream_t st) {
+  for (int64_t s = 0; s < n; ++s) {
+    const int r = enqueue_step(p->dtiles, p->tiles, p->tune.tile_x, p->tune.block, p->tune.max_blocks, p->ddft,
+                               (int)p->dft.size(),
+                               p->maxnf, plan_dft_due(p, p->step + s), (int)s, st);
+    if (r) return r;
+  }
+  HIPCHK(fd_launch_advance_one(p->ddesc, n, st));
+  return FDTD_OK;
+}
+
+}  // namespace
+
+// =================================================================== ABI
+
+extern "C" {
+
+const char* fdtd_last_error(void) { return g_err.c_str(); }
+const char* fdtd_version(void) { return "libfdtd 0.1 (gfx950)"; }
+
+int fdtd_plan_create(const fdtd_grid_desc* g, fdtd_plan** out) {
+  if (!g || !out) return fail(FDTD_EINVAL, "null argument");
+  *out = nullptr;
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(FDTD_EINVAL, "grid sizes must be >= 1");
+  const int64_t ncell = (int64_t)g->nx * g->ny * g->nz;
+  if (ncell > (int64_t)1 << 30) return fail(FDTD_EUNSUPPORTED, "more than 2^30 cells");
+  if (g->res < 1) return fail(FDTD_EINVAL, "res must be >= 1");
+  if (!(g->courant > 0.0)) return fail(FDTD_EINVAL, "courant must be > 0");
+  if (g->courant >= 1.0 / std::sqrt(3.0)) return fail(FDTD_EUNSTABLE, "courant %g >= 1/sqrt(3)", g->courant);
+  const int n[3] = {g->nx, g->ny, g->nz};
+  for (int w = 0; w < 3; ++w) {
+    if (g->bc[w] != FDTD_BC_PERIODIC && g->bc[w] != FDTD_BC_PEC) return fail(FDTD_EINVAL, "bad bc on axis %d", w);
+    if (g->pml_lo[w] < 0 || g->pml_hi[w] < 0) return fail(FDTD_EINVAL, "negative CPML width");
+    if (g->bc[w] == FDTD_BC_PERIODIC && (g->pml_lo[w] || g->pml_hi[w]))
+      return fail(FDTD_EINVAL, "CPML on a periodic axis %d", w);
+    if (g->pml_lo[w] + g->pml_hi[w] > n[w]) return fail(FDTD_EINVAL, "CPML wider than the axis");
+  }
+  if (g->pml_lo[0] + g->pml_hi[0] + g->pml_lo[1] + g->pml_hi[1] + g->pml_lo[2] + g->pml_hi[2] > 0) {
+    if (!(g->cpml_m >= 0.0) || !(g->cpml_kappa_max >= 1.0) || !(g->cpml_alpha_max >= 0.0))
+      return fail(FDTD_EINVAL, "bad CPML grading parameters");
+  }
+  fdtd_plan* p = new (std::nothrow) fdtd_plan();
+  if (!p) return fail(FDTD_ENOMEM, "host allocation");
+  p->g = *g;
+  p->dx = 1.0 / g->res;
+  p->dt = g->courant * p->dx;
+  p->ncell = ncell;
+  fdtd_material vac{};
+  vac.eps = 1.0;
+  p->mats.push_back(vac);
+  *out = p;
+  return FDTD_OK;
+}
+
+void fdtd_plan_destroy(fdtd_plan* p) {
+  if (!p) return;
+  for (auto& kv : p->graphs) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+  }
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  delete p;
+}
+
+int fdtd_set_materials(fdtd_plan* p, const fdtd_material* tab, int32_t n) {
+  if (!p || !tab) return fail(FDTD_EINVAL, "null argument");
+  if (p->bound) return fail(FDTD_ESTATE, "plan already bound");
+  if (n < 1 || n > FDTD_MAX_MATERIALS) return fail(FDTD_EINVAL, "1..%d materials", FDTD_MAX_MATERIALS);
+  for (int q = 0; q < n; ++q) {
+    const fdtd_material& m = tab[q];
+    if (!(m.eps > 0.0)) return fail(FDTD_EINVAL, "material %d: eps must be > 0", q);
+    if (m.gain) {
+      if (!(m.n_total >= 0.0) || !(m.tau32 > 0.0) || !(m.tau21 > 0.0) || !(m.tau10 > 0.0) || !(m.pump >= 0.0) ||
+          !(m.f_a > 0.0) || !(m.df_a >= 0.0))
+        return fail(FDTD_EINVAL, "material %d: bad gain parameters", q);
+      if (!(p->g.a_meters > 0.0)) return fail(FDTD_EINVAL, "gain needs a_meters > 0");
+    }
+  }
+  p->mats.assign(tab, tab + n);
+  fd_mat scratch;
+  for (int q = 0; q < n; ++q) {
+    const int r = build_material(p, p->mats[q], scratch);
+    if (r) return r;
+  }
+  return FDTD_OK;
+}
+
+int fdtd_build_opal(fdtd_plan* p, const fdtd_opal_desc* d) {
+  if (!p || !d) return fail(FDTD_EINVAL, "null argument");
+  if (p->bound) return fail(FDTD_ESTATE, "plan already bound");
+  const int n[3] = {p->g.nx, p->g.ny, p->g.nz};
+  fdg::OpalSpec o{};
+  for (int a = 0; a < 3; ++a) {
+    if (d->cells[a] < 1 || d->origin[a] < 0) return fail(FDTD_EINVAL, "bad opal cells/origin");
+    if ((int64_t)d->origin[a] + (int64_t)d->cells[a] * p->g.res > n[a])
+      return fail(FDTD_EINVAL, "opal does not fit the grid on axis %d", a);
+    const bool per = p->g.bc[a] == FDTD_BC_PERIODIC;
+    if (per && (d->origin[a] != 0 || d->cells[a] * p->g.res != n[a]))
+      return fail(FDTD_EINVAL, "a periodic axis must be spanned by the crystal (axis %d)", a);
+    o.cells[a] = d->cells[a];
+    o.periodic[a] = per ? 1 : 0;
+  }
+  if (d->disorder < 0 || d->disorder > 2) return fail(FDTD_EINVAL, "bad disorder kind");
+  if (!(d->r0 >= 0.0) || !(d->strength >= 0.0)) return fail(FDTD_EINVAL, "bad radius or strength");
+  for (int m : {d->mat_bg, d->mat_void, d->mat_out})
+    if (m < 0 || m >= (int)p->mats.size()) return fail(FDTD_EINVAL, "opal material index %d out of range", m);
+  o.res = p->g.res;
+  o.r0 = d->r0;
+  o.disorder = d->disorder;
+  o.strength = d->strength;
+  o.seed = p->g.seed;
+  o.realization = p->g.realization;
+  std::vector<int64_t> rows;
+  if (fdg::build_spheres(o, rows)) return fail(FDTD_EINVAL, "sphere generation failed");
+  for (int a = 0; a < 3; ++a) {
+    if (!o.periodic[a]) continue;
+    const int64_t period = (int64_t)d->cells[a] * p->g.res * 2 * 65536;
+    for (size_t s = 0; s < rows.size() / 5; ++s)
+      if (2 * rows[5 * s + 4] >= period) return fail(FDTD_EINVAL, "sphere diameter reaches the period");
+  }
+  p->spheres.swap(rows);
+  p->opal = *d;
+  p->have_opal = true;
+  p->map_given = false;
+  return FDTD_OK;
+}
+
+int fdtd_set_material_map(fdtd_plan* p, const uint8_t* host_map) {
+  if (!p || !host_map) return fail(FDTD_EINVAL, "null argument");
+  if (p->bound) return fail(FDTD_ESTATE, "plan already bound");
+  p->host_map.assign(host_map, host_map + p->ncell);
+  p->map_given = true;
+  p->have_opal = false;
+  p->spheres.clear();
+  return FDTD_OK;
+}
+
+int fdtd_get_spheres(const fdtd_plan* p, int64_t* out, int64_t* n) {
+  if (!p || !n) return fail(FDTD_EINVAL, "null argument");
+  *n = (int64_t)(p->spheres.size() / 5);
+  if (out) std::memcpy(out, p->spheres.data(), p->spheres.size() * sizeof(int64_t));
+  return FDTD_OK;
+}
+
+int fdtd_add_source(fdtd_plan* p, const fdtd_source_desc* s, int32_t* id) {
+  if (!p || !s) return fail(FDTD_EINVAL, "null argument");
+  if (p->bound) return fail(FDTD_ESTATE, "plan already bound");
+  if (p->sources.size() >= FD_MAXSRC) return fail(FDTD_EINVAL, "at most %d sources", FD_MAXSRC);
+  if (s->comp < 0 || s->comp > 2) return fail(FDTD_EINVAL, "source component must be 0..2");
+  if (s->kind == FDTD_SRC_DIPOLE) {
+    if (s->i < 0 || s->i >= p->g.nx || s->j < 0 || s->j >= p->g.ny || s->k < 0 || s->k >= p->g.nz)
+      return fail(FDTD_EINVAL, "dipole outside the grid");
+  } else if (s->kind == FDTD_SRC_PLANE) {
+    if (s->k < 0 || s->k >= p->g.nz) return fail(FDTD_EINVAL, "source plane outside the grid");
+  } else {
+    return fail(FDTD_EINVAL, "bad source kind");
+  }
+  if (s->width_kind < 0 || s->width_kind > 2 || !(s->width > 0.0)) return fail(FDTD_EINVAL, "bad source width");
+  p->sources.push_back(*s);
+  if (id) *id = (int32_t)p->sources.size() - 1;
+  return FDTD_OK;
+}
+
+int fdtd_add_probe(fdtd_plan* p, int32_t comp, int32_t i, int32_t j, int32_t k, int32_t* id) {
+  if (!p) return fail(FDTD_EINVAL, "null plan");
+  if (p->bound) return fail(FDTD_ESTATE, "plan already bound");
+  if (p->probes.size() >= FD_MAXPROBE) return fail(FDTD_EINVAL, "at most %d probes", FD_MAXPROBE);
+  if (comp < 0 || comp > 5 || i < 0 || i >= p->g.nx || j < 0 || j >= p->g.ny || k < 0 || k >= p->g.nz)
+    return fail(FDTD_EINVAL, "probe outside the grid or bad component");
+  p->probes.push_back({comp, i, j, k});
+  if (id) *id = (int32_t)p->probes.size() - 1;
+  return FDTD_OK;
+}
+
+int fdtd_add_flux_plane(fdtd_plan* p, int32_t k, const double* f, int32_t nf, int32_t decim, int32_t* id) {
+  if (!p) return fail(FDTD_EINVAL, "null plan");
+  if (p->bound) return fail(FDTD_ESTATE, "plan already bound");
+  if (p->flux.size() >= FD_MAXFLUX) return fail(FDTD_EINVAL, "at most %d flux planes", FD_MAXFLUX);
+  if (k < 0 || k >= p->g.nz || (k == 0 && p->g.bc[2] != FDTD_BC_PERIODIC))
+    return fail(FDTD_EINVAL, "flux plane index out of range");
+  if (nf < 0 || decim < 1 || (nf > 0 && !f)) return fail(FDTD_EINVAL, "bad frequency list or decimation");
+  if (nf > 65535) return fail(FDTD_EUNSUPPORTED, "too many frequencies");
+  Flux fl;
+  fl.k = k;
+  fl.nf = nf;
+  fl.decim = decim;
+  if (nf > 0) fl.f.assign(f, f + nf);
+  p->flux.push_back(fl);
+  if (id) *id = (int32_t)p->flux.size() - 1;
+  return FDTD_OK;
+}
+
+int fdtd_set_energy_interval(fdtd_plan* p, int32_t ke) {
+  if (!p) return fail(FDTD_EINVAL, "null plan");
+  if (p->bound) return fail(FDTD_ESTATE, "plan already bound");
+  if (ke < 0) return fail(FDTD_EINVAL, "energy interval must be >= 0");
+  p->ke = ke;
+  return FDTD_OK;
+}
+
+int fdtd_set_tuning(fdtd_plan* p, const fdtd_tuning* t) {
+  if (!p || !t) return fail(FDTD_EINVAL, "null argument");
+  if (p->bound) return fail(FDTD_ESTATE, "tuning is fixed at bind");
+  if (t->block < 64 || t->block > FD_MAXBLOCK || t->block % 64) return fail(FDTD_EINVAL, "block must be 64..%d, multiple of 64", FD_MAXBLOCK);
+  if (t->zchunk < 1 || t->graph_steps < 0 || t->max_blocks < 0) return fail(FDTD_EINVAL, "bad tuning");
+  if (t->tile_x != 16 && t->tile_x != 32 && t->tile_x != 64) return fail(FDTD_EINVAL, "tile_x must be 16, 32 or 64");
+  if (t->block % t->tile_x != 0) return fail(FDTD_EINVAL, "block must be a multiple of tile_x");
+  p->tune = *t;
+  return FDTD_OK;
+}
+
+int fdtd_get_tuning(const fdtd_plan* p, fdtd_tuning* t) {
+  if (!p || !t) return fail(FDTD_EINVAL, "null argument");
+  *t = p->tune;
+  return FDTD_OK;
+}
+
+int fdtd_required_bytes(fdtd_plan* p, int64_t max_steps, size_t* bytes) {
+  if (!p || !bytes) return fail(FDTD_EINVAL, "null argument");
+  if (max_steps < 0 || max_steps > ((int64_t)1 << 31)) return fail(FDTD_EINVAL, "max_steps out of range");
+  Layout L;
+  const int r = compute_layout(p, max_steps, L);
+  if (r) return r;
+  *bytes = L.total;
+  return FDTD_OK;
+}
+
+int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, void* stream) {
+  if (!p || !dev) return fail(FDTD_EINVAL, "null argument");
+  if (p->bound) return fail(FDTD_ESTATE, "plan already bound");
+  if (((uintptr_t)dev & 255) != 0) return fail(FDTD_EINVAL, "arena must be 256-byte aligned");
+  if (max_steps < 0 || max_steps > ((int64_t)1 << 31)) return fail(FDTD_EINVAL, "max_steps out of range");
+  hipStream_t st = (hipStream_t)stream;
+  Layout L;
+  int r = compute_layout(p, max_steps, L);
+  if (r) return r;
+  if (bytes < L.total) return fail(FDTD_ENOMEM, "arena of %zu bytes, need %zu", bytes, L.total);
+  if (!p->have_opal && !p->map_given) p->host_map.assign((size_t)p->ncell, 0);
+  if (p->map_given || !p->have_opal)
+    for (uint8_t m : p->host_map)
+      if (m >= p->mats.size()) return fail(FDTD_EINVAL, "material map index %d out of range", (int)m);
+  p->arena = (uint8_t*)dev;
+  p->arena_bytes = bytes;
+  p->max_steps = max_steps;
+  p->L = L;
+  HIPCHK(fd_launch_fill(dev, L.total, st));
+
+  // materials
+  std::vector<fd_mat> mt(FD_MAXMAT);
+  std::vector<float> ninit(4 * FD_MAXMAT, 0.0f);
+  p->has_gain = false;
+  for (size_t q = 0; q < p->mats.size(); ++q) {
+    r = build_material(p, p->mats[q], mt[q]);
+    if (r) return r;
+    if (p->mats[q].gain) {
+      p->has_gain = true;
+      for (int l = 0; l < 4; ++l) ninit[4 * q + l] = (float)p->mats[q].n_init[l];
+    }
+  }
+  HIPCHK(hipMemcpyAsync(p->arena + L.mats, mt.data(), sizeof(fd_mat) * FD_MAXMAT, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->arena + L.ninit, ninit.data(), sizeof(float) * ninit.size(), hipMemcpyHostToDevice, st));
+
+  // descriptor
+  fd_desc& d = p->hdesc;
+  std::memset(&d, 0, sizeof d);
+  d.nx = p->g.nx; d.ny = p->g.ny; d.nz = p->g.nz;
+  d.plane = p->g.nx * p->g.ny;
+  for (int w = 0; w < 3; ++w) d.per[w] = p->g.bc[w] == FDTD_BC_PERIODIC ? 1 : 0;
+  d.ncell = (int)p->ncell;
+  d.ch = (float)(p->dt / p->dx);
+  d.nmat = (int)p->mats.size();
+  d.has_gain = p->has_gain ? 1 : 0;
+  d.block = p->tune.block;
+  d.step = 0;
+  d.max_steps = max_steps;
+  d.mats = at<fd_mat>(p, L.mats);
+  d.mat = at<uint8_t>(p, L.map);
+  for (int b = 0; b < 2; ++b)
+    for (int c = 0; c < 3; ++c) {
+      d.E[b][c] = at<float>(p, L.E[b][c]);
+      d.H[b][c] = at<float>(p, L.H[b][c]);
+      d.P[b][c] = p->has_gain ? at<float>(p, L.P[b][c]) : nullptr;
+    }
+  d.pop = p->has_gain ? at<float>(p, L.pop) : nullptr;
+  d.key0 = p->g.seed;
+  d.key1 = p->g.realization;
+  std::vector<float> prof;
+  for (int w = 0; w < 3; ++w) {
+    d.pml_t[w] = pml_t(p, w);
+    d.pml_lo[w] = d.pml_t[w] ? p->g.pml_lo[w] : 0;
+    d.pml_hi[w] = d.pml_t[w] ? p->g.pml_hi[w] : 0;
+    if (!d.pml_t[w]) continue;
+    const int nw = axis_n(p, w);
+    prof.assign((size_t)6 * nw, 0.0f);
+    for (int q = 0; q < nw; ++q) {
+      cpml_point(p, w, (double)q, prof[q], prof[nw + q], prof[2 * nw + q]);
+      cpml_point(p, w, (double)q + 0.5, prof[3 * nw + q], prof[4 * nw + q], prof[5 * nw + q]);
+    }
+    HIPCHK(hipMemcpyAsync(p->arena + L.prof[w], prof.data(), sizeof(float) * prof.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    d.prof[w] = at<float>(p, L.prof[w]);
+    for (int f = 0; f < 2; ++f) {
+      d.psiE[w][f] = at<float>(p, L.psiE[w][f]);
+      for (int b = 0; b < 2; ++b) d.psiH[b][w][f] = at<float>(p, L.psiH[b][w][f]);
+    }
+  }
+  // sources
+  d.nsrc = (int)p->sources.size();
+  for (int q = 0; q < d.nsrc; ++q) {
+    const fdtd_source_desc& s = p->sources[q];
+    const double sig = source_sigma_t(s);
+    const double t0 = s.delay * sig;
+    std::vector<float> tab((size_t)p->src_len[q]);
+    for (int64_t n = 0; n < p->src_len[q]; ++n) {
+      const double t = ((double)n + 0.5) * p->dt - t0;
+      const double v = s.amp * std::sin(2.0 * kPi * s.f0 * t) * std::exp(-t * t / (2.0 * sig * sig));
+      tab[(size_t)n] = (float)(s.kind == FDTD_SRC_DIPOLE ? v / (p->dx * p->dx) : v);
+    }
+    HIPCHK(hipMemcpyAsync(p->arena + L.src[q], tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    d.src_kind[q] = s.kind;
+    d.src_comp[q] = s.comp;
+    d.src_k[q] = s.k;
+    d.src_cell[q] = s.kind == FDTD_SRC_DIPOLE ? s.j * p->g.nx + s.i : -1;
+    d.src_len[q] = p->src_len[q];
+    d.src_tab[q] = at<float>(p, L.src[q]);
+  }
+  // probes
+  d.nprobe = (int)p->probes.size();
+  for (int q = 0; q < d.nprobe; ++q) {
+    d.probe_comp[q] = p->probes[q][0];
+    d.probe_cell[q] = p->probes[q][2] * p->g.nx + p->probes[q][1];
+    d.probe_k[q] = p->probes[q][3];
+  }
+  d.probe_ring = at<float>(p, L.probe);
+  // flux
+  d.nflux = (int)p->flux.size();
+  d.nblk = p->nblk;
+  p->maxnf = 0;
+  for (int f = 0; f < d.nflux; ++f) {
+    const Flux& fl = p->flux[f];
+    d.flux_k[f] = fl.k;
+    d.flux_T[f] = at<double>(p, L.fluxT[f]);
+    d.flux_nf[f] = fl.nf;
+    d.flux_decim[f] = fl.decim;
+    d.flux_f[f] = at<double>(p, L.fluxf[f]);
+    d.flux_acc[f] = at<double>(p, L.fluxacc[f]);
+    if (fl.nf > 0) {
+      HIPCHK(hipMemcpyAsync(p->arena + L.fluxf[f], fl.f.data(), sizeof(double) * fl.nf, hipMemcpyHostToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    p->maxnf = std::max(p->maxnf, fl.nf);
+  }
+  d.ke = p->ke;
+  d.ntiles = p->ntiles;
+  d.energy = p->ke > 0 ? at<double>(p, L.energy) : nullptr;
+  d.dt = p->dt;
+  p->ddesc = at<fd_desc>(p, L.desc);
+  HIPCHK(hipMemcpyAsync(p->ddesc, &d, sizeof d, hipMemcpyHostToDevice, st));
+
+  // material map: given, or voxelized from the sphere list on the device
+  if (p->have_opal) {
+    const fdtd_opal_desc& o = p->opal;
+    int ext[3], per[3], ncr[3];
+    for (int a = 0; a < 3; ++a) {
+      per[a] = p->g.bc[a] == FDTD_BC_PERIODIC ? 1 : 0;
+      ext[a] = 2 * o.cells[a] + (per[a] ? 0 : 1);
+      ncr[a] = o.cells[a] * p->g.res;
+    }
+    const size_t nsite = (size_t)ext[0] * ext[1] * ext[2];
+    std::vector<int64_t> sites(4 * nsite, 0);
+    for (size_t q = 0; q < nsite; ++q) sites[4 * q + 3] = -1;
+    int64_t reach[3] = {0, 0, 0};
+    const int64_t half_site = (int64_t)p->g.res * 65536;  // quanta between half-lattice sites
+    const int64_t wx = 2 * (int64_t)o.cells[0] + 1, wy = 2 * (int64_t)o.cells[1] + 1;
+    for (size_t s = 0; s < p->spheres.size() / 5; ++s) {
+      const int64_t* row = &p->spheres[5 * s];
+      const int64_t id = row[0];
+      const int64_t h = id % wx, kk = (id / wx) % wy, l = id / (wx * wy);
+      const int64_t hv[3] = {h, kk, l};
+      const size_t q = (size_t)((l * ext[1] + kk) * ext[0] + h);
+      for (int a = 0; a < 3; ++a) sites[4 * q + a] = row[1 + a];
+      sites[4 * q + 3] = row[4];
+      for (int a = 0; a < 3; ++a) {
+        const int64_t dev_a = std::llabs(row[1 + a] - hv[a] * half_site);
+        reach[a] = std::max(reach[a], row[4] + dev_a);
+      }
+    }
+    HIPCHK(hipMemcpyAsync(p->arena + L.sites, sites.data(), sizeof(int64_t) * sites.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(fd_launch_voxelize(at<int64_t>(p, L.sites), ext[0], ext[1], ext[2], per, ncr, o.origin, reach, p->g.res,
+                              o.mat_bg, o.mat_void, o.mat_out, p->g.nx, p->g.ny, p->g.nz, at<uint8_t>(p, L.map), st));
+    p->host_map.resize((size_t)p->ncell);
+    HIPCHK(hipMemcpyAsync(p->host_map.data(), p->arena + L.map, (size_t)p->ncell, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  } else {
+    HIPCHK(hipMemcpyAsync(p->arena + L.map, p->host_map.data(), (size_t)p->ncell, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  if (p->has_gain) HIPCHK(fd_launch_init_pop(p->ddesc, at<uint8_t>(p, L.map), at<float>(p, L.ninit), d.pop, d.ncell, st));
+
+  // tiles, classified by CPML and gain presence
+  const int plane = d.plane;
+  const int TX = p->tune.tile_x, TY = p->tune.block / p->tune.tile_x;
+  const int ntx = (p->g.nx + TX - 1) / TX, nty = (p->g.ny + TY - 1) / TY;
+  const auto chunks = z_chunks(p, std::max(1, p->tune.zchunk));
+  std::vector<uint8_t> gain_mat(FD_MAXMAT, 0);
+  for (size_t q = 0; q < p->mats.size(); ++q) gain_mat[q] = p->mats[q].gain ? 1 : 0;
+  // gain presence per (xy tile, z)
+  std::vector<uint8_t> blk_gain;
+  if (p->has_gain) {
+    blk_gain.assign((size_t)p->nblk * p->g.nz, 0);
+    for (int k = 0; k < p->g.nz; ++k)
+      for (int j = 0; j < p->g.ny; ++j)
+        for (int i = 0; i < p->g.nx; ++i)
+          if (gain_mat[p->host_map[(size_t)k * plane + (size_t)j * p->g.nx + i]])
+            blk_gain[(size_t)k * p->nblk + (size_t)(j / TY) * ntx + i / TX] = 1;
+  }
+  for (int c = 0; c < FD_NCLASS; ++c) p->tiles[c].clear();
+  int tidx = 0;
+  for (const auto& ch : chunks) {
+    for (int by = 0; by < nty; ++by)
+      for (int bx = 0; bx < ntx; ++bx) {
+        fd_tile t{};
+        t.d = p->ddesc;
+        t.i0 = bx * TX;
+        t.j0 = by * TY;
+        t.k0 = ch.first;
+        t.k1 = ch.second;
+        t.tidx = tidx++;
+        t.blk = by * ntx + bx;
+        // A tile needs the CPML code if any H value it evaluates lies in a slab:
+        // its own cells, the x-1 / y-1 neighbours it recomputes, and plane k0-1.
+        // (Slabs only exist on PEC axes, so no wrap-around is involved.)
+        bool pml = false;
+        if (d.pml_t[2] && (t.k0 - 1 < d.pml_lo[2] || t.k1 > p->g.nz - d.pml_hi[2])) pml = true;
+        const int iend = std::min(p->g.nx, t.i0 + TX), jend = std::min(p->g.ny, t.j0 + TY);
+        if (d.pml_t[0] && (t.i0 - 1 < d.pml_lo[0] || iend > p->g.nx - d.pml_hi[0])) pml = true;
+        if (d.pml_t[1] && (t.j0 - 1 < d.pml_lo[1] || jend > p->g.ny - d.pml_hi[1])) pml = true;
+        bool gain = false;
+        if (p->has_gain)
+          for (int k = t.k0; k < t.k1 && !gain; ++k) gain = blk_gain[(size_t)k * p->nblk + t.blk] != 0;
+        const int cls = (pml ? 1 : 0) + (gain ? 2 : 0);
+        p->tiles[cls].push_back(t);
+      }
+  }
+  for (int c = 0; c < FD_NCLASS; ++c) {
+    p->dtiles[c] = at<fd_tile>(p, L.tiles[c]);
+    if (!p->tiles[c].empty())
+      HIPCHK(hipMemcpyAsync(p->dtiles[c], p->tiles[c].data(), sizeof(fd_tile) * p->tiles[c].size(),
+                            hipMemcpyHostToDevice, st));
+  }
+  p->dft.clear();
+  for (int f = 0; f < d.nflux; ++f) {
+    if (p->flux[f].nf == 0) continue;
+    for (int p0 = 0; p0 < plane; p0 += 256) {
+      fd_dft_tile t{};
+      t.d = p->ddesc;
+      t.flux = f;
+      t.p0 = p0;
+      p->dft.push_back(t);
+    }
+  }
+  p->ddft = at<fd_dft_tile>(p, L.dft);
+  if (!p->dft.empty())
+    HIPCHK(hipMemcpyAsync(p->ddft, p->dft.data(), sizeof(fd_dft_tile) * p->dft.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  p->step = 0;
+  p->bound = true;
+  return FDTD_OK;
+}
+
+int fdtd_get_material_map(fdtd_plan* p, uint8_t* host_map, void* stream) {
+  if (!p || !host_map) return fail(FDTD_EINVAL, "null argument");
+  if (!p->bound) return fail(FDTD_ESTATE, "plan not bound");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipMemcpyAsync(host_map, p->arena + p->L.map, (size_t)p->ncell, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return FDTD_OK;
+}
+
+static int plan_step(fdtd_plan* p, int64_t n, hipStream_t st) {
+  if (n < 0) return fail(FDTD_EINVAL, "negative step count");
+  if (p->step + n > p->max_steps) return fail(FDTD_ESTATE, "max_steps (%lld) exceeded", (long long)p->max_steps);
+  const int64_t K = p->tune.graph_steps;
+  int64_t done = 0;
+  if (K > 0) {
+    while (n - done >= K) {
+      const int64_t key = plan_phase_key(p, p->step) * 1000003 + K;
+      auto it = p->graphs.find(key);
+      if (it == p->graphs.end()) {
+        if (!p->cap) HIPCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+        GraphEntry ge;
+        HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+        const int r = plan_enqueue(p, K, p->cap);
+        hipGraph_t gr = nullptr;
+        const hipError_t e = hipStreamEndCapture(p->cap, &gr);
+        if (r) {
+          if (gr) (void)hipGraphDestroy(gr);
+          return r;
+        }
+        if (e != hipSuccess) return fail(FDTD_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        ge.graph = gr;
+        HIPCHK(hipGraphInstantiate(&ge.exec, gr, nullptr, nullptr, 0));
+        it = p->graphs.emplace(key, ge).first;
+      }
+      HIPCHK(hipGraphLaunch(it->second.exec, st));
+      p->step += K;
+      done += K;
+    }
+  }
+  if (n - done > 0) {
+    const int r = plan_enqueue(p, n - done, st);
+    if (r) return r;
+    p->step += n - done;
+  }
+  return FDTD_OK;
+}
+
+int fdtd_step(fdtd_plan* p, int64_t n, void* stream) {
+  if (!p) return fail(FDTD_EINVAL, "null plan");
+  if (!p->bound) return fail(FDTD_ESTATE, "plan not bound");
+  return plan_step(p, n, (hipStream_t)stream);
+}
+
+int64_t fdtd_step_count(const fdtd_plan* p) { return p ? p->step : -1; }
+int64_t fdtd_cell_count(const fdtd_plan* p) { return p ? p->ncell : -1; }
+double fdtd_dt(const fdtd_plan* p) { return p ? p->dt : 0.0; }
+
+int fdtd_read_field(fdtd_plan* p, int32_t comp, float* host, void* stream) {
+  if (!p || !host) return fail(FDTD_EINVAL, "null argument");
+  if (!p->bound) return fail(FDTD_ESTATE, "plan not bound");
+  if (comp < 0 || comp > 5) return fail(FDTD_EINVAL, "component must be 0..5");
+  hipStream_t st = (hipStream_t)stream;
+  const int par = (int)(p->step & 1);
+  const size_t off = comp < 3 ? p->L.E[par][comp] : p->L.H[par][comp - 3];
+  HIPCHK(hipMemcpyAsync(host, p->arena + off, sizeof(float) * (size_t)p->ncell, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return FDTD_OK;
+}
+
+int fdtd_write_field(fdtd_plan* p, int32_t comp, const float* host, void* stream) {
+  if (!p || !host) return fail(FDTD_EINVAL, "null argument");
+  if (!p->bound) return fail(FDTD_ESTATE, "plan not bound");
+  if (comp < 0 || comp > 5) return fail(FDTD_EINVAL, "component must be 0..5");
+  hipStream_t st = (hipStream_t)stream;
+  const int par = (int)(p->step & 1);
+  const size_t off = comp < 3 ? p->L.E[par][comp] : p->L.H[par][comp - 3];
+  HIPCHK(hipMemcpyAsync(p->arena + off, host, sizeof(float) * (size_t)p->ncell, hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return FDTD_OK;
+}
+
+int fdtd_read_probe(fdtd_plan* p, int32_t id, float* host, int64_t* n, void* stream) {
+  if (!p || !host) return fail(FDTD_EINVAL, "null argument");
+  if (!p->bound) return fail(FDTD_ESTATE, "plan not bound");
+  if (id < 0 || id >= (int)p->probes.size()) return fail(FDTD_EINVAL, "bad probe id");
+  hipStream_t st = (hipStream_t)stream;
+  if (p->step > 0)
+    HIPCHK(hipMemcpyAsync(host, p->arena + p->L.probe + sizeof(float) * (size_t)id * (size_t)p->max_steps,
+                          sizeof(float) * (size_t)p->step, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (n) *n = p->step;
+  return FDTD_OK;
+}
+
+int fdtd_read_flux(fdtd_plan* p, int32_t id, double* T, double* spec, int64_t* n, void* stream) {
+  if (!p) return fail(FDTD_EINVAL, "null plan");
+  if (!p->bound) return fail(FDTD_ESTATE, "plan not bound");
+  if (id < 0 || id >= (int)p->flux.size()) return fail(FDTD_EINVAL, "bad flux id");
+  hipStream_t st = (hipStream_t)stream;
+  const double dx2 = p->dx * p->dx;
+  if (T && p->step > 0) {
+    std::vector<double> part((size_t)p->step * p->nblk);
+    HIPCHK(hipMemcpyAsync(part.data(), p->arena + p->L.fluxT[id], sizeof(double) * part.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int64_t s = 0; s < p->step; ++s) {
+      double acc = 0.0;
+      for (int b = 0; b < p->nblk; ++b) acc += part[(size_t)s * p->nblk + b];
+      T[s] = acc * dx2;
+    }
+  }
+  const Flux& fl = p->flux[id];
+  if (spec && fl.nf > 0) {
+    const size_t plane = (size_t)p->g.nx * p->g.ny;
+    std::vector<double> acc(2 * 4 * (size_t)fl.nf * plane);
+    HIPCHK(hipMemcpyAsync(acc.data(), p->arena + p->L.fluxacc[id], sizeof(double) * acc.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int q = 0; q < fl.nf; ++q) {
+      double sum = 0.0;
+      for (size_t pt = 0; pt < plane; ++pt) {
+        const double* ex = &acc[2 * ((0 * (size_t)fl.nf + q) * plane + pt)];
+        const double* ey = &acc[2 * ((1 * (size_t)fl.nf + q) * plane + pt)];
+        const double* hx = &acc[2 * ((2 * (size_t)fl.nf + q) * plane + pt)];
+        const double* hy = &acc[2 * ((3 * (size_t)fl.nf + q) * plane + pt)];
+        sum += (ex[0] * hy[0] + ex[1] * hy[1]) - (ey[0] * hx[0] + ey[1] * hx[1]);
+      }
+      spec[q] = sum * dx2;
+    }
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  if (n) *n = p->step;
+  return FDTD_OK;
+}
+
+int fdtd_read_populations(fdtd_plan* p, float* host, void* stream) {
+  if (!p || !host) return fail(FDTD_EINVAL, "null argument");
+  if (!p->bound) return fail(FDTD_ESTATE, "plan not bound");
+  if (!p->has_gain) return fail(FDTD_ESTATE, "no gain material");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nc = (size_t)p->ncell;
+  std::vector<float> pop(6 * nc);
+  HIPCHK(hipMemcpyAsync(pop.data(), p->arena + p->L.pop, sizeof(float) * pop.size(), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (size_t o = 0; o < nc; ++o) {
+    if (!p->mats[p->host_map[o]].gain) {
+      for (int l = 0; l < 4; ++l) host[l * nc + o] = 0.0f;
+      continue;
+    }
+    double lv[3];
+    for (int l = 0; l < 3; ++l) lv[l] = (double)pop[l * nc + o] + (double)pop[(3 + l) * nc + o];
+    host[0 * nc + o] = (float)(1.0 - (lv[0] + lv[1] + lv[2]));
+    for (int l = 0; l < 3; ++l) host[(1 + l) * nc + o] = (float)lv[l];
+  }
+  return FDTD_OK;
+}
+
+int fdtd_read_polarization(fdtd_plan* p, float* host, void* stream) {
+  if (!p || !host) return fail(FDTD_EINVAL, "null argument");
+  if (!p->bound) return fail(FDTD_ESTATE, "plan not bound");
+  if (!p->has_gain) return fail(FDTD_ESTATE, "no gain material");
+  hipStream_t st = (hipStream_t)stream;
+  const int par = (int)(p->step & 1);
+  for (int c = 0; c < 3; ++c)
+    HIPCHK(hipMemcpyAsync(host + (size_t)c * p->ncell, p->arena + p->L.P[par][c], sizeof(float) * (size_t)p->ncell,
+                          hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return FDTD_OK;
+}
+
+int fdtd_read_energy(fdtd_plan* p, double* host, int64_t* n, void* stream) {
+  if (!p || !host || !n) return fail(FDTD_EINVAL, "null argument");
+  if (!p->bound) return fail(FDTD_ESTATE, "plan not bound");
+  if (p->ke <= 0) return fail(FDTD_ESTATE, "energy not enabled");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t ns = (p->step + p->ke - 1) / p->ke;
+  if (ns > 0) {
+    std::vector<double> part((size_t)ns * p->ntiles);
+    HIPCHK(hipMemcpyAsync(part.data(), p->arena + p->L.energy, sizeof(double) * part.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double w = 0.5 * p->dx * p->dx * p->dx;
+    for (int64_t s = 0; s < ns; ++s) {
+      double acc = 0.0;
+      for (int t = 0; t < p->ntiles; ++t) acc += part[(size_t)s * p->ntiles + t];
+      host[s] = acc * w;
+    }
+  }
+  *n = ns;
+  return FDTD_OK;
+}
+
+int fdtd_time_steps(fdtd_plan* p, int64_t n, void* stream, double* ms) {
+  if (!p || !ms) return fail(FDTD_EINVAL, "null argument");
+  if (!p->bound) return fail(FDTD_ESTATE, "plan not bound");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t a, b;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  HIPCHK(hipEventRecord(a, st));
+  int r = plan_step(p, n, st);
+  if (r) {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return r;
+  }
+  HIPCHK(hipEventRecord(b, st));
+  HIPCHK(hipEventSynchronize(b));
+  float f = 0.0f;
+  HIPCHK(hipEventElapsedTime(&f, a, b));
+  *ms = f;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return FDTD_OK;
+}
+
+int fdtd_class_cells(const fdtd_plan* p, int64_t* cells) {
+  if (!p || !cells) return fail(FDTD_EINVAL, "null argument");
+  if (!p->bound) return fail(FDTD_ESTATE, "plan not bound");
+  const int plane = p->g.nx * p->g.ny;
+  const int TX = p->tune.tile_x, TY = p->tune.block / p->tune.tile_x;
+  for (int c = 0; c < FD_NCLASS; ++c) {
+    int64_t acc = 0;
+    for (const fd_tile& t : p->tiles[c])
+      acc += (int64_t)std::min(TX, p->g.nx - t.i0) * std::min(TY, p->g.ny - t.j0) * (t.k1 - t.k0);
+    cells[c] = acc;
+  }
+  int64_t pts = 0;
+  for (const Flux& f : p->flux)
+    if (f.nf > 0) pts += plane;
+  cells[FD_NCLASS] = pts;
+  return FDTD_OK;
+}
+
+int fdtd_time_kernels(fdtd_plan* p, int64_t n, void* stream, double* ms, int64_t* launches) {
+  if (!p || !ms || !launches) return fail(FDTD_EINVAL, "null argument");
+  if (!p->bound) return fail(FDTD_ESTATE, "plan not bound");
+  if (n < 0 || p->step + n > p->max_steps) return fail(FDTD_ESTATE, "max_steps exceeded");
+  hipStream_t st = (hipStream_t)stream;
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  auto cleanup = [&]() {
+    for (Rec& r : recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+  };
+  auto record = [&](int cls, auto&& launch) -> int {
+    Rec r{cls, nullptr, nullptr};
+    HIPCHK(hipEventCreate(&r.a));
+    HIPCHK(hipEventCreate(&r.b));
+    recs.push_back(r);
+    HIPCHK(hipEventRecord(r.a, st));
+    HIPCHK(launch());
+    HIPCHK(hipEventRecord(r.b, st));
+    return FDTD_OK;
+  };
+  for (int64_t s = 0; s < n; ++s) {
+    for (int c = 0; c < FD_NCLASS; ++c) {
+      const int nt = (int)p->tiles[c].size();
+      if (nt == 0) continue;
+      const int grid = p->tune.max_blocks > 0 ? std::min(nt, p->tune.max_blocks) : nt;
+      const int r = record(c, [&]() { return fd_launch_step(c, p->dtiles[c], nt, p->tune.tile_x, p->tune.block, grid, (int)s, st); });
+      if (r) { cleanup(); return r; }
+    }
+    if (plan_dft_due(p, p->step + s) && !p->dft.empty()) {
+      const int r = record(FD_NCLASS, [&]() { return fd_launch_dft(p->ddft, (int)p->dft.size(), p->maxnf, 256, (int)s, st); });
+      if (r) { cleanup(); return r; }
+    }
+  }
+  hipError_t e = fd_launch_advance_one(p->ddesc, n, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(FDTD_EHIP, "time_kernels: %s", hipGetErrorString(e));
+  }
+  p->step += n;
+  for (int c = 0; c <= FD_NCLASS; ++c) {
+    ms[c] = 0.0;
+    launches[c] = 0;
+  }
+  for (Rec& r : recs) {
+    float f = 0.0f;
+    (void)hipEventElapsedTime(&f, r.a, r.b);
+    ms[r.cls] += f;
+    launches[r.cls] += 1;
+  }
+  cleanup();
+  return FDTD_OK;
+}
+
+// ------------------------------------------------------------------ batches
+
+int fdtd_batch_create(fdtd_plan* const* plans, int32_t n, fdtd_batch** out) {
+  if (!plans || !out || n < 1) return fail(FDTD_EINVAL, "need at least one plan");
+  *out = nullptr;
+  for (int q = 0; q < n; ++q)
+    if (!plans[q] || !plans[q]->bound) return fail(FDTD_ESTATE, "batch member %d not bound", q);
+  const int block = plans[0]->tune.block;
+  for (int q = 0; q < n; ++q) {
+    if (plans[q]->tune.block != block || plans[q]->tune.tile_x != plans[0]->tune.tile_x)
+      return fail(FDTD_EINVAL, "batch members must share the block size and tile width");
+    for (int r = 0; r < q; ++r)
+      if (plans[r] == plans[q]) return fail(FDTD_EINVAL, "plan listed twice");
+  }
+  fdtd_batch* b = new (std::nothrow) fdtd_batch();
+  if (!b) return fail(FDTD_ENOMEM, "host allocation");
+  b->plans.assign(plans, plans + n);
+  b->block = block;
+  b->tile_x = plans[0]->tune.tile_x;
+  b->max_blocks = plans[0]->tune.max_blocks;
+  b->graph_steps = plans[0]->tune.graph_steps;
+  for (fdtd_plan* p : b->plans) {
+    for (int c = 0; c < FD_NCLASS; ++c) b->tiles[c].insert(b->tiles[c].end(), p->tiles[c].begin(), p->tiles[c].end());
+    b->dft.insert(b->dft.end(), p->dft.begin(), p->dft.end());
+    b->maxnf = std::max(b->maxnf, p->maxnf);
+  }
+  size_t bytes = 0;
+  size_t off_t[FD_NCLASS];
+  for (int c = 0; c < FD_NCLASS; ++c) {
+    off_t[c] = bytes;
+    bytes = align256(bytes + sizeof(fd_tile) * b->tiles[c].size());
+  }
+  const size_t off_d = bytes;
+  bytes = align256(bytes + sizeof(fd_dft_tile) * std::max<size_t>(b->dft.size(), 1));
+  const size_t off_p = bytes;
+  bytes = align256(bytes + sizeof(fd_desc*) * (size_t)n);
+  // Setup-time allocation of the batch's launch tables (small; freed by destroy).
+  hipError_t e = hipMalloc(&b->dmem, bytes);
+  if (e != hipSuccess) {
+    delete b;
+    return fail(FDTD_EHIP, "hipMalloc(batch tables): %s", hipGetErrorString(e));
+  }
+  uint8_t* base = (uint8_t*)b->dmem;
+  std::vector<fd_desc*> dl;
+  for (fdtd_plan* p : b->plans) dl.push_back(p->ddesc);
+  e = hipSuccess;
+  for (int c = 0; c < FD_NCLASS && e == hipSuccess; ++c) {
+    b->dtiles[c] = (fd_tile*)(base + off_t[c]);
+    if (!b->tiles[c].empty())
+      e = hipMemcpy(b->dtiles[c], b->tiles[c].data(), sizeof(fd_tile) * b->tiles[c].size(), hipMemcpyHostToDevice);
+  }
+  b->ddft = (fd_dft_tile*)(base + off_d);
+  if (e == hipSuccess && !b->dft.empty())
+    e = hipMemcpy(b->ddft, b->dft.data(), sizeof(fd_dft_tile) * b->dft.size(), hipMemcpyHostToDevice);
+  b->ddescs = (fd_desc**)(base + off_p);
+  if (e == hipSuccess) e = hipMemcpy(b->ddescs, dl.data(), sizeof(fd_desc*) * dl.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(b->dmem);
+    delete b;
+    return fail(FDTD_EHIP, "batch table upload: %s", hipGetErrorString(e));
+  }
+  *out = b;
+  return FDTD_OK;
+}
+
+void fdtd_batch_destroy(fdtd_batch* b) {
+  if (!b) return;
+  for (auto& kv : b->graphs) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+  }
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->dmem) (void)hipFree(b->dmem);
+  delete b;
+}
+
+static bool batch_dft_due(const fdtd_batch* b, int64_t s) {
+  for (const fdtd_plan* p : b->plans)
+    if (plan_dft_due(p, p->step + s)) return true;
+  return false;
+}
+
+static int batch_enqueue(fdtd_batch* b, int64_t n, hipStream_t st) {
+  for (int64_t s = 0; s < n; ++s) {
+    const int r = enqueue_step(b->dtiles, b->tiles, b->tile_x, b->block, b->max_blocks, b->ddft, (int)b->dft.size(),
+                               b->maxnf,
+                               batch_dft_due(b, s), (int)s, st);
+    if (r) return r;
+  }
+  HIPCHK(fd_launch_advance(b->ddescs, (int)b->plans.size(), n, st));
+  return FDTD_OK;
+}
+
+static int batch_step(fdtd_batch* b, int64_t n, hipStream_t st) {
+  if (n < 0) return fail(FDTD_EINVAL, "negative step count");
+  for (fdtd_plan* p : b->plans)
+    if (p->step + n > p->max_steps) return fail(FDTD_ESTATE, "a member would exceed its max_steps");
+  const int64_t K = b->graph_steps;
+  int64_t done = 0;
+  if (K > 0) {
+    while (n - done >= K) {
+      std::vector<int64_t> key{K};
+      for (fdtd_plan* p : b->plans) key.push_back(plan_phase_key(p, p->step));
+      auto it = b->graphs.find(key);
+      if (it == b->graphs.end()) {
+        if (!b->cap) HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+        GraphEntry ge;
+        HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+        const int r = batch_enqueue(b, K, b->cap);
+        hipGraph_t gr = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->cap, &gr);
+        if (r) {
+          if (gr) (void)hipGraphDestroy(gr);
+          return r;
+        }
+        if (e != hipSuccess) return fail(FDTD_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        ge.graph = gr;
+        HIPCHK(hipGraphInstantiate(&ge.exec, gr, nullptr, nullptr, 0));
+        it = b->graphs.emplace(key, ge).first;
+      }
+      HIPCHK(hipGraphLaunch(it->second.exec, st));
+      for (fdtd_plan* p : b->plans) p->step += K;
+      done += K;
+    }
+  }
+  if (n - done > 0) {
+    const int r = batch_enqueue(b, n - done, st);
+    if (r) return r;
+    for (fdtd_plan* p : b->plans) p->step += n - done;
+  }
+  return FDTD_OK;
+}
+
+int fdtd_batch_step(fdtd_batch* b, int64_t n, void* stream) {
+  if (!b) return fail(FDTD_EINVAL, "null batch");
+  return batch_step(b, n, (hipStream_t)stream);
+}
+
+int fdtd_batch_time_steps(fdtd_batch* b, int64_t n, void* stream, double* ms) {
+  if (!b || !ms) return fail(FDTD_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, st));
+  const int r = batch_step(b, n, st);
+  if (r) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return r;
+  }
+  HIPCHK(hipEventRecord(e1, st));
+  HIPCHK(hipEventSynchronize(e1));
+  float f = 0.0f;
+  HIPCHK(hipEventElapsedTime(&f, e0, e1));
+  *ms = f;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return FDTD_OK;
+}
+
+}  // extern "C"

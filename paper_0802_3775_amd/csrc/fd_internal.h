@@ -1,0 +1,108 @@
+// Internal layout shared by the host runtime and the gfx950 kernels of libfdtd.
+// Not part of the ABI (include/fdtd.h is).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define FD_MAXMAT 16
+#define FD_MAXSRC 4
+#define FD_MAXPROBE 16
+#define FD_MAXFLUX 4
+#define FD_MAXBLOCK 256   // threads per workgroup upper bound (launch bounds)
+
+// Per-material coefficients, FP32 (built in FP64 on the host, rounded once).
+struct fd_mat {
+  float cb;        // dt / (eps dx)
+  float inv_eps;   // 1 / eps
+  float eps;       // eps (energy diagnostic)
+  int is_gain;
+  float C1, C2;    // Lorentz ADE: P^{n+1} = C1 P^n + C2 P^{n-1} + C3 (kappa' dn E + F)
+  float C3k;       // C3 * kappa'
+  float C3;
+  float noise;     // sigma_N / sqrt(dt dx^3)
+  float inv_dt;
+  float MI[3][4];  // rows 1..3 of (M - I), M the Crank-Nicolson propagator
+  float Bu[3];     // rows 1..3 of (B e2 - B e1): response to the stimulated transfer u
+  float pad[3];
+};
+
+// One realization on the device (lives in its plan's arena).
+struct fd_desc {
+  int nx, ny, nz, plane;
+  int per[3];                  // periodic axis flags
+  int ncell;
+  float ch;                    // dt / dx
+  int nmat;
+  int has_gain;
+  int block;                   // threads per workgroup used for this plan's tiles
+  long long step;              // absolute step at batch step 0 (advanced on the device)
+  long long max_steps;
+  const fd_mat* mats;
+  const uint8_t* mat;
+  float* E[2][3];              // ping-pong by step parity
+  float* H[2][3];
+  float* P[2][3];              // polarization ping-pong (P^n in [n&1], P^{n-1} in the other)
+  float* pop;                  // 6 planes of ncell floats: n1,n2,n3 high parts, then low parts
+  uint32_t key0, key1;
+  // CPML
+  int pml_lo[3], pml_hi[3], pml_t[3];
+  const float* prof[3];        // per axis 6 x n_axis: kE, bE, cE, kH, bH, cH
+  float* psiE[3][2];           // [axis][family], updated in place
+  float* psiH[2][3][2];        // [parity][axis][family]
+  // sources
+  int nsrc;
+  int src_kind[FD_MAXSRC], src_comp[FD_MAXSRC], src_cell[FD_MAXSRC], src_k[FD_MAXSRC];
+  int src_len[FD_MAXSRC];
+  const float* src_tab[FD_MAXSRC];   // dx * J(t_{n+1/2}) per step
+  // probes
+  int nprobe;
+  int probe_comp[FD_MAXPROBE], probe_cell[FD_MAXPROBE], probe_k[FD_MAXPROBE];
+  float* probe_ring;           // [nprobe][max_steps]
+  // flux planes
+  int nflux;
+  int flux_k[FD_MAXFLUX];
+  int nblk;                    // xy tiles per plane
+  double* flux_T[FD_MAXFLUX];  // [max_steps][nblk] partial sums (no dx^2)
+  int flux_nf[FD_MAXFLUX], flux_decim[FD_MAXFLUX];
+  const double* flux_f[FD_MAXFLUX];
+  double* flux_acc[FD_MAXFLUX];  // [4][nf][plane][2]
+  // energy
+  int ke;
+  int ntiles;
+  double* energy;              // [(max_steps/ke + 1)][ntiles] partial sums (no dx^3/2)
+  double dt;
+};
+
+// One unit of work: the tile_x x (block / tile_x) columns starting at (i0, j0),
+// marched over z-planes [k0, k1).  tidx: index among the plan's tiles; blk: index
+// of the xy tile (slot of the per-step transmitted-power partial sums).
+struct fd_tile {
+  const fd_desc* d;
+  int i0, j0, k0, k1;
+  int tidx, blk;
+};
+
+struct fd_dft_tile {
+  const fd_desc* d;
+  int flux;
+  int p0;
+  long long pad;
+};
+
+// Tile classes: kernels specialised on (CPML present in the tile, gain present in the tile).
+enum { FD_CLASS_PLAIN = 0, FD_CLASS_PML = 1, FD_CLASS_GAIN = 2, FD_CLASS_PML_GAIN = 3, FD_NCLASS = 4 };
+
+// Launchers (kernels.hip).
+hipError_t fd_launch_step(int cls, const fd_tile* tiles, int ntiles, int tile_x, int block, int grid,
+                          int s, hipStream_t st);
+hipError_t fd_launch_dft(const fd_dft_tile* tiles, int ntiles, int maxnf, int block, int s,
+                         hipStream_t st);
+hipError_t fd_launch_advance(fd_desc* const* descs, int n, long long k, hipStream_t st);
+hipError_t fd_launch_advance_one(fd_desc* d, long long k, hipStream_t st);
+hipError_t fd_launch_fill(void* p, size_t bytes, hipStream_t st);
+hipError_t fd_launch_voxelize(const int64_t* sites, int ex, int ey, int ez, const int* per,
+                              const int* ncr, const int* origin, const int64_t* reach,
+                              int res, int mat_bg, int mat_void, int mat_out,
+                              int nx, int ny, int nz, uint8_t* map, hipStream_t st);
+hipError_t fd_launch_init_pop(fd_desc* d_dev, const uint8_t* map, const float* n_init_by_mat,
+                              float* pop, int ncell, hipStream_t st);

@@ -1,0 +1,852 @@
+// gfx950 kernels of libfdtd: one fused Yee step (H then E, CPML, Lorentz ADE,
+// four-level populations, noise, soft sources, probes, transmitted power,
+// energy), the running-DFT flux update, the integer voxelizer and small helpers.
+//
+// Method: C. Conti and A. Fratalocchi, arXiv:0802.3775 — Yee FDTD with absorbing
+// walls in a disordered inverted opal, pumped gain medium seeded by a stochastic
+// source, transmitted power T(t) (sections "Sample and numerical approach" and
+// "Dynamical diffusion and localization").
+//
+// Stepping scheme.  E, H, the H-side CPML memory and the polarization are
+// double-buffered by step parity, so one step reads only buffer n&1 and writes
+// only the other one.  Every tile is therefore independent within a step, and a
+// workgroup can recompute the H^{n+1/2} values its E update needs at x-1, y-1 and
+// z-1 from the read-only inputs instead of waiting for the owner: one pass over
+// HBM per step (E, H, material index in; E, H out).
+//
+// Work mapping.  A tile is `block` consecutive (i,j) columns of the flattened xy
+// plane (x fastest, so every wavefront reads 64 contiguous floats per array) and a
+// z range [k0, k1) that the workgroup marches upward, carrying the H^{n+1/2} of
+// plane k-1 in registers.  Tiles whose columns touch no CPML slab and no gain cell
+// run a specialised kernel without that code.
+#include "fd_internal.h"
+
+namespace {
+
+constexpr float kTwoPiF = 6.28318530717958647692f;
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// ------------------------------------------------------------------ Philox
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c[0];
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]);
+    const uint32_t lo1 = 0xCD9E8D57u * c[2];
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    const uint32_t y0 = hi1 ^ c[1] ^ k0;
+    const uint32_t y2 = hi0 ^ c[3] ^ k1;
+    c[0] = y0; c[1] = lo1; c[2] = y2; c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+__device__ __forceinline__ float u24(uint32_t x) {
+  return (static_cast<float>(x >> 8) + 0.5f) * 5.9604644775390625e-8f;  // 2^-24
+}
+
+// Three standard normals for (step n, cell o): Box-Muller on the uniform pairs.
+__device__ __forceinline__ void normals3(uint32_t n, uint32_t o, uint32_t k0, uint32_t k1, float g[3]) {
+  uint32_t c[4] = {n, o, 0u, 2u};
+  philox10(c, k0, k1);
+  const float r0 = sqrtf(-2.0f * logf(u24(c[0])));
+  float s0, c0;
+  sincosf(kTwoPiF * u24(c[1]), &s0, &c0);
+  const float r1 = sqrtf(-2.0f * logf(u24(c[2])));
+  g[0] = r0 * c0;
+  g[1] = r0 * s0;
+  g[2] = r1 * cosf(kTwoPiF * u24(c[3]));
+}
+
+// ------------------------------------------------------------------ context
+// Field arrays are reached through pointers stored in the plan's descriptor, so
+// the compiler cannot infer their address space; every pointer is cast to the
+// global space (1) so loads and stores are global_* instructions, and the
+// descriptor itself to the constant space (4) so its fields are scalar loads.
+typedef __attribute__((address_space(1))) float gf;
+typedef __attribute__((address_space(1))) double gd;
+typedef __attribute__((address_space(1))) uint8_t gu8;
+typedef __attribute__((address_space(4))) fd_desc cdesc;
+typedef __attribute__((address_space(4))) fd_mat cmat;
+
+__device__ __forceinline__ gf* G(float* p) { return (gf*)p; }
+__device__ __forceinline__ const gf* G(const float* p) { return (const gf*)p; }
+__device__ __forceinline__ gd* G(double* p) { return (gd*)p; }
+__device__ __forceinline__ const gd* G(const double* p) { return (const gd*)p; }
+
+struct Ctx {
+  int nx, ny, nz, plane;
+  int px, py, pz;
+  float ch;
+  const gf* Ein[3];
+  gf* Eout[3];
+  const gf* Hin[3];
+  gf* Hout[3];
+  // CPML (used by the kernels specialised with PML)
+  int lo[3], hi[3], t[3], n[3];
+  const gf* prof[3];
+  gf* psiE[3][2];
+  const gf* psiHin[3][2];
+  gf* psiHout[3][2];
+};
+
+__device__ __forceinline__ void make_ctx(Ctx& x, const cdesc* d, int par, bool pml) {
+  x.nx = d->nx; x.ny = d->ny; x.nz = d->nz; x.plane = d->plane;
+  x.px = d->per[0]; x.py = d->per[1]; x.pz = d->per[2];
+  x.ch = d->ch;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    x.Ein[c] = G((const float*)d->E[par][c]);
+    x.Eout[c] = G(d->E[par ^ 1][c]);
+    x.Hin[c] = G((const float*)d->H[par][c]);
+    x.Hout[c] = G(d->H[par ^ 1][c]);
+  }
+  x.n[0] = d->nx; x.n[1] = d->ny; x.n[2] = d->nz;
+  if (!pml) return;
+#pragma unroll
+  for (int w = 0; w < 3; ++w) {
+    x.lo[w] = d->pml_lo[w]; x.hi[w] = d->pml_hi[w]; x.t[w] = d->pml_t[w];
+    x.prof[w] = G(d->prof[w]);
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      x.psiE[w][f] = G(d->psiE[w][f]);
+      x.psiHin[w][f] = G((const float*)d->psiH[par][w][f]);
+      x.psiHout[w][f] = G(d->psiH[par ^ 1][w][f]);
+    }
+  }
+}
+
+__device__ __forceinline__ int nxt(int i, int n, int per) { return i + 1 < n ? i + 1 : (per ? 0 : -1); }
+__device__ __forceinline__ int prv(int i, int n, int per) { return i > 0 ? i - 1 : (per ? n - 1 : -1); }
+
+// index along an axis after periodic wrap, or -1 beyond a PEC wall
+__device__ __forceinline__ int wrap(int i, int n, int per) {
+  if (i >= 0 && i < n) return i;
+  if (!per) return -1;
+  const int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// slab-local index along axis w, or -1 outside the slabs
+__device__ __forceinline__ int slab(const Ctx& x, int w, int p) {
+  if (x.t[w] == 0) return -1;
+  if (p < x.lo[w]) return p;
+  if (p >= x.n[w] - x.hi[w]) return p - (x.n[w] - x.hi[w]) + x.lo[w];
+  return -1;
+}
+
+// psi array offset for axis w, slab index sp, at (i, j, k)
+__device__ __forceinline__ int psi_off(const Ctx& x, int w, int sp, int i, int j, int k) {
+  if (w == 2) return sp * x.plane + j * x.nx + i;
+  if (w == 0) return (k * x.ny + j) * x.t[0] + sp;
+  return (k * x.t[1] + sp) * x.nx + i;
+}
+
+// family of component c within axis w's two stored psi arrays
+__device__ __forceinline__ int fam(int c, int w) { return c == (w + 1) % 3 ? 0 : 1; }
+
+// CPML stretch of one difference d along axis w at index p (E position when
+// HSIDE = false, H position when HSIDE = true): returns d/kappa + psi with the
+// psi recursion psi = b psi + c d; the owner of the cell stores psi.
+template <bool HSIDE>
+__device__ __forceinline__ float stretch(const Ctx& x, int c, int w, int p, int i, int j, int k, float d,
+                                         bool own) {
+  const int sp = slab(x, w, p);
+  if (sp < 0) return d;
+  const gf* pr = x.prof[w] + (HSIDE ? 3 : 0) * x.n[w];
+  const float kinv = pr[p], b = pr[x.n[w] + p], cc = pr[2 * x.n[w] + p];
+  const int off = psi_off(x, w, sp, i, j, k);
+  const int f = fam(c, w);
+  float psi;
+  if (HSIDE) {
+    psi = fmaf(b, x.psiHin[w][f][off], cc * d);
+    if (own) x.psiHout[w][f][off] = psi;
+  } else {
+    psi = fmaf(b, x.psiE[w][f][off], cc * d);
+    if (own) x.psiE[w][f][off] = psi;
+  }
+  return fmaf(d, kinv, psi);
+}
+
+// One H component from its two differences: H^{n+1/2} = H^{n-1/2} - (dt/dx)(d1 - d2),
+// each difference stretched by the CPML where the position lies in a slab.  The
+// owner and every workgroup that recomputes the value as a halo call this with
+// identical operands, so all copies agree bit for bit.
+// c: component; (w1, p1) / (w2, p2): axis and index of the two differences.
+template <bool PML>
+__device__ __forceinline__ float h_from(const Ctx& x, int c, int w1, int p1, int w2, int p2, int i, int j, int k,
+                                        float a1, float a0, float b1, float b0, float hold, bool own) {
+  float d1 = a1 - a0, d2 = b1 - b0;
+  if (PML) {
+    d1 = stretch<true>(x, c, w1, p1, i, j, k, d1, own);
+    d2 = stretch<true>(x, c, w2, p2, i, j, k, d2, own);
+  }
+  return fmaf(-x.ch, d1 - d2, hold);
+}
+
+// The same values from global memory (used for the plane below a tile's z range).
+template <bool PML>
+__device__ __forceinline__ float h_x(const Ctx& x, int i, int j, int k) {
+  const int o = k * x.plane + j * x.nx + i;
+  const int jp = nxt(j, x.ny, x.py), kp = nxt(k, x.nz, x.pz);
+  const float ez1 = jp >= 0 ? x.Ein[2][k * x.plane + jp * x.nx + i] : 0.0f;
+  const float ey1 = kp >= 0 ? x.Ein[1][kp * x.plane + j * x.nx + i] : 0.0f;
+  return h_from<PML>(x, 0, 1, j, 2, k, i, j, k, ez1, x.Ein[2][o], ey1, x.Ein[1][o], x.Hin[0][o], false);
+}
+
+template <bool PML>
+__device__ __forceinline__ float h_y(const Ctx& x, int i, int j, int k) {
+  const int o = k * x.plane + j * x.nx + i;
+  const int ip = nxt(i, x.nx, x.px), kp = nxt(k, x.nz, x.pz);
+  const float ex1 = kp >= 0 ? x.Ein[0][kp * x.plane + j * x.nx + i] : 0.0f;
+  const float ez1 = ip >= 0 ? x.Ein[2][k * x.plane + j * x.nx + ip] : 0.0f;
+  return h_from<PML>(x, 1, 2, k, 0, i, i, j, k, ex1, x.Ein[0][o], ez1, x.Ein[2][o], x.Hin[1][o], false);
+}
+
+// Workgroup barrier for LDS traffic only.  Within a step no workgroup reads
+// global memory that another thread of the step writes (inputs and outputs are
+// separate buffers), so the barrier waits for outstanding LDS operations but
+// not for global loads in flight: loads issued for the next z-plane keep
+// streaming across it.
+__device__ __forceinline__ void lds_barrier() {
+  __asm__ __volatile__("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Deterministic block sum (fixed shuffle tree, then wave partials in order).
+__device__ double block_sum(double v, double* sred) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  lds_barrier();
+  if (lane == 0) sred[w] = v;
+  lds_barrier();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) r += sred[q];
+  return r;
+}
+
+// (hi, lo) += inc as an unevaluated FP32 pair (Knuth's two-sum, then renormalise).
+__device__ __forceinline__ void two_sum(float& hi, float& lo, float inc) {
+  const float s = hi + inc;
+  const float bb = s - hi;
+  const float err = (hi - (s - bb)) + (inc - bb);
+  const float l = lo + err;
+  const float h2 = s + l;
+  lo = l - (h2 - s);
+  hi = h2;
+}
+
+template <int TX>
+struct Lds {
+  static constexpr int TYM = FD_MAXBLOCK / TX;
+  static constexpr int W = TX + 2;
+  float E[2][3][(TYM + 2) * (TX + 2)];  // E^n, planes k and k+1, over [i0-1, i0+TX] x [j0-1, j0+TY]
+  float H[3][(TYM + 1) * (TX + 1)];     // H^{n+1/2} of plane k over [i0-1, i0+TX-1] x [j0-1, j0+TY-1]
+  fd_mat mat[FD_MAXMAT];
+  double red[FD_MAXBLOCK / 64];
+};
+
+constexpr int RMAX = 3;  // ring cells staged per thread (block >= 64, tile_x <= 64)
+
+template <int TX, bool PML, bool GAIN>
+__device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
+  const cdesc* d = (const cdesc*)tl.d;
+  constexpr int W = Lds<TX>::W;
+  const int TY = (int)blockDim.x / TX;
+  const int t = (int)threadIdx.x;
+  const int tx = t % TX, ty = t / TX;
+  lds_barrier();  // LDS reuse across tiles of the persistent loop
+  {
+    const int words = d->nmat * (int)(sizeof(fd_mat) / 4);
+    const gf* src = G((const float*)d->mats);
+    float* dst = reinterpret_cast<float*>(s.mat);
+    for (int q = t; q < words; q += blockDim.x) dst[q] = src[q];
+  }
+  const long long n = d->step + s_rel;
+  const int par = (int)(n & 1);
+  Ctx x;
+  make_ctx(x, d, par, PML);
+  const int i0 = tl.i0, j0 = tl.j0, k0 = tl.k0, k1 = tl.k1;
+  const int i = i0 + tx, j = j0 + ty;
+  const bool act = i < x.nx && j < x.ny;
+  const int c = j * x.nx + i;
+
+  // ---- per-tile gather offsets (plane-relative), outside the z loop
+  int own_off;
+  {
+    const int gi = wrap(i, x.nx, x.px), gj = wrap(j, x.ny, x.py);
+    own_off = (gi >= 0 && gj >= 0) ? gj * x.nx + gi : -1;
+  }
+  const int own_slot = (ty + 1) * W + tx + 1;
+  int r_off[RMAX], r_slot[RMAX];
+  {
+    const int nring = 2 * (TX + 2) + 2 * TY;
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+      const int q = t + r * (int)blockDim.x;
+      r_slot[r] = -1;
+      r_off[r] = -1;
+      if (q < nring) {
+        int lx, ly;
+        if (q < TX + 2) { lx = q; ly = 0; }
+        else if (q < 2 * (TX + 2)) { lx = q - (TX + 2); ly = TY + 1; }
+        else if (q < 2 * (TX + 2) + TY) { lx = 0; ly = 1 + q - 2 * (TX + 2); }
+        else { lx = TX + 1; ly = 1 + q - 2 * (TX + 2) - TY; }
+        const int gi = wrap(i0 - 1 + lx, x.nx, x.px), gj = wrap(j0 - 1 + ly, x.ny, x.py);
+        r_slot[r] = ly * W + lx;
+        r_off[r] = (gi >= 0 && gj >= 0) ? gj * x.nx + gi : -1;
+      }
+    }
+  }
+  // halo duty: threads [0, TY) own the column i0-1, threads [TY, TY+TX) the row j0-1
+  const bool lh = t < TY;
+  const bool bh = !lh && t < TY + TX;
+  const int hgi = wrap(lh ? i0 - 1 : i0 + (t - TY), x.nx, x.px);
+  const int hgj = wrap(lh ? j0 + t : j0 - 1, x.ny, x.py);
+  const bool hact = (lh || bh) && hgi >= 0 && hgj >= 0 && (lh ? (j0 + t < x.ny) : (i0 + (t - TY) < x.nx));
+  const int h_off = hact ? hgj * x.nx + hgi : 0;
+
+  // ---- per-tile masks of sources, probes and flux planes that can touch it
+  const int iend = i0 + TX, jend = j0 + TY;
+  unsigned srcmask = 0u, srcmine = 0u;
+  for (int q = 0; q < d->nsrc; ++q) {
+    if (d->src_k[q] < k0 || d->src_k[q] >= k1) continue;
+    if (d->src_kind[q] == 1) {
+      srcmask |= 1u << q;
+      srcmine |= 1u << q;
+    } else {
+      const int sc = d->src_cell[q], si = sc % x.nx, sj = sc / x.nx;
+      if (si >= i0 && si < iend && sj >= j0 && sj < jend) {
+        srcmask |= 1u << q;
+        if (sc == c) srcmine |= 1u << q;
+      }
+    }
+  }
+  unsigned pmask = 0u;
+  for (int q = 0; q < d->nprobe; ++q) {
+    const int pc = d->probe_cell[q], pi = pc % x.nx, pj = pc / x.nx;
+    if (d->probe_k[q] >= k0 && d->probe_k[q] < k1 && pi >= i0 && pi < iend && pj >= j0 && pj < jend)
+      pmask |= 1u << q;
+  }
+  unsigned fmask = 0u;
+  for (int q = 0; q < d->nflux; ++q)
+    if (d->flux_k[q] >= k0 && d->flux_k[q] < k1) fmask |= 1u << q;
+  const bool edue = d->ke > 0 && (n % d->ke) == 0;
+  double eacc = 0.0;
+
+  // ---- staging of E^n planes: global loads into registers (one plane ahead of
+  // use), then LDS stores.  Slots outside the grid hold the periodic image or 0.
+  struct Plane {
+    float own[3];
+    float ring[RMAX][3];
+  };
+  auto load_plane = [&](int kk, Plane& P) {
+    const int kz = kk < x.nz ? kk : (x.pz ? kk - x.nz : -1);
+    const int zo = kz * x.plane;
+    const bool okz = kz >= 0;
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) P.own[cc] = (okz && own_off >= 0) ? x.Ein[cc][zo + own_off] : 0.0f;
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc)
+        P.ring[r][cc] = (okz && r_off[r] >= 0) ? x.Ein[cc][zo + r_off[r]] : 0.0f;
+  };
+  auto store_plane = [&](int b, const Plane& P) {
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) s.E[b][cc][own_slot] = P.own[cc];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+      if (r_slot[r] < 0) continue;
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) s.E[b][cc][r_slot[r]] = P.ring[r][cc];
+    }
+  };
+  const gu8* matp = (const gu8*)d->mat;
+  // per-plane own inputs: H^{n-1/2} (own and halo duty) and the material index
+  struct Cell {
+    float ho[3];
+    float hh[2];
+    int m;
+  };
+  auto load_cell = [&](int kk, Cell& C) {
+    const int zo = kk * x.plane;
+    C.ho[0] = C.ho[1] = C.ho[2] = 0.0f;
+    C.hh[0] = C.hh[1] = 0.0f;
+    C.m = 0;
+    if (act) {
+      C.ho[0] = x.Hin[0][zo + c];
+      C.ho[1] = x.Hin[1][zo + c];
+      C.ho[2] = x.Hin[2][zo + c];
+      C.m = matp[zo + c];
+    }
+    if (hact) {
+      // the column i0-1 needs Hy, Hz; the row j0-1 needs Hx, Hz
+      C.hh[0] = lh ? x.Hin[1][zo + h_off] : x.Hin[0][zo + h_off];
+      C.hh[1] = x.Hin[2][zo + h_off];
+    }
+  };
+
+  float ecur[3], enxt[3];
+  int cb = 0;
+  Plane pre;
+  load_plane(k0, pre);
+  store_plane(cb, pre);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) ecur[q] = pre.own[q];
+  load_plane(k0 + 1, pre);
+  Cell cur, nxc;
+  load_cell(k0, cur);
+  float hxm = 0.0f, hym = 0.0f;
+  {
+    const int km = prv(k0, x.nz, x.pz);
+    if (act && km >= 0) {
+      hxm = h_x<PML>(x, i, j, km);
+      hym = h_y<PML>(x, i, j, km);
+    }
+  }
+
+  for (int k = k0; k < k1; ++k) {
+    const int nb = cb ^ 1;
+    // plane k+1 (loaded during the previous iteration) into LDS; issue the loads
+    // of plane k+2 and of the next plane's own inputs, consumed one iteration later
+    store_plane(nb, pre);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) enxt[q] = pre.own[q];
+    if (k + 1 < k1) {
+      load_plane(k + 2, pre);
+      load_cell(k + 1, nxc);
+    }
+    const int zo = k * x.plane;
+    const int o = zo + c;
+    const float* ho = cur.ho;
+    const int m = cur.m;
+    const float hho0 = cur.hh[0], hho1 = cur.hh[1];
+    lds_barrier();
+    // ---- H^{n+1/2} of plane k: own cell and halo duty
+    float hx = 0.0f, hy = 0.0f, hz = 0.0f;
+    {
+      const float* Ex = s.E[cb][0];
+      const float* Ey = s.E[cb][1];
+      const float* Ez = s.E[cb][2];
+      const int a = own_slot;
+      if (act) {
+        hx = h_from<PML>(x, 0, 1, j, 2, k, i, j, k, Ez[a + W], Ez[a], enxt[1], Ey[a], ho[0], true);
+        hy = h_from<PML>(x, 1, 2, k, 0, i, i, j, k, enxt[0], Ex[a], Ez[a + 1], Ez[a], ho[1], true);
+        hz = h_from<PML>(x, 2, 0, i, 1, j, i, j, k, Ey[a + 1], Ey[a], Ex[a + W], Ex[a], ho[2], true);
+        x.Hout[0][o] = hx;
+        x.Hout[1][o] = hy;
+        x.Hout[2][o] = hz;
+      }
+      const int hs = (ty + 1) * (TX + 1) + tx + 1;
+      s.H[0][hs] = hx;
+      s.H[1][hs] = hy;
+      s.H[2][hs] = hz;
+      if (hact) {
+        const float* Ex1 = s.E[nb][0];
+        const float* Ey1 = s.E[nb][1];
+        if (lh) {
+          // cell (i0-1, j0+t): LDS column 0, row t+1
+          const int e = (t + 1) * W;
+          const float hyv = h_from<PML>(x, 1, 2, k, 0, hgi, hgi, hgj, k, Ex1[e], Ex[e], Ez[e + 1], Ez[e], hho0, false);
+          const float hzv = h_from<PML>(x, 2, 0, hgi, 1, hgj, hgi, hgj, k, Ey[e + 1], Ey[e], Ex[e + W], Ex[e], hho1, false);
+          s.H[1][(t + 1) * (TX + 1)] = hyv;
+          s.H[2][(t + 1) * (TX + 1)] = hzv;
+        } else {
+          // cell (i0+q-1, j0-1): LDS row 0, column q
+          const int q = t - TY + 1;
+          const float hxv = h_from<PML>(x, 0, 1, hgj, 2, k, hgi, hgj, k, Ez[W + q], Ez[q], Ey1[q], Ey[q], hho0, false);
+          const float hzv = h_from<PML>(x, 2, 0, hgi, 1, hgj, hgi, hgj, k, Ey[q + 1], Ey[q], Ex[W + q], Ex[q], hho1, false);
+          s.H[0][q] = hxv;
+          s.H[2][q] = hzv;
+        }
+      }
+    }
+    lds_barrier();
+    // ---- E^{n+1} of plane k (own cell)
+    float ex_n = 0.0f, ey_n = 0.0f, ez_n = 0.0f;
+    if (act) {
+      const int hs = (ty + 1) * (TX + 1) + tx + 1;
+      const float hz_im = s.H[2][hs - 1], hy_im = s.H[1][hs - 1];
+      const float hx_jm = s.H[0][hs - (TX + 1)], hz_jm = s.H[2][hs - (TX + 1)];
+      const fd_mat& mt = s.mat[m];
+      const float* eo = ecur;
+      float dP[3] = {0.0f, 0.0f, 0.0f};
+      float Pnew[3] = {0.0f, 0.0f, 0.0f};
+      const bool g = GAIN && mt.is_gain;
+      float nh[3] = {0.0f, 0.0f, 0.0f}, nl[3] = {0.0f, 0.0f, 0.0f};
+      if (g) {
+        const int nc = d->ncell;
+        const gf* pop = G(d->pop);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          nh[q] = pop[q * nc + o];
+          nl[q] = pop[(3 + q) * nc + o];
+        }
+        const float n1 = nh[0] + nl[0], n2 = nh[1] + nl[1];
+        float F[3] = {0.0f, 0.0f, 0.0f};
+        if (mt.noise != 0.0f) {
+          float gg[3];
+          normals3((uint32_t)n, (uint32_t)o, d->key0, d->key1, gg);
+          const float amp = mt.noise * sqrtf(fmaxf(n2, 0.0f));
+#pragma unroll
+          for (int q = 0; q < 3; ++q) F[q] = amp * gg[q];
+        }
+        const float dn = n1 - n2;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const float Pn = G((const float*)d->P[par][q])[o];
+          const float Pm = G((const float*)d->P[par ^ 1][q])[o];
+          Pnew[q] = fmaf(mt.C1, Pn, fmaf(mt.C2, Pm, fmaf(mt.C3k * dn, eo[q], mt.C3 * F[q])));
+          dP[q] = Pnew[q] - Pn;
+        }
+      }
+      float cx = 0.0f, cy = 0.0f, cz = 0.0f;  // source terms dx*J of this cell
+      if (srcmask) {
+        for (int q = 0; q < FD_MAXSRC; ++q) {
+          if (!((srcmine >> q) & 1u) || d->src_k[q] != k) continue;
+          const float v = n < d->src_len[q] ? G((const float*)d->src_tab[q])[n] : 0.0f;
+          const int sc = d->src_comp[q];
+          if (sc == 0) cx += v;
+          else if (sc == 1) cy += v;
+          else cz += v;
+        }
+      }
+      if (!((!x.py && j == 0) || (!x.pz && k == 0))) {  // Ex: d/dy Hz - d/dz Hy
+        float d1 = hz - hz_jm, d2 = hy - hym;
+        if (PML) {
+          d1 = stretch<false>(x, 0, 1, j, i, j, k, d1, true);
+          d2 = stretch<false>(x, 0, 2, k, i, j, k, d2, true);
+        }
+        ex_n = fmaf(mt.cb, (d1 - d2) - cx, eo[0]) - dP[0] * mt.inv_eps;
+      }
+      if (!((!x.pz && k == 0) || (!x.px && i == 0))) {  // Ey: d/dz Hx - d/dx Hz
+        float d1 = hx - hxm, d2 = hz - hz_im;
+        if (PML) {
+          d1 = stretch<false>(x, 1, 2, k, i, j, k, d1, true);
+          d2 = stretch<false>(x, 1, 0, i, i, j, k, d2, true);
+        }
+        ey_n = fmaf(mt.cb, (d1 - d2) - cy, eo[1]) - dP[1] * mt.inv_eps;
+      }
+      if (!((!x.px && i == 0) || (!x.py && j == 0))) {  // Ez: d/dx Hy - d/dy Hx
+        float d1 = hy - hy_im, d2 = hx - hx_jm;
+        if (PML) {
+          d1 = stretch<false>(x, 2, 0, i, i, j, k, d1, true);
+          d2 = stretch<false>(x, 2, 1, j, i, j, k, d2, true);
+        }
+        ez_n = fmaf(mt.cb, (d1 - d2) - cz, eo[2]) - dP[2] * mt.inv_eps;
+      }
+      x.Eout[0][o] = ex_n;
+      x.Eout[1][o] = ey_n;
+      x.Eout[2][o] = ez_n;
+      if (g) {
+        const float en[3] = {ex_n, ey_n, ez_n};
+        float u = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) u = fmaf(0.5f * (eo[q] + en[q]), dP[q] * mt.inv_dt, u);
+        const float nn[4] = {1.0f - ((nh[0] + nh[1]) + nh[2]) - ((nl[0] + nl[1]) + nl[2]),
+                             nh[0] + nl[0], nh[1] + nl[1], nh[2] + nl[2]};
+        const int nc = d->ncell;
+        gf* pop = G(d->pop);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          float inc = mt.Bu[r] * u;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) inc = fmaf(mt.MI[r][q], nn[q], inc);
+          two_sum(nh[r], nl[r], inc);
+          pop[r * nc + o] = nh[r];
+          pop[(3 + r) * nc + o] = nl[r];
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) G(d->P[par ^ 1][q])[o] = Pnew[q];
+      }
+      if (pmask) {
+        for (int p = 0; p < FD_MAXPROBE; ++p) {
+          if (!((pmask >> p) & 1u) || d->probe_k[p] != k || d->probe_cell[p] != c) continue;
+          const int cp = d->probe_comp[p];
+          const float v = cp == 0 ? ex_n : cp == 1 ? ey_n : cp == 2 ? ez_n : cp == 3 ? hx : cp == 4 ? hy : hz;
+          G(d->probe_ring)[(long long)p * d->max_steps + n] = v;
+        }
+      }
+      if (edue) {
+        const float e2 = fmaf(eo[0], eo[0], fmaf(eo[1], eo[1], eo[2] * eo[2]));
+        const float hh = fmaf(ho[0], hx, fmaf(ho[1], hy, ho[2] * hz));
+        eacc += (double)(mt.eps * e2) + (double)hh;
+      }
+    }
+    // transmitted power through flux planes at this k (uniform branch)
+    if (fmask) {
+      for (int f = 0; f < FD_MAXFLUX; ++f) {
+        if (!((fmask >> f) & 1u) || d->flux_k[f] != k) continue;
+        double v = 0.0;
+        if (act) {
+          const float sx = 0.5f * (ecur[0] + ex_n), sy = 0.5f * (ecur[1] + ey_n);
+          const float hyc = 0.5f * (hym + hy), hxc = 0.5f * (hxm + hx);
+          v = (double)(sx * hyc) - (double)(sy * hxc);
+        }
+        const double tot = block_sum(v, s.red);
+        if (t == 0) G(d->flux_T[f])[n * d->nblk + tl.blk] = tot;
+      }
+    }
+    hxm = hx;
+    hym = hy;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) ecur[q] = enxt[q];
+    cur = nxc;
+    cb = nb;
+  }
+  if (edue) {
+    const double tot = block_sum(eacc, s.red);
+    if (t == 0) G(d->energy)[(n / d->ke) * d->ntiles + tl.tidx] = tot;
+  }
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup w runs on XCD
+// w mod 8), and each XCD has its own L2.  Renumber so that XCD x walks one
+// contiguous eighth of the tile list: tiles adjacent in the list (x, y and z
+// neighbours, whose halos overlap) then share an L2.  A bijection on [0, n).
+__device__ __forceinline__ int xcd_tile(int w, int n) {
+  constexpr int kXcd = 8;
+  const int q = n / kXcd, r = n % kXcd;
+  const int x = w % kXcd, s = w / kXcd;
+  return x * q + (x < r ? x : r) + s;
+}
+
+template <int TX, bool PML, bool GAIN>
+__global__ __launch_bounds__(FD_MAXBLOCK) void step_kernel(const fd_tile* __restrict__ tiles, int ntiles, int s) {
+  __shared__ Lds<TX> lds;
+  for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
+    const fd_tile tl = tiles[xcd_tile(w, ntiles)];
+    run_tile<TX, PML, GAIN>(tl, s, lds);
+  }
+}
+
+// Running DFT of the flux-plane fields, every decim steps of each realization.
+__global__ __launch_bounds__(FD_MAXBLOCK) void dft_kernel(const fd_dft_tile* __restrict__ tiles, int s) {
+  const fd_dft_tile t = tiles[blockIdx.x];
+  const cdesc* d = (const cdesc*)t.d;
+  const int fl = t.flux;
+  const int q = blockIdx.y;
+  if (q >= d->flux_nf[fl]) return;
+  const long long n = d->step + s;
+  if (n % d->flux_decim[fl] != 0) return;
+  const int p = t.p0 + (int)threadIdx.x;
+  if (p >= d->plane) return;
+  const int par = (int)(n & 1);
+  const int kf = d->flux_k[fl];
+  const int km = kf > 0 ? kf - 1 : d->nz - 1;
+  const int of = kf * d->plane + p, om = km * d->plane + p;
+  const gf* ex = G((const float*)d->E[par][0]);
+  const gf* ey = G((const float*)d->E[par][1]);
+  const gf* hx = G((const float*)d->H[par ^ 1][0]);
+  const gf* hy = G((const float*)d->H[par ^ 1][1]);
+  const double v[4] = {(double)ex[of], (double)ey[of], 0.5 * ((double)hx[om] + (double)hx[of]),
+                       0.5 * ((double)hy[om] + (double)hy[of])};
+  const double f = G((const double*)d->flux_f[fl])[q];
+  const double w = (double)d->flux_decim[fl] * d->dt;
+  double sE, cE, sH, cH;
+  sincos(kTwoPi * f * (double)n * d->dt, &sE, &cE);
+  sincos(kTwoPi * f * ((double)n + 0.5) * d->dt, &sH, &cH);
+  const int nf = d->flux_nf[fl];
+  gd* acc = G(d->flux_acc[fl]);
+#pragma unroll
+  for (int cpt = 0; cpt < 4; ++cpt) {
+    const size_t at = 2 * (((size_t)cpt * nf + q) * d->plane + p);
+    const double cr = cpt < 2 ? cE : cH, si = cpt < 2 ? sE : sH;
+    const double re = acc[at] + v[cpt] * cr * w;
+    const double im = acc[at + 1] + v[cpt] * si * w;
+    acc[at] = re;
+    acc[at + 1] = im;
+  }
+}
+
+__global__ void advance_kernel(fd_desc* const* descs, int n, long long k) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) descs[t]->step += k;
+}
+
+__global__ void advance_one_kernel(fd_desc* d, long long k) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) d->step += k;
+}
+
+__global__ void fill_kernel(uint4* p, size_t n16, uint8_t* tail, size_t ntail) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n16; q += stride)
+    p[q] = make_uint4(0u, 0u, 0u, 0u);
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < ntail) tail[t] = 0;
+}
+
+// Integer-exact voxelization: voxel centre X = (2 (i - origin) + 1) 2^16 quanta,
+// inside sphere (C, rho) iff |X - C|^2 < rho^2 (minimum image on periodic axes).
+// Candidate sites: those whose nominal position (h res 2^16 quanta along each axis)
+// lies within `reach` of the voxel centre.
+__device__ __forceinline__ long long floordiv_ll(long long a, long long b) {
+  long long q = a / b;
+  if ((a % b != 0) && (a < 0)) --q;
+  return q;
+}
+
+__global__ void voxelize_kernel(const int64_t* __restrict__ sites, int ex, int ey, int ez, int3 per,
+                                int3 ncr, int3 org, longlong3 reach, int res, int mat_bg, int mat_void,
+                                int mat_out, int nx, int ny, int nz, uint8_t* __restrict__ map) {
+  const long long ncell = (long long)nx * ny * nz;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long H16 = 65536;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < ncell; v += stride) {
+    const int i = (int)(v % nx);
+    const int j = (int)((v / nx) % ny);
+    const int k = (int)(v / ((long long)nx * ny));
+    const int rel[3] = {i - org.x, j - org.y, k - org.z};
+    const int nc[3] = {ncr.x, ncr.y, ncr.z};
+    bool in_crystal = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) in_crystal = in_crystal && rel[a] >= 0 && rel[a] < nc[a];
+    if (!in_crystal) {
+      map[v] = (uint8_t)mat_out;
+      continue;
+    }
+    const int pr[3] = {per.x, per.y, per.z};
+    const long long rc[3] = {reach.x, reach.y, reach.z};
+    const int ext[3] = {ex, ey, ez};
+    const long long X[3] = {(2LL * rel[0] + 1) * H16, (2LL * rel[1] + 1) * H16, (2LL * rel[2] + 1) * H16};
+    // res * 2^16 quanta between consecutive half-lattice sites; the period of a
+    // periodic axis is the crystal length, ncr * 2^17 quanta
+    long long hlo[3], hhi[3], sstep[3], period[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      sstep[a] = (long long)res * H16;
+      period[a] = (long long)nc[a] * 2 * H16;
+      hlo[a] = -floordiv_ll(-(X[a] - rc[a]), sstep[a]);  // ceil
+      hhi[a] = floordiv_ll(X[a] + rc[a], sstep[a]);
+      if (!pr[a]) {
+        if (hlo[a] < 0) hlo[a] = 0;
+        if (hhi[a] > ext[a] - 1) hhi[a] = ext[a] - 1;
+      }
+    }
+    bool hit = false;
+    for (long long l = hlo[2]; l <= hhi[2] && !hit; ++l) {
+      long long lw = l;
+      if (pr[2]) { lw %= ext[2]; if (lw < 0) lw += ext[2]; }
+      for (long long kk = hlo[1]; kk <= hhi[1] && !hit; ++kk) {
+        long long kw = kk;
+        if (pr[1]) { kw %= ext[1]; if (kw < 0) kw += ext[1]; }
+        for (long long h = hlo[0]; h <= hhi[0] && !hit; ++h) {
+          long long hw = h;
+          if (pr[0]) { hw %= ext[0]; if (hw < 0) hw += ext[0]; }
+          if (((hw + kw + lw) & 1) != 0) continue;
+          const int64_t* S = sites + 4 * ((lw * ey + kw) * ex + hw);
+          const long long rho = S[3];
+          if (rho <= 0) continue;
+          long long r2 = 0;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            long long dd = X[a] - S[a];
+            if (pr[a]) {
+              dd %= period[a];
+              if (dd < 0) dd += period[a];
+              if (2 * dd > period[a]) dd -= period[a];
+            }
+            r2 += dd * dd;
+          }
+          if (r2 < rho * rho) hit = true;
+        }
+      }
+    }
+    map[v] = (uint8_t)(hit ? mat_void : mat_bg);
+  }
+}
+
+__global__ void init_pop_kernel(const uint8_t* __restrict__ map, const float* __restrict__ ninit, float* pop,
+                                int ncell) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < ncell; o += stride) {
+    const int m = map[o];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      pop[q * ncell + o] = ninit[4 * m + 1 + q];
+      pop[(3 + q) * ncell + o] = 0.0f;
+    }
+  }
+}
+
+}  // namespace
+
+template <int TX>
+static hipError_t launch_tx(int cls, const fd_tile* tiles, int ntiles, int block, int grid, int s, hipStream_t st) {
+  switch (cls) {
+    case FD_CLASS_PLAIN: step_kernel<TX, false, false><<<grid, block, 0, st>>>(tiles, ntiles, s); break;
+    case FD_CLASS_PML: step_kernel<TX, true, false><<<grid, block, 0, st>>>(tiles, ntiles, s); break;
+    case FD_CLASS_GAIN: step_kernel<TX, false, true><<<grid, block, 0, st>>>(tiles, ntiles, s); break;
+    case FD_CLASS_PML_GAIN: step_kernel<TX, true, true><<<grid, block, 0, st>>>(tiles, ntiles, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t fd_launch_step(int cls, const fd_tile* tiles, int ntiles, int tile_x, int block, int grid, int s,
+                          hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  if (block < 64 || block > FD_MAXBLOCK || (block & 63) != 0 || grid <= 0 || block % tile_x != 0)
+    return hipErrorInvalidValue;
+  switch (tile_x) {
+    case 16: return launch_tx<16>(cls, tiles, ntiles, block, grid, s, st);
+    case 32: return launch_tx<32>(cls, tiles, ntiles, block, grid, s, st);
+    case 64: return launch_tx<64>(cls, tiles, ntiles, block, grid, s, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t fd_launch_dft(const fd_dft_tile* tiles, int ntiles, int maxnf, int block, int s, hipStream_t st) {
+  if (ntiles <= 0 || maxnf <= 0) return hipSuccess;
+  dft_kernel<<<dim3(ntiles, maxnf), block, 0, st>>>(tiles, s);
+  return hipGetLastError();
+}
+
+hipError_t fd_launch_advance(fd_desc* const* descs, int n, long long k, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  advance_kernel<<<(n + 255) / 256, 256, 0, st>>>(descs, n, k);
+  return hipGetLastError();
+}
+
+hipError_t fd_launch_advance_one(fd_desc* d, long long k, hipStream_t st) {
+  advance_one_kernel<<<1, 64, 0, st>>>(d, k);
+  return hipGetLastError();
+}
+
+hipError_t fd_launch_fill(void* p, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  const size_t n16 = bytes / 16;
+  const size_t ntail = bytes - n16 * 16;
+  size_t blocks = (n16 + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  fill_kernel<<<(unsigned)blocks, 256, 0, st>>>(reinterpret_cast<uint4*>(p), n16,
+                                                reinterpret_cast<uint8_t*>(p) + n16 * 16, ntail);
+  return hipGetLastError();
+}
+
+hipError_t fd_launch_voxelize(const int64_t* sites, int ex, int ey, int ez, const int* per, const int* ncr,
+                              const int* origin, const int64_t* reach, int res, int mat_bg,
+                              int mat_void, int mat_out, int nx, int ny, int nz, uint8_t* map, hipStream_t st) {
+  const long long ncell = (long long)nx * ny * nz;
+  long long blocks = (ncell + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  voxelize_kernel<<<(unsigned)blocks, 256, 0, st>>>(
+      sites, ex, ey, ez, make_int3(per[0], per[1], per[2]), make_int3(ncr[0], ncr[1], ncr[2]),
+      make_int3(origin[0], origin[1], origin[2]), make_longlong3(reach[0], reach[1], reach[2]), res, mat_bg,
+      mat_void, mat_out, nx, ny, nz, map);
+  return hipGetLastError();
+}
+
+hipError_t fd_launch_init_pop(fd_desc* d_dev, const uint8_t* map, const float* n_init_by_mat, float* pop, int ncell,
+                              hipStream_t st) {
+  (void)d_dev;
+  int blocks = (ncell + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  init_pop_kernel<<<blocks, 256, 0, st>>>(map, n_init_by_mat, pop, ncell);
+  return hipGetLastError();
+}

@@ -1,0 +1,193 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (stated for the method's FP32 fields):
+  - voxelized material maps: bit-exact;
+  - linear runs: field relative L2 <= 1e-4 at the final step, probes and T(t)
+    relative L2 <= 1e-4 / 1e-3, flux and transmission spectra <= 1e-3;
+  - lasing runs: population sum within 1e-6 of 1, fields <= 1e-3 up to onset.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import field_rel_l2, pec_clean, rel_l2, run_gpu, run_oracle
+from oracle import oracle as O
+from paper_0802_3775_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("maker", [
+    ("cell32", lambda: W.periodic_cell(res=32)),
+    ("slab_d0", lambda: W.slab(delta=0.0, seed=11, steps=1)),
+    ("slab_d02", lambda: W.slab(delta=0.02, seed=12, steps=1)),
+    ("slab_d05", lambda: W.slab(delta=0.05, seed=13, steps=1)),
+    ("slab_d10", lambda: W.slab(delta=0.10, seed=14, steps=1)),
+    ("lasing168", lambda: W.lasing(steps=1)),
+    ("ens5", lambda: W.ensemble(count=6, steps=1)[5]),
+    ("uniform_radius", lambda: dict(W.slab(delta=0.0, res=16, cells=(2, 2, 3), steps=1),
+                                    opal=dict(W.slab(res=16, cells=(2, 2, 3), steps=1)["opal"],
+                                              disorder="uniform", strength=0.3, r0=0.3536))),
+], ids=lambda m: m[0] if isinstance(m, tuple) else None)
+def test_voxel_map_bit_exact(maker):
+    import torch
+    from paper_0802_3775_amd import fdtd as F
+    name, mk = maker
+    cfg = mk()
+    _say("voxel map", name, cfg["grid"]["n"])
+    plan = F.Plan(cfg, max_steps=1)
+    got = plan.material_map()
+    want = O.voxelize(cfg["grid"], cfg["opal"], method="scatter")
+    assert np.array_equal(got, want)
+    assert np.array_equal(plan.spheres(), O.opal_spheres(cfg["grid"], cfg["opal"]))
+    plan.close()
+    torch.cuda.synchronize()
+
+
+def test_voxel_map_largest_serving_grid():
+    """The largest serving request: 10^3 cubic cells at 32 cells/a (320^3 crystal,
+    41.8 M cells with margins and z-CPML)."""
+    import torch
+    from paper_0802_3775_amd import fdtd as F
+    cfg = W.slab(delta=0.12, seed=4242, res=32, cells=(10, 10, 10), steps=1, nf=0)
+    _say("voxel map 320^3", cfg["grid"]["n"])
+    plan = F.Plan(cfg, max_steps=1)
+    got = plan.material_map()
+    want = O.voxelize(cfg["grid"], cfg["opal"], method="scatter")
+    assert np.array_equal(got, want)
+    plan.close()
+    torch.cuda.synchronize()
+
+
+def test_periodic_cell_full_config():
+    """One fcc cell at 32 cells/a, periodic, Ez dipole, 2000 steps."""
+    cfg = W.periodic_cell(res=32, steps=2000)
+    _say("periodic cell 32^3 x 2000")
+    orc = run_oracle(cfg, 2000)
+    gpu = run_gpu(cfg, 2000)
+    err = field_rel_l2(gpu.fields(), orc.fields())
+    perr = rel_l2(gpu.probe(0), orc.probe(0))
+    _say("field rel L2", err, "probe", perr)
+    assert err <= 1e-4 and perr <= 1e-4
+
+
+def _slab_small(delta=0.05, seed=13, steps=1600, empty=False):
+    return W.slab(delta=delta, seed=seed, res=12, cells=(2, 2, 3), steps=steps, nf=40, decim=8,
+                  empty=empty, energy_interval=50)
+
+
+def test_slab_reduced_fields_flux_spectra():
+    steps = 1600
+    cfg = _slab_small(steps=steps)
+    _say("slab reduced", cfg["grid"]["n"], steps)
+    orc = run_oracle(cfg, steps)
+    gpu = run_gpu(cfg, steps, tuning={"block": 128, "zchunk": 16, "graph_steps": 64})
+    err = field_rel_l2(gpu.fields(), orc.fields())
+    _say("fields", err)
+    assert err <= 1e-4
+    assert rel_l2(gpu.probe(0), orc.probe(0)) <= 1e-4
+    for f in range(2):
+        Tg, Sg = gpu.flux(f)
+        To, So = orc.flux(f)
+        _say("flux", f, rel_l2(Tg, To), rel_l2(Sg, So))
+        assert rel_l2(Tg, To) <= 1e-3
+        assert rel_l2(Sg, So) <= 1e-3
+    assert rel_l2(gpu.energy(), orc.energy()) <= 1e-4
+    # transmission spectrum against the empty-slab run
+    e_cfg = _slab_small(steps=steps, empty=True)
+    e_orc = run_oracle(e_cfg, steps)
+    e_gpu = run_gpu(e_cfg, steps)
+    tg = gpu.flux(0)[1] / e_gpu.flux(0)[1]
+    to = orc.flux(0)[1] / e_orc.flux(0)[1]
+    _say("transmission", rel_l2(tg, to))
+    assert rel_l2(tg, to) <= 1e-3
+
+
+def test_slab_full_size_random_fields():
+    """Full slab grid (80x80x224, z-CPML) from random initial fields: every cell,
+    the CPML slabs and the periodic wrap are exercised at the benchmark's size and
+    launch configuration."""
+    steps = 120
+    cfg = W.slab(delta=0.05, seed=13, steps=steps)
+    f = pec_clean(W.random_fields(cfg["grid"]["n"], seed=3), cfg["grid"]["periodic"])
+    cfg["init_fields"] = f
+    _say("slab full random", cfg["grid"]["n"], steps)
+    orc = run_oracle(cfg, steps)
+    gpu = run_gpu(cfg, steps, tuning={"block": 256, "zchunk": 32, "graph_steps": 40})
+    err = field_rel_l2(gpu.fields(), orc.fields())
+    _say("fields", err)
+    assert err <= 1e-4
+    for fl in range(2):
+        assert rel_l2(gpu.flux(fl)[0], orc.flux(fl)[0]) <= 1e-3
+
+
+@pytest.mark.parametrize("shape,periodic,pml", [
+    ((1, 1, 60), (1, 1, 0), (0, 0, 8)),
+    ((5, 6, 7), (0, 0, 0), (0, 0, 0)),
+    ((7, 1, 9), (1, 1, 0), (0, 0, 2)),
+    ((17, 13, 11), (0, 1, 0), (3, 0, 2)),
+    ((23, 19, 21), (0, 0, 0), (4, 5, 3)),
+    ((33, 30, 5), (1, 0, 1), (0, 6, 0)),
+])
+def test_edge_shapes_random_fields(shape, periodic, pml):
+    """Ragged blocks, one-cell axes, PEC boxes, CPML on each axis, random materials."""
+    steps = 60
+    cfg = W.homogeneous_box(n=shape, periodic=periodic, res=10, pml=pml, steps=steps,
+                            materials=[{"eps": 1.0}, {"eps": 3.0}, {"eps": 11.9}])
+    cfg["map"] = W.random_map(shape, 3, seed=8)
+    cfg["init_fields"] = pec_clean(W.random_fields(shape, seed=5), periodic)
+    cfg["energy_interval"] = 7
+    cfg["probes"] = [(0, 0, 0, shape[2] - 1), (5, shape[0] - 1, shape[1] - 1, 0)]
+    _say("edge", shape, periodic, pml)
+    orc = run_oracle(cfg, steps)
+    for tune in ({"block": 64, "zchunk": 1, "graph_steps": 0},
+                 {"block": 256, "zchunk": 4, "graph_steps": 16, "max_blocks": 3}):
+        gpu = run_gpu(cfg, steps, tuning=tune)
+        err = field_rel_l2(gpu.fields(), orc.fields())
+        assert err <= 1e-4, (tune, err)
+        for p in range(2):
+            assert rel_l2(gpu.probe(p), orc.probe(p)) <= 1e-4
+        assert rel_l2(gpu.energy(), orc.energy()) <= 1e-5
+
+
+def test_energy_invariant_closed_box():
+    """Lossless periodic box with random permittivity: W^n stays constant on the
+    GPU to FP32 accuracy and matches the oracle's W^n."""
+    n = (24, 20, 16)
+    steps = 400
+    cfg = W.homogeneous_box(n=n, res=12, steps=steps, materials=[{"eps": 1.0}, {"eps": 2.5}, {"eps": 11.9}])
+    cfg["map"] = W.random_map(n, 3, seed=5)
+    cfg["init_fields"] = W.random_fields(n, seed=9)
+    cfg["energy_interval"] = 1
+    orc = run_oracle(cfg, steps)
+    gpu = run_gpu(cfg, steps)
+    wg, wo = gpu.energy(), orc.energy()
+    assert len(wg) == steps
+    assert np.max(np.abs(wg - wg[0])) / wg[0] < 2e-5
+    assert np.max(np.abs(wg - wo)) / wo[0] < 2e-5
+
+
+def test_lasing_reduced_populations_and_fields():
+    """Gain box (crystal flush with a 6-layer CPML on all faces), inverted start,
+    strong pump, seeded polarization noise."""
+    steps = 1500
+    cfg = W.lasing(res=10, cells=(2, 2, 2), pml=6, steps=steps, pump=1e13, noise=1e-3,
+                   n_init=(0.3, 0.1, 0.5, 0.1), energy_interval=10)
+    _say("lasing reduced", cfg["grid"]["n"], steps)
+    orc = run_oracle(cfg, steps)
+    gpu = run_gpu(cfg, steps, tuning={"block": 128, "zchunk": 8, "graph_steps": 50})
+    gain = orc.map == 1
+    Ng, No = gpu.populations(), orc.populations()
+    s = Ng.astype(np.float64).sum(axis=0)
+    assert np.max(np.abs(s[gain] - 1.0)) <= 1e-6
+    assert np.max(np.abs(Ng[:, gain] - No[:, gain])) <= 1e-5
+    w = orc.energy()
+    onset = np.argmax(w >= 0.01 * w.max())
+    err = field_rel_l2(gpu.fields(), orc.fields())
+    _say("lasing fields", err, "onset index", onset, "of", len(w))
+    assert err <= 1e-3
+    assert rel_l2(gpu.probe(0), orc.probe(0)) <= 1e-3
+    assert rel_l2(gpu.polarization()[:, gain], orc.polarization()[:, gain]) <= 1e-3
