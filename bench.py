@@ -6,13 +6,15 @@ Headline workload: the disordered slab for femtosecond-pulse transmission —
 vacuum margins and a 12-cell CPML on z (80x80x224 = 1,433,600 cells), Gaussian
 jitter delta = 0.05 a, 30 fs plane-wave pulse at 0.8 c/a, probe, transmitted power
 T(t) and running-DFT spectra (100 frequencies, every 8 steps) on two planes,
-energy every 100 steps.  One "step" is one full FDTD step of that slab.
+energy every 100 steps.  One "step" is one full FDTD step of that slab; the
+default run is the workload's 20,000 steps.
 
 Prints one JSON line: cell-updates/s of the plain stepper (inputs resident in
-HBM), the roofline of the dominant kernel measured live with hipEvents, the CPU
-oracle timed on a bounded sample of the same workload, and the batched
-(64 uneven realizations in one graph-captured launch sequence) and lasing
-(four-level gain box) figures beside it.
+HBM, autotuned launch shape, hipGraph replay), the roofline of the dominant
+kernel measured live with hipEvents around its launches, the CPU oracle timed
+on a bounded sample of the same workload, and beside them the batched ensemble
+(64 uneven realizations, one launch per tile class per step), the served
+request stream (p50/p99 latency), the lasing box and the 320^3 grid.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
 """
@@ -27,7 +29,6 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, vendor figure
 B_ALG_LINEAR = 49.0          # bytes per linear cell-update: E,H (24) + material (1) in, E,H (24) out
-B_PSI_PER_AXIS = 32.0        # CPML: 2 E-side psi (r+w) + 2 H-side psi (r + w) per slab axis
 METRIC = "cell-updates/s & HBM-roofline %, batched vs plain; served p50/p99 latency"
 
 
@@ -41,41 +42,76 @@ def headline_config(steps):
                   energy_interval=100)
 
 
-def measure_plain(args):
-    import torch
+def kernel_table(plan, nsteps):
+    """Per kernel class: average launch duration (hipEvents around each launch on
+    the launch stream) and algorithmic bytes per launch."""
     from paper_0802_3775_amd import fdtd
-    total = args.warmup + args.steps + args.kernel_steps
-    cfg = headline_config(total)
-    tuning = {"block": 256, "zchunk": 32, "graph_steps": 100, "max_blocks": 0}
-    plan = fdtd.Plan(cfg, max_steps=total, tuning=tuning)
-    ncell = plan.ncell
-    log("plain: grid %s, %d cells, warmup %d" % (cfg["grid"]["n"], ncell, args.warmup))
-    plan.step(args.warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan.step(args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
-    log("plain: %d steps in %.3f s" % (args.steps, wall))
-    # per-kernel durations with hipEvents around each launch, on the launch stream
-    ms, cnt = plan.time_kernels(args.kernel_steps)
+    ms, cnt = plan.time_kernels(nsteps)
     cells = plan.class_cells()
-    names = ["step_plain", "step_cpml", "step_gain", "step_cpml_gain", "dft"]
+    nf = max(plan.nf) if plan.nf else 0
     kern = {}
-    for c in range(5):
+    for c, name in enumerate(fdtd.Plan.CLASSES):
         if cnt[c] == 0:
             continue
         avg = ms[c] / cnt[c]
-        if c < 4:
-            nbytes = cells[c] * (B_ALG_LINEAR + (B_PSI_PER_AXIS if c in (1, 3) else 0.0))
+        if name == "dft":
+            nbytes = cells[c] * nf * 4 * 16 * 2      # 4 complex FP64 accumulators, read + write
         else:
-            nbytes = cells[4] * 4 * 100 * 16 * 2
-        kern[names[c]] = {"avg_ms": avg, "launches": int(cnt[c]), "cells": int(cells[c]),
-                          "alg_bytes": float(nbytes), "GBps": nbytes / (avg * 1e-3) / 1e9}
-    dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
+            nbytes = cells[c] * B_ALG_LINEAR        # CPML psi and gain bytes not counted (lower bound)
+        kern[name] = {"avg_ms": avg, "launches": int(cnt[c]), "cells": int(cells[c]),
+                      "alg_bytes": float(nbytes), "GBps": nbytes / (avg * 1e-3) / 1e9}
+    return kern
+
+
+def timed_run(plan, steps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.step(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def measure_plain(args):
+    from paper_0802_3775_amd import fdtd, tune
+    total = args.warmup + args.steps + args.kernel_steps
+    cfg = headline_config(total)
+    t0 = time.perf_counter()
+    tuning = tune.autotune(dict(cfg), budget_s=args.tune_seconds)
+    log("plain: tuning %s (%.1f s)" % (tuning, time.perf_counter() - t0))
+    plan = fdtd.Plan(cfg, max_steps=total, tuning=tuning)
+    log("plain: grid %s, %d cells, warmup %d" % (cfg["grid"]["n"], plan.ncell, args.warmup))
+    plan.step(args.warmup)
+    wall = timed_run(plan, args.steps)
+    log("plain: %d steps in %.3f s" % (args.steps, wall))
+    kern = kernel_table(plan, args.kernel_steps)
+    ncell = plan.ncell
     plan.close()
-    return {"ncell": ncell, "wall": wall, "kernels": kern, "dominant": dom, "cfg": cfg}
+    dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
+    return {"ncell": ncell, "wall": wall, "kernels": kern, "dominant": dom, "cfg": cfg, "tuning": tuning}
+
+
+def measure_big(args):
+    """The largest serving grid (10^3 cubic cells at 32 cells/a, 320x320x408): the
+    state (2 GB) is far larger than the 256 MB Infinity Cache."""
+    from paper_0802_3775_amd import fdtd, tune
+    from paper_0802_3775_amd import workloads as W
+    steps = 200
+    cfg = W.slab(delta=0.05, seed=4242, res=32, cells=(10, 10, 10), steps=steps + 150, nf=0)
+    tuning = tune.autotune(dict(cfg), budget_s=args.tune_seconds, quick=True)
+    plan = fdtd.Plan(cfg, max_steps=steps + 150, tuning=tuning)
+    plan.step(20)
+    wall = timed_run(plan, steps)
+    kern = kernel_table(plan, 100)
+    n = plan.ncell
+    plan.close()
+    k = kern["step_plain"]
+    return {"workload": "linear slab 10x10x10 cubic cells at 32 cells/a (320x320x408, z-CPML)",
+            "cells": n, "steps_timed": steps, "cell_updates_per_s": n * steps / wall, "tuning": tuning,
+            "roofline": {"bound": "hbm", "kernel": "step_plain", "achieved": k["GBps"], "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": k["GBps"] / HBM_PEAK_GBS, "avg_launch_ms": k["avg_ms"],
+                         "alg_bytes_per_launch": k["alg_bytes"]},
+            "kernels": kern}
 
 
 def measure_cpu(cfg, budget_s):
@@ -83,39 +119,32 @@ def measure_cpu(cfg, budget_s):
     sim = O.OracleSim(dict(cfg, steps=100000), max_steps=100000)
     t0 = time.perf_counter()
     sim.step(2)
-    t1 = time.perf_counter()
-    per = (t1 - t0) / 2
+    per = (time.perf_counter() - t0) / 2
     n = max(2, int(budget_s / max(per, 1e-6)))
     t0 = time.perf_counter()
     sim.step(n)
-    t1 = time.perf_counter()
+    dt = time.perf_counter() - t0
     ncell = cfg["grid"]["n"][0] * cfg["grid"]["n"][1] * cfg["grid"]["n"][2]
-    return {"value": ncell * n / (t1 - t0), "unit": "cell-updates/s", "cores": O.threads(),
-            "kind": "oracle", "sample": "%d steps of the headline slab (full %dx%dx%d grid, FP64, "
-            "steps 2..%d of the run), %.1f s" % ((n,) + tuple(cfg["grid"]["n"]) + (n + 2, t1 - t0))}
+    return {"value": ncell * n / dt, "unit": "cell-updates/s", "cores": O.threads(), "kind": "oracle",
+            "sample": "steps 3..%d of the headline slab run (full %dx%dx%d grid, FP64 oracle), %.1f s"
+                      % ((n + 2,) + tuple(cfg["grid"]["n"]) + (dt,))}
 
 
-def measure_batched(steps):
+def measure_batched(args, steps=300):
     import torch
-    from paper_0802_3775_amd import fdtd
+    from paper_0802_3775_amd import fdtd, tune
     from paper_0802_3775_amd import workloads as W
     cfgs = W.ensemble(count=64, steps=10000)
-    tuning = {"block": 256, "zchunk": 32, "graph_steps": 50, "max_blocks": 0}
+    tuning = tune.common_tuning(cfgs, budget_s=args.tune_seconds)
     total = 2 * steps + 100
     plans = [fdtd.Plan(c, max_steps=total, tuning=tuning) for c in cfgs]
     cells = sum(p.ncell for p in plans)
-    log("batched: %d realizations, %d cells" % (len(plans), cells))
-    # sequential plain: each realization alone
-    seq = 0.0
+    log("batched: %d realizations, %d cells, tuning %s" % (len(plans), cells, tuning))
     for p in plans:
         p.step(50)
-    torch.cuda.synchronize()
-    for p in plans:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        p.step(steps)
-        torch.cuda.synchronize()
-        seq += time.perf_counter() - t0
+    seq = 0.0
+    for p in plans:          # sequential plain: each realization alone
+        seq += timed_run(p, steps)
     b = fdtd.Batch(plans)
     b.step(50)
     torch.cuda.synchronize()
@@ -126,32 +155,60 @@ def measure_batched(steps):
     b.close()
     for p in plans:
         p.close()
-    full = 10000.0 / steps
-    return {"realizations": len(cfgs), "cells": cells, "steps_timed": steps,
+    scale = 10000.0 / steps
+    return {"realizations": len(cfgs), "cells": cells, "steps_timed": steps, "tuning": tuning,
             "cell_updates_per_s": cells * steps / tb,
             "sequential_cell_updates_per_s": cells * steps / seq,
-            "realizations_per_hour": 3600.0 * len(cfgs) / (tb * full),
-            "sequential_realizations_per_hour": 3600.0 * len(cfgs) / (seq * full),
-            "note": "10k-step runs extrapolated from %d timed steps" % steps}
+            "realizations_per_hour": 3600.0 * len(cfgs) / (tb * scale),
+            "sequential_realizations_per_hour": 3600.0 * len(cfgs) / (seq * scale),
+            "note": "10k-step runs extrapolated from %d timed steps per realization" % steps}
 
 
-def measure_lasing(steps):
-    import torch
-    from paper_0802_3775_amd import fdtd
+def measure_lasing(args, steps=1000):
+    from paper_0802_3775_amd import fdtd, tune
     from paper_0802_3775_amd import workloads as W
-    cfg = W.lasing(pump=1e10, steps=steps + 100)
-    plan = fdtd.Plan(cfg, max_steps=steps + 100,
-                     tuning={"block": 256, "zchunk": 24, "graph_steps": 100, "max_blocks": 0})
+    cfg = W.lasing(pump=1e10, steps=steps + 300)
+    tuning = tune.autotune(dict(cfg), budget_s=args.tune_seconds, quick=True)
+    plan = fdtd.Plan(cfg, max_steps=steps + 300, tuning=tuning)
     plan.step(100)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan.step(steps)
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
+    wall = timed_run(plan, steps)
+    kern = kernel_table(plan, 50)
     n = plan.ncell
     plan.close()
-    return {"workload": "lasing box 6x6x6 cells at 24 cells/a + 12-cell CPML (168^3), gain voids, "
-            "pump 1e10 s^-1", "cells": n, "steps_timed": steps, "cell_updates_per_s": n * steps / t}
+    return {"workload": "lasing box 6x6x6 cells at 24 cells/a + 12-cell CPML on all faces (168^3), "
+            "gain voids, pump 1e10 s^-1, noise", "cells": n, "steps_timed": steps,
+            "cell_updates_per_s": n * steps / wall, "tuning": tuning, "kernels": kern}
+
+
+def measure_serving(args, plain_rate):
+    """A reduced Poisson trace of mixed requests (70% linear slabs, 30% lasing
+    boxes, 27k-512k-cell crystals, 2000 steps each), offered at 0.9 of the
+    sequential capacity estimated from the plain stepper's rate."""
+    import torch
+    from paper_0802_3775_amd import serve
+    from paper_0802_3775_amd import workloads as W
+    base = W.serving_trace(count=args.serve_requests, seed=42, rho=1.0, capacity_per_s=1.0,
+                           n_range=(2, 4), res_range=(12, 20), cell_range=(30 ** 3, 80 ** 3),
+                           linear_steps=2000, lasing_steps=2000)
+    work = 0.0
+    for r in base:
+        c = serve.request_config(r)
+        work += c["grid"]["n"][0] * c["grid"]["n"][1] * c["grid"]["n"][2] * r["steps"]
+    cap = plain_rate / (work / len(base))          # requests per second, sequential estimate
+    lam = 0.9 * cap
+    reqs = [dict(r, arrival=r["arrival"] / lam) for r in base]
+    tuning = {"block": 256, "tile_x": 16, "zchunk": 2, "graph_steps": 100, "max_blocks": 0}
+    backend = serve.GpuBackend(tuning)
+    free, _ = torch.cuda.mem_get_info()
+    srv = serve.Server(backend, budget_bytes=int(0.5 * free), chunk=400)
+    wall = srv.run(reqs)
+    s_b = serve.summarize(reqs, wall, srv.results, srv.failed)
+    srv2, wall2 = serve.run_sequential(backend, reqs)
+    s_s = serve.summarize(reqs, wall2, srv2.results, srv2.failed)
+    return {"requests": len(reqs), "offered_rate_per_s": lam, "chunk_steps": 400,
+            "served": s_b, "sequential_fifo": s_s,
+            "note": "reduced trace (27k-512k-cell crystals plus margins and CPML, 2000 steps per "
+                    "request) so the run stays within the benchmark's time budget"}
 
 
 def main():
@@ -163,6 +220,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--tune-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-requests", type=int, default=24)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); the multi-GPU "
@@ -173,7 +232,6 @@ def main():
     plain = measure_plain(args)
     value = plain["ncell"] * args.steps / plain["wall"]
     dom = plain["kernels"][plain["dominant"]]
-    achieved = dom["GBps"]
     out = {
         "metric": METRIC,
         "value": value,
@@ -191,9 +249,9 @@ def main():
                                "(80x80x224 with 1a margins and 12-cell z-CPML), delta=0.05a, 30 fs "
                                "plane-wave pulse, probe + T(t) + 100-frequency DFT flux on 2 planes, "
                                "energy every 100 steps",
-                   "cells": plain["ncell"], "run_steps": 20000},
-        "roofline": {"bound": "hbm", "kernel": plain["dominant"], "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                   "cells": plain["ncell"], "run_steps": 20000, "tuning": plain["tuning"]},
+        "roofline": {"bound": "hbm", "kernel": plain["dominant"], "achieved": dom["GBps"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["GBps"] / HBM_PEAK_GBS,
                      "traffic": None, "alg_bytes_per_launch": dom["alg_bytes"],
                      "avg_launch_ms": dom["avg_ms"]},
         "kernels": plain["kernels"],
@@ -202,10 +260,14 @@ def main():
         log("cpu baseline ...")
         out["cpu_baseline"] = measure_cpu(plain["cfg"], args.cpu_seconds)
     if not args.no_extras:
-        log("batched ...")
-        out["batched"] = measure_batched(300)
+        log("320^3 ...")
+        out["big_320"] = measure_big(args)
         log("lasing ...")
-        out["lasing"] = measure_lasing(1000)
+        out["lasing"] = measure_lasing(args)
+        log("batched ...")
+        out["batched"] = measure_batched(args)
+        log("serving ...")
+        out["serving"] = measure_serving(args, value)
     print(json.dumps(out), flush=True)
 
 

@@ -208,13 +208,14 @@ int fdtd_time_steps(fdtd_plan* p, int64_t n, void* stream, double* ms);
 /* Same for a batch. */
 int fdtd_batch_time_steps(fdtd_batch* b, int64_t n, void* stream, double* ms);
 
-/* Kernel classes of a step: 0 plain tiles, 1 tiles with CPML, 2 tiles with gain
-   cells, 3 both; 4 is the running-DFT update.  cells[c] = cells covered by the
-   plan's tiles of class c (c < 4), cells[4] = flux-plane points. */
-int fdtd_class_cells(const fdtd_plan* p, int64_t* cells /* 5 */);
+/* Kernel classes of a step: 0 plain tiles, 1 tiles touching z-CPML slabs only,
+   2 tiles touching x or y slabs, 3-5 the same with gain cells; 6 is the
+   running-DFT update.  cells[c] = cells covered by the plan's tiles of class c
+   (c < 6), cells[6] = flux-plane points (7 entries). */
+int fdtd_class_cells(const fdtd_plan* p, int64_t* cells /* 7 */);
 /* Advance n steps without graphs, bracketing every kernel launch with a pair of
    hipEvents on the stream; ms[c] = summed milliseconds and launches[c] = number of
-   launches of class c (5 entries each, as above). */
+   launches of class c (7 entries each, as above). */
 int fdtd_time_kernels(fdtd_plan* p, int64_t n, void* stream, double* ms, int64_t* launches);
 
 #ifdef __cplusplus

@@ -73,6 +73,31 @@ struct GraphEntry {
   hipGraphExec_t exec = nullptr;
 };
 
+// Side streams and events that let the tile classes of one step run as
+// parallel branches of a captured graph (fork after the previous step, join
+// before the DFT / next step).
+struct Fork {
+  hipStream_t side[FD_NCLASS] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[FD_NCLASS] = {};
+  ~Fork() {
+    for (int c = 0; c < FD_NCLASS; ++c) {
+      if (side[c]) (void)hipStreamDestroy(side[c]);
+      if (join[c]) (void)hipEventDestroy(join[c]);
+    }
+    if (fork) (void)hipEventDestroy(fork);
+  }
+  int init() {
+    if (fork) return FDTD_OK;
+    HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    for (int c = 0; c < FD_NCLASS; ++c) {
+      HIPCHK(hipStreamCreateWithFlags(&side[c], hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&join[c], hipEventDisableTiming));
+    }
+    return FDTD_OK;
+  }
+};
+
 }  // namespace
 
 struct fdtd_plan {
@@ -101,13 +126,14 @@ struct fdtd_plan {
   int64_t step = 0;
   int nblk = 0, ntiles = 0;
   std::vector<fd_tile> tiles[FD_NCLASS];
-  fd_tile* dtiles[FD_NCLASS] = {nullptr, nullptr, nullptr, nullptr};
+  fd_tile* dtiles[FD_NCLASS] = {};
   std::vector<fd_dft_tile> dft;
   fd_dft_tile* ddft = nullptr;
   int maxnf = 0;
   int src_len[FD_MAXSRC] = {0, 0, 0, 0};
   bool has_gain = false;
   hipStream_t cap = nullptr;
+  std::unique_ptr<Fork> fork;
   std::map<int64_t, GraphEntry> graphs;
 };
 
@@ -121,10 +147,11 @@ struct fdtd_batch {
   std::vector<fd_dft_tile> dft;
   int maxnf = 0;
   void* dmem = nullptr;  // tile tables + desc pointer list (setup-time allocation)
-  fd_tile* dtiles[FD_NCLASS] = {nullptr, nullptr, nullptr, nullptr};
+  fd_tile* dtiles[FD_NCLASS] = {};
   fd_dft_tile* ddft = nullptr;
   fd_desc** ddescs = nullptr;
   hipStream_t cap = nullptr;
+  std::unique_ptr<Fork> fork;
   std::map<std::vector<int64_t>, GraphEntry> graphs;
 };
 
@@ -350,14 +377,30 @@ T* at(fdtd_plan* p, size_t off) {
 }
 
 // Enqueue one step (batch-relative index s) of the given tile sets.
+// Enqueue one step (batch-relative index s) of the given tile sets.  With a
+// Fork (graph capture) the non-empty classes become parallel graph branches.
 int enqueue_step(fd_tile* const dtiles[FD_NCLASS], const std::vector<fd_tile>* tiles, int tile_x, int block,
-                 int max_blocks, const fd_dft_tile* ddft, int ndft, int maxnf, bool dft_due, int s, hipStream_t st) {
-  for (int c = 0; c < FD_NCLASS; ++c) {
+                 int max_blocks, const fd_dft_tile* ddft, int ndft, int maxnf, bool dft_due, int s, hipStream_t st,
+                 Fork* fk) {
+  int used[FD_NCLASS], nused = 0;
+  for (int c = 0; c < FD_NCLASS; ++c)
+    if (!tiles[c].empty()) used[nused++] = c;
+  const bool par = fk && nused > 1;
+  if (par) HIPCHK(hipEventRecord(fk->fork, st));
+  for (int u = 0; u < nused; ++u) {
+    const int c = used[u];
     const int nt = (int)tiles[c].size();
-    if (nt == 0) continue;
     const int grid = max_blocks > 0 ? std::min(nt, max_blocks) : nt;
-    HIPCHK(fd_launch_step(c, dtiles[c], nt, tile_x, block, grid, s, st));
+    hipStream_t on = st;
+    if (par && u > 0) {
+      on = fk->side[c];
+      HIPCHK(hipStreamWaitEvent(on, fk->fork, 0));
+    }
+    HIPCHK(fd_launch_step(c, dtiles[c], nt, tile_x, block, grid, s, on));
+    if (par && u > 0) HIPCHK(hipEventRecord(fk->join[c], on));
   }
+  if (par)
+    for (int u = 1; u < nused; ++u) HIPCHK(hipStreamWaitEvent(st, fk->join[used[u]], 0));
   if (dft_due && ndft > 0) HIPCHK(fd_launch_dft(ddft, ndft, maxnf, 256, s, st));
   return FDTD_OK;
 }
@@ -375,11 +418,10 @@ int64_t plan_phase_key(const fdtd_plan* p, int64_t n0) {
   return n0 % l;
 }
 
-int plan_enqueue(fdtd_plan* p, int64_t n, hipStream_t st) {
+int plan_enqueue(fdtd_plan* p, int64_t n, hipStream_t st, Fork* fk) {
   for (int64_t s = 0; s < n; ++s) {
     const int r = enqueue_step(p->dtiles, p->tiles, p->tune.tile_x, p->tune.block, p->tune.max_blocks, p->ddft,
-                               (int)p->dft.size(),
-                               p->maxnf, plan_dft_due(p, p->step + s), (int)s, st);
+                               (int)p->dft.size(), p->maxnf, plan_dft_due(p, p->step + s), (int)s, st, fk);
     if (r) return r;
   }
   HIPCHK(fd_launch_advance_one(p->ddesc, n, st));
@@ -808,15 +850,16 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
         // A tile needs the CPML code if any H value it evaluates lies in a slab:
         // its own cells, the x-1 / y-1 neighbours it recomputes, and plane k0-1.
         // (Slabs only exist on PEC axes, so no wrap-around is involved.)
-        bool pml = false;
-        if (d.pml_t[2] && (t.k0 - 1 < d.pml_lo[2] || t.k1 > p->g.nz - d.pml_hi[2])) pml = true;
+        int axes = 0;
+        if (d.pml_t[2] && (t.k0 - 1 < d.pml_lo[2] || t.k1 > p->g.nz - d.pml_hi[2])) axes |= 4;
         const int iend = std::min(p->g.nx, t.i0 + TX), jend = std::min(p->g.ny, t.j0 + TY);
-        if (d.pml_t[0] && (t.i0 - 1 < d.pml_lo[0] || iend > p->g.nx - d.pml_hi[0])) pml = true;
-        if (d.pml_t[1] && (t.j0 - 1 < d.pml_lo[1] || jend > p->g.ny - d.pml_hi[1])) pml = true;
+        if (d.pml_t[0] && (t.i0 - 1 < d.pml_lo[0] || iend > p->g.nx - d.pml_hi[0])) axes |= 1;
+        if (d.pml_t[1] && (t.j0 - 1 < d.pml_lo[1] || jend > p->g.ny - d.pml_hi[1])) axes |= 2;
+        const int pml = axes == 0 ? 0 : (axes == 4 ? 1 : 2);
         bool gain = false;
         if (p->has_gain)
           for (int k = t.k0; k < t.k1 && !gain; ++k) gain = blk_gain[(size_t)k * p->nblk + t.blk] != 0;
-        const int cls = (pml ? 1 : 0) + (gain ? 2 : 0);
+        const int cls = pml + (gain ? 3 : 0);
         p->tiles[cls].push_back(t);
       }
   }
@@ -866,9 +909,11 @@ static int plan_step(fdtd_plan* p, int64_t n, hipStream_t st) {
       auto it = p->graphs.find(key);
       if (it == p->graphs.end()) {
         if (!p->cap) HIPCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+        if (!p->fork) p->fork.reset(new Fork());
+        if (int rf = p->fork->init()) return rf;
         GraphEntry ge;
         HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
-        const int r = plan_enqueue(p, K, p->cap);
+        const int r = plan_enqueue(p, K, p->cap, p->fork.get());
         hipGraph_t gr = nullptr;
         const hipError_t e = hipStreamEndCapture(p->cap, &gr);
         if (r) {
@@ -886,7 +931,7 @@ static int plan_step(fdtd_plan* p, int64_t n, hipStream_t st) {
     }
   }
   if (n - done > 0) {
-    const int r = plan_enqueue(p, n - done, st);
+    const int r = plan_enqueue(p, n - done, st, nullptr);
     if (r) return r;
     p->step += n - done;
   }
@@ -1219,11 +1264,10 @@ static bool batch_dft_due(const fdtd_batch* b, int64_t s) {
   return false;
 }
 
-static int batch_enqueue(fdtd_batch* b, int64_t n, hipStream_t st) {
+static int batch_enqueue(fdtd_batch* b, int64_t n, hipStream_t st, Fork* fk) {
   for (int64_t s = 0; s < n; ++s) {
     const int r = enqueue_step(b->dtiles, b->tiles, b->tile_x, b->block, b->max_blocks, b->ddft, (int)b->dft.size(),
-                               b->maxnf,
-                               batch_dft_due(b, s), (int)s, st);
+                               b->maxnf, batch_dft_due(b, s), (int)s, st, fk);
     if (r) return r;
   }
   HIPCHK(fd_launch_advance(b->ddescs, (int)b->plans.size(), n, st));
@@ -1243,9 +1287,11 @@ static int batch_step(fdtd_batch* b, int64_t n, hipStream_t st) {
       auto it = b->graphs.find(key);
       if (it == b->graphs.end()) {
         if (!b->cap) HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+        if (!b->fork) b->fork.reset(new Fork());
+        if (int rf = b->fork->init()) return rf;
         GraphEntry ge;
         HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-        const int r = batch_enqueue(b, K, b->cap);
+        const int r = batch_enqueue(b, K, b->cap, b->fork.get());
         hipGraph_t gr = nullptr;
         const hipError_t e = hipStreamEndCapture(b->cap, &gr);
         if (r) {
@@ -1263,7 +1309,7 @@ static int batch_step(fdtd_batch* b, int64_t n, hipStream_t st) {
     }
   }
   if (n - done > 0) {
-    const int r = batch_enqueue(b, n - done, st);
+    const int r = batch_enqueue(b, n - done, st, nullptr);
     if (r) return r;
     for (fdtd_plan* p : b->plans) p->step += n - done;
   }

@@ -89,8 +89,12 @@ struct fd_dft_tile {
   long long pad;
 };
 
-// Tile classes: kernels specialised on (CPML present in the tile, gain present in the tile).
-enum { FD_CLASS_PLAIN = 0, FD_CLASS_PML = 1, FD_CLASS_GAIN = 2, FD_CLASS_PML_GAIN = 3, FD_NCLASS = 4 };
+// Tile classes: kernels specialised on the CPML slabs a tile touches (none, z
+// only, any axis) and on gain cells being present.  class = cpml + 3 * gain.
+enum {
+  FD_CLASS_PLAIN = 0, FD_CLASS_PMLZ = 1, FD_CLASS_PML = 2,
+  FD_CLASS_GAIN = 3, FD_CLASS_PMLZ_GAIN = 4, FD_CLASS_PML_GAIN = 5, FD_NCLASS = 6
+};
 
 // Launchers (kernels.hip).
 hipError_t fd_launch_step(int cls, const fd_tile* tiles, int ntiles, int tile_x, int block, int grid,

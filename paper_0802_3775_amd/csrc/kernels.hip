@@ -150,9 +150,10 @@ __device__ __forceinline__ int fam(int c, int w) { return c == (w + 1) % 3 ? 0 :
 // CPML stretch of one difference d along axis w at index p (E position when
 // HSIDE = false, H position when HSIDE = true): returns d/kappa + psi with the
 // psi recursion psi = b psi + c d; the owner of the cell stores psi.
-template <bool HSIDE>
+template <bool HSIDE, int PM>
 __device__ __forceinline__ float stretch(const Ctx& x, int c, int w, int p, int i, int j, int k, float d,
                                          bool own) {
+  if (!((PM >> w) & 1)) return d;  // no slab on this axis in this tile class
   const int sp = slab(x, w, p);
   if (sp < 0) return d;
   const gf* pr = x.prof[w] + (HSIDE ? 3 : 0) * x.n[w];
@@ -175,34 +176,34 @@ __device__ __forceinline__ float stretch(const Ctx& x, int c, int w, int p, int 
 // owner and every workgroup that recomputes the value as a halo call this with
 // identical operands, so all copies agree bit for bit.
 // c: component; (w1, p1) / (w2, p2): axis and index of the two differences.
-template <bool PML>
+template <int PM>
 __device__ __forceinline__ float h_from(const Ctx& x, int c, int w1, int p1, int w2, int p2, int i, int j, int k,
                                         float a1, float a0, float b1, float b0, float hold, bool own) {
   float d1 = a1 - a0, d2 = b1 - b0;
-  if (PML) {
-    d1 = stretch<true>(x, c, w1, p1, i, j, k, d1, own);
-    d2 = stretch<true>(x, c, w2, p2, i, j, k, d2, own);
+  if (PM) {
+    d1 = stretch<true, PM>(x, c, w1, p1, i, j, k, d1, own);
+    d2 = stretch<true, PM>(x, c, w2, p2, i, j, k, d2, own);
   }
   return fmaf(-x.ch, d1 - d2, hold);
 }
 
 // The same values from global memory (used for the plane below a tile's z range).
-template <bool PML>
+template <int PM>
 __device__ __forceinline__ float h_x(const Ctx& x, int i, int j, int k) {
   const int o = k * x.plane + j * x.nx + i;
   const int jp = nxt(j, x.ny, x.py), kp = nxt(k, x.nz, x.pz);
   const float ez1 = jp >= 0 ? x.Ein[2][k * x.plane + jp * x.nx + i] : 0.0f;
   const float ey1 = kp >= 0 ? x.Ein[1][kp * x.plane + j * x.nx + i] : 0.0f;
-  return h_from<PML>(x, 0, 1, j, 2, k, i, j, k, ez1, x.Ein[2][o], ey1, x.Ein[1][o], x.Hin[0][o], false);
+  return h_from<PM>(x, 0, 1, j, 2, k, i, j, k, ez1, x.Ein[2][o], ey1, x.Ein[1][o], x.Hin[0][o], false);
 }
 
-template <bool PML>
+template <int PM>
 __device__ __forceinline__ float h_y(const Ctx& x, int i, int j, int k) {
   const int o = k * x.plane + j * x.nx + i;
   const int ip = nxt(i, x.nx, x.px), kp = nxt(k, x.nz, x.pz);
   const float ex1 = kp >= 0 ? x.Ein[0][kp * x.plane + j * x.nx + i] : 0.0f;
   const float ez1 = ip >= 0 ? x.Ein[2][k * x.plane + j * x.nx + ip] : 0.0f;
-  return h_from<PML>(x, 1, 2, k, 0, i, i, j, k, ex1, x.Ein[0][o], ez1, x.Ein[2][o], x.Hin[1][o], false);
+  return h_from<PM>(x, 1, 2, k, 0, i, i, j, k, ex1, x.Ein[0][o], ez1, x.Ein[2][o], x.Hin[1][o], false);
 }
 
 // Workgroup barrier for LDS traffic only.  Within a step no workgroup reads
@@ -251,7 +252,7 @@ struct Lds {
 
 constexpr int RMAX = 3;  // ring cells staged per thread (block >= 64, tile_x <= 64)
 
-template <int TX, bool PML, bool GAIN>
+template <int TX, int PM, bool GAIN>
 __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   const cdesc* d = (const cdesc*)tl.d;
   constexpr int W = Lds<TX>::W;
@@ -268,7 +269,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   const long long n = d->step + s_rel;
   const int par = (int)(n & 1);
   Ctx x;
-  make_ctx(x, d, par, PML);
+  make_ctx(x, d, par, PM != 0);
   const int i0 = tl.i0, j0 = tl.j0, k0 = tl.k0, k1 = tl.k1;
   const int i = i0 + tx, j = j0 + ty;
   const bool act = i < x.nx && j < x.ny;
@@ -404,8 +405,8 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   {
     const int km = prv(k0, x.nz, x.pz);
     if (act && km >= 0) {
-      hxm = h_x<PML>(x, i, j, km);
-      hym = h_y<PML>(x, i, j, km);
+      hxm = h_x<PM>(x, i, j, km);
+      hym = h_y<PM>(x, i, j, km);
     }
   }
 
@@ -434,9 +435,9 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       const float* Ez = s.E[cb][2];
       const int a = own_slot;
       if (act) {
-        hx = h_from<PML>(x, 0, 1, j, 2, k, i, j, k, Ez[a + W], Ez[a], enxt[1], Ey[a], ho[0], true);
-        hy = h_from<PML>(x, 1, 2, k, 0, i, i, j, k, enxt[0], Ex[a], Ez[a + 1], Ez[a], ho[1], true);
-        hz = h_from<PML>(x, 2, 0, i, 1, j, i, j, k, Ey[a + 1], Ey[a], Ex[a + W], Ex[a], ho[2], true);
+        hx = h_from<PM>(x, 0, 1, j, 2, k, i, j, k, Ez[a + W], Ez[a], enxt[1], Ey[a], ho[0], true);
+        hy = h_from<PM>(x, 1, 2, k, 0, i, i, j, k, enxt[0], Ex[a], Ez[a + 1], Ez[a], ho[1], true);
+        hz = h_from<PM>(x, 2, 0, i, 1, j, i, j, k, Ey[a + 1], Ey[a], Ex[a + W], Ex[a], ho[2], true);
         x.Hout[0][o] = hx;
         x.Hout[1][o] = hy;
         x.Hout[2][o] = hz;
@@ -451,15 +452,15 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         if (lh) {
           // cell (i0-1, j0+t): LDS column 0, row t+1
           const int e = (t + 1) * W;
-          const float hyv = h_from<PML>(x, 1, 2, k, 0, hgi, hgi, hgj, k, Ex1[e], Ex[e], Ez[e + 1], Ez[e], hho0, false);
-          const float hzv = h_from<PML>(x, 2, 0, hgi, 1, hgj, hgi, hgj, k, Ey[e + 1], Ey[e], Ex[e + W], Ex[e], hho1, false);
+          const float hyv = h_from<PM>(x, 1, 2, k, 0, hgi, hgi, hgj, k, Ex1[e], Ex[e], Ez[e + 1], Ez[e], hho0, false);
+          const float hzv = h_from<PM>(x, 2, 0, hgi, 1, hgj, hgi, hgj, k, Ey[e + 1], Ey[e], Ex[e + W], Ex[e], hho1, false);
           s.H[1][(t + 1) * (TX + 1)] = hyv;
           s.H[2][(t + 1) * (TX + 1)] = hzv;
         } else {
           // cell (i0+q-1, j0-1): LDS row 0, column q
           const int q = t - TY + 1;
-          const float hxv = h_from<PML>(x, 0, 1, hgj, 2, k, hgi, hgj, k, Ez[W + q], Ez[q], Ey1[q], Ey[q], hho0, false);
-          const float hzv = h_from<PML>(x, 2, 0, hgi, 1, hgj, hgi, hgj, k, Ey[q + 1], Ey[q], Ex[W + q], Ex[q], hho1, false);
+          const float hxv = h_from<PM>(x, 0, 1, hgj, 2, k, hgi, hgj, k, Ez[W + q], Ez[q], Ey1[q], Ey[q], hho0, false);
+          const float hzv = h_from<PM>(x, 2, 0, hgi, 1, hgj, hgi, hgj, k, Ey[q + 1], Ey[q], Ex[W + q], Ex[q], hho1, false);
           s.H[0][q] = hxv;
           s.H[2][q] = hzv;
         }
@@ -517,25 +518,25 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       }
       if (!((!x.py && j == 0) || (!x.pz && k == 0))) {  // Ex: d/dy Hz - d/dz Hy
         float d1 = hz - hz_jm, d2 = hy - hym;
-        if (PML) {
-          d1 = stretch<false>(x, 0, 1, j, i, j, k, d1, true);
-          d2 = stretch<false>(x, 0, 2, k, i, j, k, d2, true);
+        if (PM) {
+          d1 = stretch<false, PM>(x, 0, 1, j, i, j, k, d1, true);
+          d2 = stretch<false, PM>(x, 0, 2, k, i, j, k, d2, true);
         }
         ex_n = fmaf(mt.cb, (d1 - d2) - cx, eo[0]) - dP[0] * mt.inv_eps;
       }
       if (!((!x.pz && k == 0) || (!x.px && i == 0))) {  // Ey: d/dz Hx - d/dx Hz
         float d1 = hx - hxm, d2 = hz - hz_im;
-        if (PML) {
-          d1 = stretch<false>(x, 1, 2, k, i, j, k, d1, true);
-          d2 = stretch<false>(x, 1, 0, i, i, j, k, d2, true);
+        if (PM) {
+          d1 = stretch<false, PM>(x, 1, 2, k, i, j, k, d1, true);
+          d2 = stretch<false, PM>(x, 1, 0, i, i, j, k, d2, true);
         }
         ey_n = fmaf(mt.cb, (d1 - d2) - cy, eo[1]) - dP[1] * mt.inv_eps;
       }
       if (!((!x.px && i == 0) || (!x.py && j == 0))) {  // Ez: d/dx Hy - d/dy Hx
         float d1 = hy - hy_im, d2 = hx - hx_jm;
-        if (PML) {
-          d1 = stretch<false>(x, 2, 0, i, i, j, k, d1, true);
-          d2 = stretch<false>(x, 2, 1, j, i, j, k, d2, true);
+        if (PM) {
+          d1 = stretch<false, PM>(x, 2, 0, i, i, j, k, d1, true);
+          d2 = stretch<false, PM>(x, 2, 1, j, i, j, k, d2, true);
         }
         ez_n = fmaf(mt.cb, (d1 - d2) - cz, eo[2]) - dP[2] * mt.inv_eps;
       }
@@ -615,12 +616,12 @@ __device__ __forceinline__ int xcd_tile(int w, int n) {
   return x * q + (x < r ? x : r) + s;
 }
 
-template <int TX, bool PML, bool GAIN>
+template <int TX, int PM, bool GAIN>
 __global__ __launch_bounds__(FD_MAXBLOCK) void step_kernel(const fd_tile* __restrict__ tiles, int ntiles, int s) {
   __shared__ Lds<TX> lds;
   for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
     const fd_tile tl = tiles[xcd_tile(w, ntiles)];
-    run_tile<TX, PML, GAIN>(tl, s, lds);
+    run_tile<TX, PM, GAIN>(tl, s, lds);
   }
 }
 
@@ -778,10 +779,12 @@ __global__ void init_pop_kernel(const uint8_t* __restrict__ map, const float* __
 template <int TX>
 static hipError_t launch_tx(int cls, const fd_tile* tiles, int ntiles, int block, int grid, int s, hipStream_t st) {
   switch (cls) {
-    case FD_CLASS_PLAIN: step_kernel<TX, false, false><<<grid, block, 0, st>>>(tiles, ntiles, s); break;
-    case FD_CLASS_PML: step_kernel<TX, true, false><<<grid, block, 0, st>>>(tiles, ntiles, s); break;
-    case FD_CLASS_GAIN: step_kernel<TX, false, true><<<grid, block, 0, st>>>(tiles, ntiles, s); break;
-    case FD_CLASS_PML_GAIN: step_kernel<TX, true, true><<<grid, block, 0, st>>>(tiles, ntiles, s); break;
+    case FD_CLASS_PLAIN: step_kernel<TX, 0, false><<<grid, block, 0, st>>>(tiles, ntiles, s); break;
+    case FD_CLASS_PMLZ: step_kernel<TX, 4, false><<<grid, block, 0, st>>>(tiles, ntiles, s); break;
+    case FD_CLASS_PML: step_kernel<TX, 7, false><<<grid, block, 0, st>>>(tiles, ntiles, s); break;
+    case FD_CLASS_GAIN: step_kernel<TX, 0, true><<<grid, block, 0, st>>>(tiles, ntiles, s); break;
+    case FD_CLASS_PMLZ_GAIN: step_kernel<TX, 4, true><<<grid, block, 0, st>>>(tiles, ntiles, s); break;
+    case FD_CLASS_PML_GAIN: step_kernel<TX, 7, true><<<grid, block, 0, st>>>(tiles, ntiles, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

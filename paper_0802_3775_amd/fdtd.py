@@ -265,15 +265,18 @@ class Plan:
         _check(lib().fdtd_time_steps(self.h, int(n), _stream(stream), C.byref(ms)))
         return ms.value
 
+    CLASSES = ("step_plain", "step_cpml_z", "step_cpml", "step_gain", "step_cpml_z_gain",
+               "step_cpml_gain", "dft")
+
     def class_cells(self):
-        out = np.zeros(5, dtype=np.int64)
+        out = np.zeros(7, dtype=np.int64)
         _check(lib().fdtd_class_cells(self.h, _ptr(out, C.c_int64)))
         return out
 
     def time_kernels(self, n, stream=None):
         """Per kernel class: (total ms, launches) over n eager steps."""
-        ms = np.zeros(5, dtype=np.float64)
-        cnt = np.zeros(5, dtype=np.int64)
+        ms = np.zeros(7, dtype=np.float64)
+        cnt = np.zeros(7, dtype=np.int64)
         _check(lib().fdtd_time_kernels(self.h, int(n), _stream(stream), _ptr(ms, C.c_double),
                                        _ptr(cnt, C.c_int64)))
         return ms, cnt

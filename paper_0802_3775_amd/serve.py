@@ -1,0 +1,225 @@
+"""Continuous-batching solve server for disorder-realization requests.
+
+Requests (linear transmission runs or lasing runs of given size, resolution,
+disorder and seed) arrive over time.  The server admits them in arrival order
+while their HBM footprint fits the budget, keeps every admitted request's
+fields resident in its own device arena, and steps all admitted requests
+together in batched launches of `chunk` steps.  At every launch boundary it
+retires finished requests (results copied to the host), frees their arenas,
+and admits waiting requests into the freed memory, so new work joins while
+older work is still running.  Each request keeps its own step counter, source
+timing and DFT phase, so its result is bit-identical to a run of the same
+request alone.
+
+The scheduling policy (Server) is independent of the device: a Backend does
+the work.  GpuBackend drives libfdtd; tests drive the same policy with a host
+test double.
+"""
+import math
+import time
+
+from . import workloads as W
+
+
+def request_config(req):
+    """Workload dict of a request: linear slab (crystal n^3 cubic cells at `res`,
+    vacuum margins, z-CPML, pulse, transmission flux) or lasing box (n^3 cells,
+    CPML on all faces, gain voids at pump 1e10 s^-1)."""
+    n, res = int(req["n"]), int(req["res"])
+    if req["kind"] == "linear":
+        cfg = W.slab(delta=req["delta"], seed=req["seed"], res=res, cells=(n, n, n), steps=req["steps"],
+                     nf=req.get("nf", 100), decim=8, energy_interval=req.get("energy_interval", 100))
+    else:
+        cfg = W.lasing(pump=req.get("pump", 1e10), delta=req["delta"], seed=req["seed"], res=res,
+                       cells=(n, n, n), steps=req["steps"], energy_interval=req.get("energy_interval", 100))
+    cfg["name"] = "req%d_%s" % (req["id"], cfg["name"])
+    return cfg
+
+
+class GpuBackend:
+    """libfdtd plans and batches; one torch uint8 arena per request."""
+
+    def __init__(self, tuning=None):
+        import torch
+        from . import fdtd
+        self.fdtd = fdtd
+        self.torch = torch
+        self.tuning = tuning or fdtd.default_tuning()
+        self._batch = None
+        self._members = None
+
+    def prepare(self, req):
+        cfg = request_config(req)
+        plan = self.fdtd.Plan(cfg, max_steps=req["steps"], tuning=self.tuning, bind=False)
+        return {"plan": plan, "cfg": cfg, "bytes": plan.required_bytes() + 256}
+
+    def footprint(self, h):
+        return h["bytes"]
+
+    def bind(self, h):
+        h["plan"].bind()
+
+    def step(self, hs, n):
+        if len(hs) == 1:
+            hs[0]["plan"].step(n)   # a lone request runs on the plain stepper
+            return
+        members = tuple(id(h["plan"]) for h in hs)
+        if members != self._members:
+            if self._batch is not None:
+                self._batch.close()
+            self._batch = self.fdtd.Batch([h["plan"] for h in hs])
+            self._members = members
+        self._batch.step(n)
+
+    def sync(self):
+        self.torch.cuda.synchronize()
+
+    def healthy(self, h):
+        p = h["plan"]
+        if p.cfg.get("energy_interval") and p.step_count > 0:
+            w = p.energy()
+            if len(w) and not math.isfinite(float(w[-1])):
+                return False
+        if p.nprobe and p.step_count > 0:
+            v = p.probe(0)
+            if len(v) and not math.isfinite(float(v[-1])):
+                return False
+        return True
+
+    def result(self, h):
+        p = h["plan"]
+        out = {"probe": [p.probe(q) for q in range(p.nprobe)], "steps": p.step_count}
+        if p.nf:
+            out["flux"] = [p.flux(f) for f in range(len(p.nf))]
+        if p.cfg.get("energy_interval"):
+            out["energy"] = p.energy()
+        return out
+
+    def release(self, h):
+        if self._members is not None and id(h["plan"]) in self._members:
+            if self._batch is not None:
+                self._batch.close()
+            self._batch, self._members = None, None
+        h["plan"].close()
+
+
+class Server:
+    """Arrival-ordered admission by footprint; batched stepping in chunks."""
+
+    def __init__(self, backend, budget_bytes, chunk=400, max_active=64, clock=None, sleep=None):
+        self.backend = backend
+        self.budget = int(budget_bytes)
+        self.chunk = int(chunk)
+        self.max_active = int(max_active)
+        self.clock = clock or time.perf_counter
+        self.sleep = sleep or time.sleep
+        self.pending = []     # (req, handle) in arrival order
+        self.active = []      # dicts: req, h, done
+        self.used = 0
+        self.results = {}
+        self.failed = {}
+        self.cancelled = set()
+        self.log = []
+
+    def cancel(self, rid):
+        self.cancelled.add(rid)
+
+    def _admit(self, now):
+        while self.pending and self.pending[0][0]["arrival"] <= now and len(self.active) < self.max_active:
+            req, h = self.pending[0]
+            if req["id"] in self.cancelled:
+                self.pending.pop(0)
+                self.failed[req["id"]] = "cancelled before admission"
+                continue
+            need = self.backend.footprint(h)
+            if need > self.budget:
+                self.pending.pop(0)
+                self.failed[req["id"]] = "footprint %d exceeds the budget %d" % (need, self.budget)
+                continue
+            if self.used + need > self.budget:
+                break  # head of line waits for memory
+            self.pending.pop(0)
+            try:
+                self.backend.bind(h)
+            except Exception as e:  # allocation failure: report, keep serving others
+                self.failed[req["id"]] = "bind failed: %s" % (e,)
+                continue
+            self.used += need
+            self.active.append({"req": req, "h": h, "done": 0, "admitted": now})
+            self.log.append(("admit", req["id"], now))
+
+    def _retire(self, entry, now, ok=True, why=""):
+        req = entry["req"]
+        if ok:
+            res = self.backend.result(entry["h"])
+            res["latency"] = now - req["arrival"]
+            res["admitted"] = entry["admitted"]
+            self.results[req["id"]] = res
+            self.log.append(("done", req["id"], now))
+        else:
+            self.failed[req["id"]] = why
+            self.log.append(("fail", req["id"], now))
+        self.backend.release(entry["h"])
+        self.used -= self.backend.footprint(entry["h"])
+
+    def run(self, requests):
+        """Serve the requests (each with an 'arrival' time in seconds relative to the
+        start of run); returns wall time."""
+        reqs = sorted(requests, key=lambda r: (r["arrival"], r["id"]))
+        self.pending = [(r, self.backend.prepare(r)) for r in reqs]
+        t0 = self.clock()
+        while self.pending or self.active:
+            now = self.clock() - t0
+            self._admit(now)
+            if not self.active:
+                if self.pending:
+                    wait = self.pending[0][0]["arrival"] - (self.clock() - t0)
+                    if wait > 0:
+                        self.sleep(wait)
+                    elif self.used == 0:
+                        # nothing running and the head request cannot be admitted
+                        req, h = self.pending.pop(0)
+                        self.failed[req["id"]] = "not admissible"
+                continue
+            for e in list(self.active):
+                if e["req"]["id"] in self.cancelled:
+                    self.active.remove(e)
+                    self._retire(e, self.clock() - t0, ok=False, why="cancelled")
+            if not self.active:
+                continue
+            n = min(self.chunk, min(e["req"]["steps"] - e["done"] for e in self.active))
+            self.backend.step([e["h"] for e in self.active], n)
+            self.backend.sync()
+            now = self.clock() - t0
+            for e in list(self.active):
+                e["done"] += n
+                if not self.backend.healthy(e["h"]):
+                    self.active.remove(e)
+                    self._retire(e, now, ok=False, why="non-finite field")
+                elif e["done"] >= e["req"]["steps"]:
+                    self.active.remove(e)
+                    self._retire(e, now)
+        return self.clock() - t0
+
+
+def percentile(vals, q):
+    v = sorted(vals)
+    if not v:
+        return float("nan")
+    pos = (len(v) - 1) * q / 100.0
+    lo, hi = int(math.floor(pos)), int(math.ceil(pos))
+    return v[lo] + (v[hi] - v[lo]) * (pos - lo)
+
+
+def summarize(requests, wall, results, failed):
+    lat = [results[r["id"]]["latency"] for r in requests if r["id"] in results]
+    return {"requests": len(requests), "completed": len(lat), "failed": len(failed),
+            "wall_s": wall, "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),
+            "realizations_per_hour": 3600.0 * len(lat) / wall if wall > 0 else float("nan")}
+
+
+def run_sequential(backend, requests, clock=None, sleep=None):
+    """Baseline: one request at a time, in arrival order, each stepped alone."""
+    srv = Server(backend, budget_bytes=1 << 62, chunk=1 << 30, max_active=1, clock=clock, sleep=sleep)
+    wall = srv.run(requests)
+    return srv, wall

@@ -1,0 +1,131 @@
+"""Autotuner for the launch configuration of a plan.
+
+A tuning is {tile_x, block, zchunk, graph_steps, max_blocks}: the xy tile of a
+workgroup (tile_x x block/tile_x columns), the number of z-planes each tile
+marches, the number of steps captured in one hipGraph, and an optional cap on
+resident workgroups.  Fields are bit-identical for every tuning (each cell's
+arithmetic does not depend on the tiling), so the tuner is free to pick the
+fastest.  It times candidate tunings on a scratch plan of the same shape
+(same grid, materials, sources and diagnostics; its own arena), keeps the
+fastest, and caches the choice per shape bin in a JSON file.
+"""
+import itertools
+import json
+import os
+import time
+
+CACHE_VERSION = 3
+
+
+def _cache_path():
+    base = os.environ.get("FDTD_TUNE_CACHE")
+    if base:
+        return base
+    root = os.environ.get("XDG_CACHE_HOME", os.path.join(os.path.expanduser("~"), ".cache"))
+    return os.path.join(root, "paper_0802_3775_amd", "tune.json")
+
+
+def shape_key(cfg):
+    """Shape bin: grid extents, boundary/CPML layout, gain and flux presence."""
+    g = cfg["grid"]
+    gain = any(m.get("gain") for m in cfg["materials"])
+    nflux = sum(1 for f in cfg.get("flux", []) if len(f.get("freqs", ())) > 0)
+    return "v%d|n=%s|per=%s|pml=%s,%s|gain=%d|flux=%d" % (
+        CACHE_VERSION, tuple(g["n"]), tuple(g.get("periodic", (1, 1, 1))), tuple(g.get("pml_lo", (0, 0, 0))),
+        tuple(g.get("pml_hi", (0, 0, 0))), int(gain), nflux)
+
+
+def candidates(cfg, quick=False):
+    nx, ny, nz = cfg["grid"]["n"]
+    tiles = [(16, 256), (32, 256), (64, 256), (16, 128), (32, 128)]
+    if quick:
+        tiles = [(16, 256), (32, 256), (64, 256)]
+    chunks = [1, 2, 4, 8, 16, 32]
+    out = []
+    for (tx, b), z in itertools.product(tiles, chunks):
+        if tx > 16 and tx > 2 * nx:
+            continue
+        if z > nz:
+            continue
+        out.append({"tile_x": tx, "block": b, "zchunk": z, "max_blocks": 0})
+    return out
+
+
+def _load_cache():
+    try:
+        with open(_cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save_cache(cache):
+    path = _cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def _time_candidate(cfg, tune, steps, warm):
+    import torch
+    from . import fdtd
+    plan = fdtd.Plan(cfg, max_steps=warm + steps, tuning=tune)
+    try:
+        plan.step(warm)
+        torch.cuda.synchronize()
+        ms = plan.time_steps(steps)
+        return ms / steps
+    finally:
+        plan.close()
+
+
+def autotune(cfg, budget_s=20.0, quick=False, use_cache=True, graph_steps=(50, 200), verbose=False):
+    """Return the fastest tuning for this configuration's shape (cached)."""
+    key = shape_key(cfg)
+    cache = _load_cache() if use_cache else {}
+    if key in cache:
+        return dict(cache[key]["tuning"])
+    ncell = cfg["grid"]["n"][0] * cfg["grid"]["n"][1] * cfg["grid"]["n"][2]
+    # steps per trial: about 2e8 cell-updates, at least 8
+    steps = int(max(8, min(200, 2e8 / max(ncell, 1))))
+    t_end = time.perf_counter() + budget_s
+    best, best_ms = None, float("inf")
+    results = []
+    for cand in candidates(cfg, quick=quick):
+        if time.perf_counter() > t_end and best is not None:
+            break
+        tune = dict(cand, graph_steps=min(graph_steps))
+        ms = _time_candidate(dict(cfg, steps=steps + 4), tune, steps, 4)
+        results.append((ms, tune))
+        if verbose:
+            print("tune %s: %.2f us/step" % (tune, ms * 1e3), flush=True)
+        if ms < best_ms:
+            best, best_ms = tune, ms
+    # graph length: longer graphs amortise launches; keep the faster
+    for gsteps in graph_steps:
+        if gsteps == best["graph_steps"]:
+            continue
+        n = max(steps, gsteps)
+        tune = dict(best, graph_steps=gsteps)
+        ms = _time_candidate(dict(cfg, steps=n + 4), tune, n, 4)
+        if verbose:
+            print("tune %s: %.2f us/step" % (tune, ms * 1e3), flush=True)
+        if ms < best_ms:
+            best, best_ms = tune, ms
+    if use_cache:
+        cache = _load_cache()
+        cache[key] = {"tuning": best, "us_per_step": best_ms * 1e3, "trials": len(results)}
+        _save_cache(cache)
+    return dict(best)
+
+
+def common_tuning(cfgs, budget_s=30.0, verbose=False):
+    """One tuning for a batch (members share tile_x and block): tune the largest
+    member, keep its tile shape for all."""
+    big = max(cfgs, key=lambda c: c["grid"]["n"][0] * c["grid"]["n"][1] * c["grid"]["n"][2])
+    return autotune(big, budget_s=budget_s, verbose=verbose)
