@@ -36,10 +36,47 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def headline_config(steps):
+def headline_config(steps, workload="slab"):
     from paper_0802_3775_amd import workloads as W
+    if workload == "big":
+        return W.slab(delta=0.05, seed=4242, res=32, cells=(10, 10, 10), steps=steps, nf=0)
     return W.slab(delta=0.05, seed=13, res=20, cells=(4, 4, 8), steps=steps, nf=100, decim=8,
                   energy_interval=100)
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "fd_internal.h"):
+        with open(os.path.join(ROOT, "paper_0802_3775_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(workload, kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter runs (FETCH_SIZE,
+    WRITE_SIZE, each scaled by the same counter's reading for a copy of known
+    size), or None if the kernel source changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get("%s/%s" % (workload, kernel))
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
+def copy_calibration():
+    """A device copy of exactly 1 GiB (read 1 GiB, write 1 GiB) for scaling the
+    HBM byte counters in profiled runs."""
+    import torch
+    x = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
 
 
 def kernel_table(plan, nsteps):
@@ -75,9 +112,13 @@ def timed_run(plan, steps):
 def measure_plain(args):
     from paper_0802_3775_amd import fdtd, tune
     total = args.warmup + args.steps + args.kernel_steps
-    cfg = headline_config(total)
+    cfg = headline_config(total, args.workload)
     t0 = time.perf_counter()
-    tuning = tune.autotune(dict(cfg), budget_s=args.tune_seconds)
+    if args.tuning:
+        tx, blk, zc, gs = (int(v) for v in args.tuning.split(","))
+        tuning = {"tile_x": tx, "block": blk, "zchunk": zc, "graph_steps": gs, "max_blocks": 0}
+    else:
+        tuning = tune.autotune(dict(cfg), budget_s=args.tune_seconds)
     log("plain: tuning %s (%.1f s)" % (tuning, time.perf_counter() - t0))
     plan = fdtd.Plan(cfg, max_steps=total, tuning=tuning)
     log("plain: grid %s, %d cells, warmup %d" % (cfg["grid"]["n"], plan.ncell, args.warmup))
@@ -110,20 +151,25 @@ def measure_big(args):
             "cells": n, "steps_timed": steps, "cell_updates_per_s": n * steps / wall, "tuning": tuning,
             "roofline": {"bound": "hbm", "kernel": "step_plain", "achieved": k["GBps"], "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": k["GBps"] / HBM_PEAK_GBS, "avg_launch_ms": k["avg_ms"],
-                         "alg_bytes_per_launch": k["alg_bytes"]},
+                         "alg_bytes_per_launch": k["alg_bytes"],
+                         "traffic": recorded_traffic("big", "step_plain")},
             "kernels": kern}
 
 
 def measure_cpu(cfg, budget_s):
+    """The FP64 oracle on the host cores, stepped in chunks until about budget_s
+    seconds of stepping have been timed (the first steps are left out)."""
     from oracle import oracle as O
-    sim = O.OracleSim(dict(cfg, steps=100000), max_steps=100000)
-    t0 = time.perf_counter()
+    sim = O.OracleSim(dict(cfg, steps=1000000), max_steps=1000000)
     sim.step(2)
-    per = (time.perf_counter() - t0) / 2
-    n = max(2, int(budget_s / max(per, 1e-6)))
-    t0 = time.perf_counter()
-    sim.step(n)
-    dt = time.perf_counter() - t0
+    n, dt = 0, 0.0
+    chunk = 4
+    while dt < budget_s:
+        t0 = time.perf_counter()
+        sim.step(chunk)
+        dt += time.perf_counter() - t0
+        n += chunk
+        chunk = min(64, chunk * 2)
     ncell = cfg["grid"]["n"][0] * cfg["grid"]["n"][1] * cfg["grid"]["n"][2]
     return {"value": ncell * n / dt, "unit": "cell-updates/s", "cores": O.threads(), "kind": "oracle",
             "sample": "steps 3..%d of the headline slab run (full %dx%dx%d grid, FP64 oracle), %.1f s"
@@ -222,6 +268,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tune-seconds", type=float, default=15.0)
     ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--workload", choices=("slab", "big"), default="slab",
+                    help="headline slab (default) or the 320^3 grid (profiling)")
+    ap.add_argument("--tuning", default="", help="fixed tile_x,block,zchunk,graph_steps (skip the autotuner)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 1 GiB device copy first (counter calibration in profiled runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); the multi-GPU "
@@ -229,6 +280,8 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
+    if args.copy_calibration:
+        copy_calibration()
     plain = measure_plain(args)
     value = plain["ncell"] * args.steps / plain["wall"]
     dom = plain["kernels"][plain["dominant"]]
@@ -245,14 +298,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "disordered inverted-opal slab, 4x4x8 cubic cells at 20 cells/a "
-                               "(80x80x224 with 1a margins and 12-cell z-CPML), delta=0.05a, 30 fs "
-                               "plane-wave pulse, probe + T(t) + 100-frequency DFT flux on 2 planes, "
-                               "energy every 100 steps",
+        "config": {"workload": ("disordered inverted-opal slab, 4x4x8 cubic cells at 20 cells/a "
+                                "(80x80x224 with 1a margins and 12-cell z-CPML), delta=0.05a, 30 fs "
+                                "plane-wave pulse, probe + T(t) + 100-frequency DFT flux on 2 planes, "
+                                "energy every 100 steps") if args.workload == "slab" else
+                               "linear slab 10x10x10 cubic cells at 32 cells/a (320x320x408, z-CPML)",
                    "cells": plain["ncell"], "run_steps": 20000, "tuning": plain["tuning"]},
         "roofline": {"bound": "hbm", "kernel": plain["dominant"], "achieved": dom["GBps"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["GBps"] / HBM_PEAK_GBS,
-                     "traffic": None, "alg_bytes_per_launch": dom["alg_bytes"],
+                     "traffic": recorded_traffic(args.workload, plain["dominant"]),
+                     "alg_bytes_per_launch": dom["alg_bytes"],
                      "avg_launch_ms": dom["avg_ms"]},
         "kernels": plain["kernels"],
     }
