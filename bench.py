@@ -81,22 +81,20 @@ def copy_calibration():
 
 def kernel_table(plan, nsteps):
     """Per kernel class: average launch duration (hipEvents around each launch on
-    the launch stream) and algorithmic bytes per launch."""
+    the launch stream) and the algorithmic bytes of one launch (libfdtd counts
+    them per cell: 49 B, +32 B per CPML slab axis, +84 B per gain cell; DFT
+    128 B per plane point and frequency)."""
     from paper_0802_3775_amd import fdtd
     ms, cnt = plan.time_kernels(nsteps)
     cells = plan.class_cells()
-    nf = max(plan.nf) if plan.nf else 0
+    nbytes = plan.class_bytes()
     kern = {}
     for c, name in enumerate(fdtd.Plan.CLASSES):
         if cnt[c] == 0:
             continue
         avg = ms[c] / cnt[c]
-        if name == "dft":
-            nbytes = cells[c] * nf * 4 * 16 * 2      # 4 complex FP64 accumulators, read + write
-        else:
-            nbytes = cells[c] * B_ALG_LINEAR        # CPML psi and gain bytes not counted (lower bound)
         kern[name] = {"avg_ms": avg, "launches": int(cnt[c]), "cells": int(cells[c]),
-                      "alg_bytes": float(nbytes), "GBps": nbytes / (avg * 1e-3) / 1e9}
+                      "alg_bytes": float(nbytes[c]), "GBps": nbytes[c] / (avg * 1e-3) / 1e9}
     return kern
 
 
@@ -115,8 +113,9 @@ def measure_plain(args):
     cfg = headline_config(total, args.workload)
     t0 = time.perf_counter()
     if args.tuning:
-        tx, blk, zc, gs = (int(v) for v in args.tuning.split(","))
-        tuning = {"tile_x": tx, "block": blk, "zchunk": zc, "graph_steps": gs, "max_blocks": 0}
+        v = [int(q) for q in args.tuning.split(",")] + [1, 0]
+        tuning = {"tile_x": v[0], "block": v[1], "zchunk": v[2], "graph_steps": v[3], "max_blocks": 0,
+                  "merge": v[4], "parallel": v[5]}
     else:
         tuning = tune.autotune(dict(cfg), budget_s=args.tune_seconds)
     log("plain: tuning %s (%.1f s)" % (tuning, time.perf_counter() - t0))
@@ -146,13 +145,14 @@ def measure_big(args):
     kern = kernel_table(plan, 100)
     n = plan.ncell
     plan.close()
-    k = kern["step_plain"]
+    kname = max(kern, key=lambda q: kern[q]["avg_ms"] * kern[q]["launches"])
+    k = kern[kname]
     return {"workload": "linear slab 10x10x10 cubic cells at 32 cells/a (320x320x408, z-CPML)",
             "cells": n, "steps_timed": steps, "cell_updates_per_s": n * steps / wall, "tuning": tuning,
-            "roofline": {"bound": "hbm", "kernel": "step_plain", "achieved": k["GBps"], "peak": HBM_PEAK_GBS,
+            "roofline": {"bound": "hbm", "kernel": kname, "achieved": k["GBps"], "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": k["GBps"] / HBM_PEAK_GBS, "avg_launch_ms": k["avg_ms"],
                          "alg_bytes_per_launch": k["alg_bytes"],
-                         "traffic": recorded_traffic("big", "step_plain")},
+                         "traffic": recorded_traffic("big", kname)},
             "kernels": kern}
 
 
@@ -243,7 +243,8 @@ def measure_serving(args, plain_rate):
     cap = plain_rate / (work / len(base))          # requests per second, sequential estimate
     lam = 0.9 * cap
     reqs = [dict(r, arrival=r["arrival"] / lam) for r in base]
-    tuning = {"block": 256, "tile_x": 16, "zchunk": 2, "graph_steps": 100, "max_blocks": 0}
+    tuning = {"block": 256, "tile_x": 16, "zchunk": 2, "graph_steps": 100, "max_blocks": 0, "merge": 1,
+              "parallel": 0}
     backend = serve.GpuBackend(tuning)
     free, _ = torch.cuda.mem_get_info()
     srv = serve.Server(backend, budget_bytes=int(0.5 * free), chunk=400)
@@ -270,7 +271,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--workload", choices=("slab", "big"), default="slab",
                     help="headline slab (default) or the 320^3 grid (profiling)")
-    ap.add_argument("--tuning", default="", help="fixed tile_x,block,zchunk,graph_steps (skip the autotuner)")
+    ap.add_argument("--tuning", default="", help="fixed tile_x,block,zchunk,graph_steps[,merge,parallel] (skip the autotuner)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration in profiled runs)")
     args = ap.parse_args()

@@ -124,9 +124,14 @@ typedef struct {
    thread (64..256, multiple of 64); tile_x: tile width along x (16, 32 or 64;
    the tile is tile_x x block/tile_x columns); zchunk: z-planes per tile (>= 1);
    graph_steps: steps captured per hipGraph (0: no graph); max_blocks: upper
-   bound on resident workgroups for the tile loop (0: one per tile). */
+   bound on resident workgroups for the tile loop (0: one per tile).
+   merge: 0 one launch per tile class; 1 tiles without CPML run with the z-CPML
+   kernel of the same gain flag (one launch for both); 2 every tile runs with the
+   plan's most general kernel (one launch per step).  parallel: 1 makes the
+   launches of a step parallel branches of the captured graph, 0 keeps them in
+   stream order.  Results do not depend on any of these. */
 typedef struct {
-  int32_t block, zchunk, graph_steps, max_blocks, tile_x;
+  int32_t block, zchunk, graph_steps, max_blocks, tile_x, merge, parallel;
 } fdtd_tuning;
 
 const char* fdtd_last_error(void);
@@ -213,6 +218,13 @@ int fdtd_batch_time_steps(fdtd_batch* b, int64_t n, void* stream, double* ms);
    running-DFT update.  cells[c] = cells covered by the plan's tiles of class c
    (c < 6), cells[6] = flux-plane points (7 entries). */
 int fdtd_class_cells(const fdtd_plan* p, int64_t* cells /* 7 */);
+/* Algorithmic bytes one launch of each class moves (7 entries): 49 per cell
+   (E, H and the material index in, E and H out) + 32 per cell and CPML axis
+   whose slab holds it (2 E-side psi read+write, 2 H-side psi read + write) + 84
+   per gain cell (P^n, P^{n-1}, populations in; P^{n+1}, populations out); the
+   DFT entry is the bytes of one call (4 complex FP64 accumulators read + write
+   per plane point and frequency). */
+int fdtd_class_bytes(const fdtd_plan* p, double* bytes /* 7 */);
 /* Advance n steps without graphs, bracketing every kernel launch with a pair of
    hipEvents on the stream; ms[c] = summed milliseconds and launches[c] = number of
    launches of class c (7 entries each, as above). */

@@ -98,6 +98,29 @@ struct Fork {
   }
 };
 
+// Split a tile list into 8 contiguous parts of about equal cost, one per XCD;
+// *grid = 8 x the longest part (the kernel's workgroup count).
+fd_xcd xcd_partition(const std::vector<double>& cost, int* grid) {
+  fd_xcd r{};
+  double total = 0.0;
+  for (double c : cost) total += c;
+  size_t idx = 0;
+  double cum = 0.0;
+  int longest = 0;
+  for (int x = 0; x < 8; ++x) {
+    r.start[x] = (int)idx;
+    const double target = total * (x + 1) / 8.0;
+    while (idx < cost.size() && (x == 7 || cum + 0.5 * cost[idx] <= target)) {
+      cum += cost[idx];
+      ++idx;
+    }
+    r.count[x] = (int)idx - r.start[x];
+    longest = std::max(longest, r.count[x]);
+  }
+  *grid = 8 * std::max(longest, 1);
+  return r;
+}
+
 }  // namespace
 
 struct fdtd_plan {
@@ -114,7 +137,7 @@ struct fdtd_plan {
   std::vector<std::array<int, 4>> probes;
   std::vector<Flux> flux;
   int ke = 0;
-  fdtd_tuning tune{256, 4, 64, 0, 32};
+  fdtd_tuning tune{256, 4, 64, 0, 32, 1, 0};
   // bound state
   bool bound = false;
   uint8_t* arena = nullptr;
@@ -126,6 +149,9 @@ struct fdtd_plan {
   int64_t step = 0;
   int nblk = 0, ntiles = 0;
   std::vector<fd_tile> tiles[FD_NCLASS];
+  std::vector<double> tcost[FD_NCLASS];  // algorithmic bytes of each tile (XCD balancing)
+  fd_xcd part[FD_NCLASS] = {};
+  int pgrid[FD_NCLASS] = {};
   fd_tile* dtiles[FD_NCLASS] = {};
   std::vector<fd_dft_tile> dft;
   fd_dft_tile* ddft = nullptr;
@@ -141,9 +167,12 @@ struct fdtd_batch {
   std::vector<fdtd_plan*> plans;
   int block = 256;
   int tile_x = 32;
+  int parallel = 0;
   int max_blocks = 0;
   int graph_steps = 0;
   std::vector<fd_tile> tiles[FD_NCLASS];
+  fd_xcd part[FD_NCLASS] = {};
+  int pgrid[FD_NCLASS] = {};
   std::vector<fd_dft_tile> dft;
   int maxnf = 0;
   void* dmem = nullptr;  // tile tables + desc pointer list (setup-time allocation)
@@ -379,9 +408,9 @@ T* at(fdtd_plan* p, size_t off) {
 // Enqueue one step (batch-relative index s) of the given tile sets.
 // Enqueue one step (batch-relative index s) of the given tile sets.  With a
 // Fork (graph capture) the non-empty classes become parallel graph branches.
-int enqueue_step(fd_tile* const dtiles[FD_NCLASS], const std::vector<fd_tile>* tiles, int tile_x, int block,
-                 int max_blocks, const fd_dft_tile* ddft, int ndft, int maxnf, bool dft_due, int s, hipStream_t st,
-                 Fork* fk) {
+int enqueue_step(fd_tile* const dtiles[FD_NCLASS], const std::vector<fd_tile>* tiles, const fd_xcd* part,
+                 const int* pgrid, int tile_x, int block, int max_blocks, const fd_dft_tile* ddft, int ndft,
+                 int maxnf, bool dft_due, int s, hipStream_t st, Fork* fk) {
   int used[FD_NCLASS], nused = 0;
   for (int c = 0; c < FD_NCLASS; ++c)
     if (!tiles[c].empty()) used[nused++] = c;
@@ -390,13 +419,14 @@ int enqueue_step(fd_tile* const dtiles[FD_NCLASS], const std::vector<fd_tile>* t
   for (int u = 0; u < nused; ++u) {
     const int c = used[u];
     const int nt = (int)tiles[c].size();
-    const int grid = max_blocks > 0 ? std::min(nt, max_blocks) : nt;
+    const int grid = max_blocks > 0 ? std::min(nt, max_blocks) : pgrid[c];
+    const fd_xcd* pc = max_blocks > 0 ? nullptr : &part[c];
     hipStream_t on = st;
     if (par && u > 0) {
       on = fk->side[c];
       HIPCHK(hipStreamWaitEvent(on, fk->fork, 0));
     }
-    HIPCHK(fd_launch_step(c, dtiles[c], nt, tile_x, block, grid, s, on));
+    HIPCHK(fd_launch_step(c, dtiles[c], nt, tile_x, block, grid, s, pc, on));
     if (par && u > 0) HIPCHK(hipEventRecord(fk->join[c], on));
   }
   if (par)
@@ -420,8 +450,9 @@ int64_t plan_phase_key(const fdtd_plan* p, int64_t n0) {
 
 int plan_enqueue(fdtd_plan* p, int64_t n, hipStream_t st, Fork* fk) {
   for (int64_t s = 0; s < n; ++s) {
-    const int r = enqueue_step(p->dtiles, p->tiles, p->tune.tile_x, p->tune.block, p->tune.max_blocks, p->ddft,
-                               (int)p->dft.size(), p->maxnf, plan_dft_due(p, p->step + s), (int)s, st, fk);
+    const int r = enqueue_step(p->dtiles, p->tiles, p->part, p->pgrid, p->tune.tile_x, p->tune.block,
+                               p->tune.max_blocks, p->ddft, (int)p->dft.size(), p->maxnf,
+                               plan_dft_due(p, p->step + s), (int)s, st, fk);
     if (r) return r;
   }
   HIPCHK(fd_launch_advance_one(p->ddesc, n, st));
@@ -624,6 +655,7 @@ int fdtd_set_tuning(fdtd_plan* p, const fdtd_tuning* t) {
   if (t->zchunk < 1 || t->graph_steps < 0 || t->max_blocks < 0) return fail(FDTD_EINVAL, "bad tuning");
   if (t->tile_x != 16 && t->tile_x != 32 && t->tile_x != 64) return fail(FDTD_EINVAL, "tile_x must be 16, 32 or 64");
   if (t->block % t->tile_x != 0) return fail(FDTD_EINVAL, "block must be a multiple of tile_x");
+  if (t->merge < 0 || t->merge > 2 || t->parallel < 0 || t->parallel > 1) return fail(FDTD_EINVAL, "bad merge/parallel");
   p->tune = *t;
   return FDTD_OK;
 }
@@ -824,17 +856,31 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
   const auto chunks = z_chunks(p, std::max(1, p->tune.zchunk));
   std::vector<uint8_t> gain_mat(FD_MAXMAT, 0);
   for (size_t q = 0; q < p->mats.size(); ++q) gain_mat[q] = p->mats[q].gain ? 1 : 0;
-  // gain presence per (xy tile, z)
-  std::vector<uint8_t> blk_gain;
+  // gain cells per (xy tile, z)
+  std::vector<int> blk_gain;
   if (p->has_gain) {
     blk_gain.assign((size_t)p->nblk * p->g.nz, 0);
     for (int k = 0; k < p->g.nz; ++k)
       for (int j = 0; j < p->g.ny; ++j)
         for (int i = 0; i < p->g.nx; ++i)
           if (gain_mat[p->host_map[(size_t)k * plane + (size_t)j * p->g.nx + i]])
-            blk_gain[(size_t)k * p->nblk + (size_t)(j / TY) * ntx + i / TX] = 1;
+            blk_gain[(size_t)k * p->nblk + (size_t)(j / TY) * ntx + i / TX] += 1;
   }
-  for (int c = 0; c < FD_NCLASS; ++c) p->tiles[c].clear();
+  // cells of [a, b) inside the slabs of axis w
+  auto slab_count = [&](int w, int a, int b) {
+    if (!d.pml_t[w]) return 0;
+    const int n = w == 0 ? p->g.nx : (w == 1 ? p->g.ny : p->g.nz);
+    const int lo = std::max(0, std::min(b, d.pml_lo[w]) - a);
+    const int hi = std::max(0, b - std::max(a, n - d.pml_hi[w]));
+    return lo + hi;
+  };
+  for (int c = 0; c < FD_NCLASS; ++c) {
+    p->tiles[c].clear();
+    p->tcost[c].clear();
+  }
+  std::vector<fd_tile> all;
+  std::vector<double> tcost;
+  std::vector<std::pair<int, int>> tcls;
   int tidx = 0;
   for (const auto& ch : chunks) {
     for (int by = 0; by < nty; ++by)
@@ -855,14 +901,39 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
         const int iend = std::min(p->g.nx, t.i0 + TX), jend = std::min(p->g.ny, t.j0 + TY);
         if (d.pml_t[0] && (t.i0 - 1 < d.pml_lo[0] || iend > p->g.nx - d.pml_hi[0])) axes |= 1;
         if (d.pml_t[1] && (t.j0 - 1 < d.pml_lo[1] || jend > p->g.ny - d.pml_hi[1])) axes |= 2;
-        const int pml = axes == 0 ? 0 : (axes == 4 ? 1 : 2);
-        bool gain = false;
+        int pml = axes == 0 ? 0 : (axes == 4 ? 1 : 2);
+        long long ngain = 0;
         if (p->has_gain)
-          for (int k = t.k0; k < t.k1 && !gain; ++k) gain = blk_gain[(size_t)k * p->nblk + t.blk] != 0;
-        const int cls = pml + (gain ? 3 : 0);
-        p->tiles[cls].push_back(t);
+          for (int k = t.k0; k < t.k1; ++k) ngain += blk_gain[(size_t)k * p->nblk + t.blk];
+        const bool gain = ngain > 0;
+        const int nxt_ = iend - t.i0, nyt_ = jend - t.j0, nzt_ = t.k1 - t.k0;
+        const double slab_cells = (double)slab_count(0, t.i0, iend) * nyt_ * nzt_ +
+                                  (double)nxt_ * slab_count(1, t.j0, jend) * nzt_ +
+                                  (double)nxt_ * nyt_ * slab_count(2, t.k0, t.k1);
+        // algorithmic bytes of the tile, plus the plane below it that it also stages
+        tcost.push_back(49.0 * nxt_ * nyt_ * (nzt_ + 1) + 32.0 * slab_cells + 84.0 * (double)ngain);
+        tcls.push_back({pml, gain ? 1 : 0});
+        all.push_back(t);
       }
   }
+  // fold classes into fewer launches: a more general kernel is correct on a
+  // simpler tile (slab and gain tests are per cell / per plane at run time)
+  int max_pml = 0, any_gain = 0;
+  for (const auto& pc : tcls) {
+    max_pml = std::max(max_pml, pc.first);
+    any_gain |= pc.second;
+  }
+  for (size_t q = 0; q < all.size(); ++q) {
+    int pml = tcls[q].first, gain = tcls[q].second;
+    if (p->tune.merge >= 1 && pml == 0 && d.pml_t[2]) pml = 1;
+    if (p->tune.merge >= 2) {
+      pml = max_pml;
+      gain = any_gain;
+    }
+    p->tiles[pml + 3 * gain].push_back(all[q]);
+    p->tcost[pml + 3 * gain].push_back(tcost[q]);
+  }
+  for (int c = 0; c < FD_NCLASS; ++c) p->part[c] = xcd_partition(p->tcost[c], &p->pgrid[c]);
   for (int c = 0; c < FD_NCLASS; ++c) {
     p->dtiles[c] = at<fd_tile>(p, L.tiles[c]);
     if (!p->tiles[c].empty())
@@ -909,11 +980,15 @@ static int plan_step(fdtd_plan* p, int64_t n, hipStream_t st) {
       auto it = p->graphs.find(key);
       if (it == p->graphs.end()) {
         if (!p->cap) HIPCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
-        if (!p->fork) p->fork.reset(new Fork());
-        if (int rf = p->fork->init()) return rf;
+        Fork* fk = nullptr;
+        if (p->tune.parallel) {
+          if (!p->fork) p->fork.reset(new Fork());
+          if (int rf = p->fork->init()) return rf;
+          fk = p->fork.get();
+        }
         GraphEntry ge;
         HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
-        const int r = plan_enqueue(p, K, p->cap, p->fork.get());
+        const int r = plan_enqueue(p, K, p->cap, fk);
         hipGraph_t gr = nullptr;
         const hipError_t e = hipStreamEndCapture(p->cap, &gr);
         if (r) {
@@ -1122,6 +1197,35 @@ int fdtd_class_cells(const fdtd_plan* p, int64_t* cells) {
   return FDTD_OK;
 }
 
+int fdtd_class_bytes(const fdtd_plan* p, double* bytes) {
+  if (!p || !bytes) return fail(FDTD_EINVAL, "null argument");
+  if (!p->bound) return fail(FDTD_ESTATE, "plan not bound");
+  const int nx = p->g.nx, ny = p->g.ny, nz = p->g.nz;
+  const int TX = p->tune.tile_x, TY = p->tune.block / p->tune.tile_x;
+  auto in_slab = [&](int w, int q) {
+    const int n = w == 0 ? nx : (w == 1 ? ny : nz);
+    return pml_t(p, w) > 0 && (q < p->g.pml_lo[w] || q >= n - p->g.pml_hi[w]);
+  };
+  for (int c = 0; c < FD_NCLASS; ++c) {
+    double acc = 0.0;
+    for (const fd_tile& t : p->tiles[c])
+      for (int k = t.k0; k < t.k1; ++k)
+        for (int j = t.j0; j < std::min(ny, t.j0 + TY); ++j)
+          for (int i = t.i0; i < std::min(nx, t.i0 + TX); ++i) {
+            double b = 49.0;
+            b += 32.0 * ((in_slab(0, i) ? 1 : 0) + (in_slab(1, j) ? 1 : 0) + (in_slab(2, k) ? 1 : 0));
+            const uint8_t m = p->host_map[((size_t)k * ny + j) * nx + i];
+            if (p->mats[m].gain) b += 84.0;
+            acc += b;
+          }
+    bytes[c] = acc;
+  }
+  double dft = 0.0;
+  for (const Flux& f : p->flux) dft += 128.0 * (double)f.nf * nx * ny;
+  bytes[FD_NCLASS] = dft;
+  return FDTD_OK;
+}
+
 int fdtd_time_kernels(fdtd_plan* p, int64_t n, void* stream, double* ms, int64_t* launches) {
   if (!p || !ms || !launches) return fail(FDTD_EINVAL, "null argument");
   if (!p->bound) return fail(FDTD_ESTATE, "plan not bound");
@@ -1152,8 +1256,11 @@ int fdtd_time_kernels(fdtd_plan* p, int64_t n, void* stream, double* ms, int64_t
     for (int c = 0; c < FD_NCLASS; ++c) {
       const int nt = (int)p->tiles[c].size();
       if (nt == 0) continue;
-      const int grid = p->tune.max_blocks > 0 ? std::min(nt, p->tune.max_blocks) : nt;
-      const int r = record(c, [&]() { return fd_launch_step(c, p->dtiles[c], nt, p->tune.tile_x, p->tune.block, grid, (int)s, st); });
+      const int grid = p->tune.max_blocks > 0 ? std::min(nt, p->tune.max_blocks) : p->pgrid[c];
+      const fd_xcd* pc = p->tune.max_blocks > 0 ? nullptr : &p->part[c];
+      const int r = record(c, [&]() {
+        return fd_launch_step(c, p->dtiles[c], nt, p->tune.tile_x, p->tune.block, grid, (int)s, pc, st);
+      });
       if (r) { cleanup(); return r; }
     }
     if (plan_dft_due(p, p->step + s) && !p->dft.empty()) {
@@ -1201,13 +1308,19 @@ int fdtd_batch_create(fdtd_plan* const* plans, int32_t n, fdtd_batch** out) {
   b->plans.assign(plans, plans + n);
   b->block = block;
   b->tile_x = plans[0]->tune.tile_x;
+  b->parallel = plans[0]->tune.parallel;
   b->max_blocks = plans[0]->tune.max_blocks;
   b->graph_steps = plans[0]->tune.graph_steps;
+  std::vector<double> bcost[FD_NCLASS];
   for (fdtd_plan* p : b->plans) {
-    for (int c = 0; c < FD_NCLASS; ++c) b->tiles[c].insert(b->tiles[c].end(), p->tiles[c].begin(), p->tiles[c].end());
+    for (int c = 0; c < FD_NCLASS; ++c) {
+      b->tiles[c].insert(b->tiles[c].end(), p->tiles[c].begin(), p->tiles[c].end());
+      bcost[c].insert(bcost[c].end(), p->tcost[c].begin(), p->tcost[c].end());
+    }
     b->dft.insert(b->dft.end(), p->dft.begin(), p->dft.end());
     b->maxnf = std::max(b->maxnf, p->maxnf);
   }
+  for (int c = 0; c < FD_NCLASS; ++c) b->part[c] = xcd_partition(bcost[c], &b->pgrid[c]);
   size_t bytes = 0;
   size_t off_t[FD_NCLASS];
   for (int c = 0; c < FD_NCLASS; ++c) {
@@ -1266,8 +1379,8 @@ static bool batch_dft_due(const fdtd_batch* b, int64_t s) {
 
 static int batch_enqueue(fdtd_batch* b, int64_t n, hipStream_t st, Fork* fk) {
   for (int64_t s = 0; s < n; ++s) {
-    const int r = enqueue_step(b->dtiles, b->tiles, b->tile_x, b->block, b->max_blocks, b->ddft, (int)b->dft.size(),
-                               b->maxnf, batch_dft_due(b, s), (int)s, st, fk);
+    const int r = enqueue_step(b->dtiles, b->tiles, b->part, b->pgrid, b->tile_x, b->block, b->max_blocks, b->ddft,
+                               (int)b->dft.size(), b->maxnf, batch_dft_due(b, s), (int)s, st, fk);
     if (r) return r;
   }
   HIPCHK(fd_launch_advance(b->ddescs, (int)b->plans.size(), n, st));
@@ -1287,11 +1400,15 @@ static int batch_step(fdtd_batch* b, int64_t n, hipStream_t st) {
       auto it = b->graphs.find(key);
       if (it == b->graphs.end()) {
         if (!b->cap) HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
-        if (!b->fork) b->fork.reset(new Fork());
-        if (int rf = b->fork->init()) return rf;
+        Fork* fk = nullptr;
+        if (b->parallel) {
+          if (!b->fork) b->fork.reset(new Fork());
+          if (int rf = b->fork->init()) return rf;
+          fk = b->fork.get();
+        }
         GraphEntry ge;
         HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-        const int r = batch_enqueue(b, K, b->cap, b->fork.get());
+        const int r = batch_enqueue(b, K, b->cap, fk);
         hipGraph_t gr = nullptr;
         const hipError_t e = hipStreamEndCapture(b->cap, &gr);
         if (r) {

@@ -97,8 +97,16 @@ enum {
 };
 
 // Launchers (kernels.hip).
+// A launch's tile list split into 8 contiguous parts of about equal cost, one
+// per XCD (workgroup w runs on XCD w mod 8).  count[x] = 0 parts are allowed.
+struct fd_xcd {
+  int start[8];
+  int count[8];
+};
+
+// part == nullptr: grid-stride loop over the tiles with the plain XCD renumbering
 hipError_t fd_launch_step(int cls, const fd_tile* tiles, int ntiles, int tile_x, int block, int grid,
-                          int s, hipStream_t st);
+                          int s, const fd_xcd* part, hipStream_t st);
 hipError_t fd_launch_dft(const fd_dft_tile* tiles, int ntiles, int maxnf, int block, int s,
                          hipStream_t st);
 hipError_t fd_launch_advance(fd_desc* const* descs, int n, long long k, hipStream_t st);

@@ -616,9 +616,21 @@ __device__ __forceinline__ int xcd_tile(int w, int n) {
   return x * q + (x < r ? x : r) + s;
 }
 
+// With a cost-balanced partition (use_part), workgroup w takes tile
+// part.start[x] + w/8 of XCD x = w mod 8, or nothing if that part is shorter;
+// otherwise the workgroups loop over the renumbered tile list.
 template <int TX, int PM, bool GAIN>
-__global__ __launch_bounds__(FD_MAXBLOCK) void step_kernel(const fd_tile* __restrict__ tiles, int ntiles, int s) {
+__global__ __launch_bounds__(FD_MAXBLOCK) void step_kernel(const fd_tile* __restrict__ tiles, int ntiles, int s,
+                                                           fd_xcd part, int use_part) {
   __shared__ Lds<TX> lds;
+  if (use_part) {
+    const int x = (int)blockIdx.x % 8, q = (int)blockIdx.x / 8;
+    if (q < part.count[x]) {
+      const fd_tile tl = tiles[part.start[x] + q];
+      run_tile<TX, PM, GAIN>(tl, s, lds);
+    }
+    return;
+  }
   for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
     const fd_tile tl = tiles[xcd_tile(w, ntiles)];
     run_tile<TX, PM, GAIN>(tl, s, lds);
@@ -777,28 +789,43 @@ __global__ void init_pop_kernel(const uint8_t* __restrict__ map, const float* __
 }  // namespace
 
 template <int TX>
-static hipError_t launch_tx(int cls, const fd_tile* tiles, int ntiles, int block, int grid, int s, hipStream_t st) {
+static hipError_t launch_tx(int cls, const fd_tile* tiles, int ntiles, int block, int grid, int s,
+                            const fd_xcd& part, int use, hipStream_t st) {
   switch (cls) {
-    case FD_CLASS_PLAIN: step_kernel<TX, 0, false><<<grid, block, 0, st>>>(tiles, ntiles, s); break;
-    case FD_CLASS_PMLZ: step_kernel<TX, 4, false><<<grid, block, 0, st>>>(tiles, ntiles, s); break;
-    case FD_CLASS_PML: step_kernel<TX, 7, false><<<grid, block, 0, st>>>(tiles, ntiles, s); break;
-    case FD_CLASS_GAIN: step_kernel<TX, 0, true><<<grid, block, 0, st>>>(tiles, ntiles, s); break;
-    case FD_CLASS_PMLZ_GAIN: step_kernel<TX, 4, true><<<grid, block, 0, st>>>(tiles, ntiles, s); break;
-    case FD_CLASS_PML_GAIN: step_kernel<TX, 7, true><<<grid, block, 0, st>>>(tiles, ntiles, s); break;
+    case FD_CLASS_PLAIN: step_kernel<TX, 0, false><<<grid, block, 0, st>>>(tiles, ntiles, s, part, use); break;
+    case FD_CLASS_PMLZ: step_kernel<TX, 4, false><<<grid, block, 0, st>>>(tiles, ntiles, s, part, use); break;
+    case FD_CLASS_PML: step_kernel<TX, 7, false><<<grid, block, 0, st>>>(tiles, ntiles, s, part, use); break;
+    case FD_CLASS_GAIN: step_kernel<TX, 0, true><<<grid, block, 0, st>>>(tiles, ntiles, s, part, use); break;
+    case FD_CLASS_PMLZ_GAIN: step_kernel<TX, 4, true><<<grid, block, 0, st>>>(tiles, ntiles, s, part, use); break;
+    case FD_CLASS_PML_GAIN: step_kernel<TX, 7, true><<<grid, block, 0, st>>>(tiles, ntiles, s, part, use); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t fd_launch_step(int cls, const fd_tile* tiles, int ntiles, int tile_x, int block, int grid, int s,
-                          hipStream_t st) {
+                          const fd_xcd* part, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
   if (block < 64 || block > FD_MAXBLOCK || (block & 63) != 0 || grid <= 0 || block % tile_x != 0)
     return hipErrorInvalidValue;
+  fd_xcd pz{};
+  int use = 0;
+  if (part) {
+    // every part must lie inside the list and the grid must cover the longest one
+    int longest = 0;
+    for (int x = 0; x < 8; ++x) {
+      if (part->start[x] < 0 || part->count[x] < 0 || part->start[x] + part->count[x] > ntiles)
+        return hipErrorInvalidValue;
+      longest = part->count[x] > longest ? part->count[x] : longest;
+    }
+    if (grid < 8 * longest) return hipErrorInvalidValue;
+    pz = *part;
+    use = 1;
+  }
   switch (tile_x) {
-    case 16: return launch_tx<16>(cls, tiles, ntiles, block, grid, s, st);
-    case 32: return launch_tx<32>(cls, tiles, ntiles, block, grid, s, st);
-    case 64: return launch_tx<64>(cls, tiles, ntiles, block, grid, s, st);
+    case 16: return launch_tx<16>(cls, tiles, ntiles, block, grid, s, pz, use, st);
+    case 32: return launch_tx<32>(cls, tiles, ntiles, block, grid, s, pz, use, st);
+    case 64: return launch_tx<64>(cls, tiles, ntiles, block, grid, s, pz, use, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -56,7 +56,8 @@ class OpalDesc(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("zchunk", C.c_int32), ("graph_steps", C.c_int32),
-                ("max_blocks", C.c_int32), ("tile_x", C.c_int32)]
+                ("max_blocks", C.c_int32), ("tile_x", C.c_int32), ("merge", C.c_int32),
+                ("parallel", C.c_int32)]
 
 
 # Every exported symbol of include/fdtd.h with its ctypes signature.
@@ -97,6 +98,7 @@ SIGNATURES = {
     "fdtd_time_steps": ([VP, C.c_int64, VP, P(C.c_double)], C.c_int),
     "fdtd_batch_time_steps": ([VP, C.c_int64, VP, P(C.c_double)], C.c_int),
     "fdtd_class_cells": ([VP, P(C.c_int64)], C.c_int),
+    "fdtd_class_bytes": ([VP, P(C.c_double)], C.c_int),
     "fdtd_time_kernels": ([VP, C.c_int64, VP, P(C.c_double), P(C.c_int64)], C.c_int),
 }
 
@@ -166,7 +168,8 @@ def _material(m):
 
 
 def default_tuning(cfg=None):
-    return {"block": 256, "zchunk": 4, "graph_steps": 64, "max_blocks": 0, "tile_x": 32}
+    return {"block": 256, "zchunk": 4, "graph_steps": 64, "max_blocks": 0, "tile_x": 32, "merge": 1,
+            "parallel": 0}
 
 
 class Plan:
@@ -221,7 +224,8 @@ class Plan:
             _check(lib().fdtd_set_energy_interval(self.h, int(cfg["energy_interval"])))
         t = dict(default_tuning(cfg))
         t.update(tuning or {})
-        tu = Tuning(t["block"], t["zchunk"], t["graph_steps"], t["max_blocks"], t["tile_x"])
+        tu = Tuning(t["block"], t["zchunk"], t["graph_steps"], t["max_blocks"], t["tile_x"], t["merge"],
+                    t["parallel"])
         _check(lib().fdtd_set_tuning(self.h, C.byref(tu)))
         self.tuning = t
         self.max_steps = int(max_steps if max_steps is not None else cfg.get("steps", 0))
@@ -271,6 +275,11 @@ class Plan:
     def class_cells(self):
         out = np.zeros(7, dtype=np.int64)
         _check(lib().fdtd_class_cells(self.h, _ptr(out, C.c_int64)))
+        return out
+
+    def class_bytes(self):
+        out = np.zeros(7, dtype=np.float64)
+        _check(lib().fdtd_class_bytes(self.h, _ptr(out, C.c_double)))
         return out
 
     def time_kernels(self, n, stream=None):

@@ -1,9 +1,10 @@
 """Autotuner for the launch configuration of a plan.
 
-A tuning is {tile_x, block, zchunk, graph_steps, max_blocks}: the xy tile of a
-workgroup (tile_x x block/tile_x columns), the number of z-planes each tile
-marches, the number of steps captured in one hipGraph, and an optional cap on
-resident workgroups.  Fields are bit-identical for every tuning (each cell's
+A tuning is {tile_x, block, zchunk, graph_steps, max_blocks, merge, parallel}:
+the xy tile of a workgroup (tile_x x block/tile_x columns), the number of
+z-planes each tile marches, the number of steps captured in one hipGraph, an
+optional cap on resident workgroups, how tile classes are folded into launches
+and whether a step's launches are parallel graph branches.  Fields are bit-identical for every tuning (each cell's
 arithmetic does not depend on the tiling), so the tuner is free to pick the
 fastest.  It times candidate tunings on a scratch plan of the same shape
 (same grid, materials, sources and diagnostics; its own arena), keeps the
@@ -14,7 +15,7 @@ import json
 import os
 import time
 
-CACHE_VERSION = 3
+CACHE_VERSION = 4
 
 
 def _cache_path():
@@ -47,7 +48,7 @@ def candidates(cfg, quick=False):
             continue
         if z > nz:
             continue
-        out.append({"tile_x": tx, "block": b, "zchunk": z, "max_blocks": 0})
+        out.append({"tile_x": tx, "block": b, "zchunk": z, "max_blocks": 0, "merge": 1, "parallel": 0})
     return out
 
 
@@ -102,6 +103,16 @@ def autotune(cfg, budget_s=20.0, quick=False, use_cache=True, graph_steps=(50, 2
         tune = dict(cand, graph_steps=min(graph_steps))
         ms = _time_candidate(dict(cfg, steps=steps + 4), tune, steps, 4)
         results.append((ms, tune))
+        if verbose:
+            print("tune %s: %.2f us/step" % (tune, ms * 1e3), flush=True)
+        if ms < best_ms:
+            best, best_ms = tune, ms
+    # launch grouping: classes folded into fewer launches, or launches as
+    # parallel graph branches
+    base = dict(best)
+    for merge, par in ((0, 0), (0, 1), (1, 1), (2, 0)):
+        tune = dict(base, merge=merge, parallel=par)
+        ms = _time_candidate(dict(cfg, steps=steps + 4), tune, steps, 4)
         if verbose:
             print("tune %s: %.2f us/step" % (tune, ms * 1e3), flush=True)
         if ms < best_ms:
