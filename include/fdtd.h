@@ -122,7 +122,9 @@ typedef struct {
 
 /* Launch tuning (per plan).  block: threads per workgroup, one (i,j) column per
    thread (64..256, multiple of 64); tile_x: tile width along x (16, 32 or 64;
-   the tile is tile_x x block/tile_x columns); zchunk: z-planes per tile (>= 1);
+   the tile is tile_x x block/tile_x columns, and its one-cell halo ring,
+   2 (tile_x + 2) + 2 block/tile_x cells, must not exceed block: 16 with any
+   block, 32 with 128 or 256, 64 with 256); zchunk: z-planes per tile (>= 1);
    graph_steps: steps captured per hipGraph (0: no graph); max_blocks: upper
    bound on resident workgroups for the tile loop (0: one per tile).
    merge: 0 one launch per tile class; 1 tiles without CPML run with the z-CPML

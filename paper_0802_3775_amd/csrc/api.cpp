@@ -655,6 +655,9 @@ int fdtd_set_tuning(fdtd_plan* p, const fdtd_tuning* t) {
   if (t->zchunk < 1 || t->graph_steps < 0 || t->max_blocks < 0) return fail(FDTD_EINVAL, "bad tuning");
   if (t->tile_x != 16 && t->tile_x != 32 && t->tile_x != 64) return fail(FDTD_EINVAL, "tile_x must be 16, 32 or 64");
   if (t->block % t->tile_x != 0) return fail(FDTD_EINVAL, "block must be a multiple of tile_x");
+  if (2 * (t->tile_x + 2) + 2 * (t->block / t->tile_x) > t->block)
+    return fail(FDTD_EINVAL, "tile_x %d with block %d: the tile's halo ring (2 (tile_x+2) + 2 block/tile_x cells) "
+                "exceeds block", t->tile_x, t->block);
   if (t->merge < 0 || t->merge > 2 || t->parallel < 0 || t->parallel > 1) return fail(FDTD_EINVAL, "bad merge/parallel");
   p->tune = *t;
   return FDTD_OK;
@@ -893,6 +896,23 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
         t.k1 = ch.second;
         t.tidx = tidx++;
         t.blk = by * ntx + bx;
+        // sources, probes and flux planes the tile's kernel must look at
+        for (int q = 0; q < d.nsrc; ++q) {
+          if (d.src_k[q] < t.k0 || d.src_k[q] >= t.k1) continue;
+          if (d.src_kind[q] == FDTD_SRC_DIPOLE) {
+            const int si = d.src_cell[q] % p->g.nx, sj = d.src_cell[q] / p->g.nx;
+            if (si < t.i0 || si >= t.i0 + TX || sj < t.j0 || sj >= t.j0 + TY) continue;
+          }
+          t.srcmask |= 1u << q;
+        }
+        for (int q = 0; q < d.nprobe; ++q) {
+          const int pi = d.probe_cell[q] % p->g.nx, pj = d.probe_cell[q] / p->g.nx;
+          if (d.probe_k[q] >= t.k0 && d.probe_k[q] < t.k1 && pi >= t.i0 && pi < t.i0 + TX && pj >= t.j0 &&
+              pj < t.j0 + TY)
+            t.pmask |= 1u << q;
+        }
+        for (int q = 0; q < d.nflux; ++q)
+          if (d.flux_k[q] >= t.k0 && d.flux_k[q] < t.k1) t.fmask |= 1u << q;
         // A tile needs the CPML code if any H value it evaluates lies in a slab:
         // its own cells, the x-1 / y-1 neighbours it recomputes, and plane k0-1.
         // (Slabs only exist on PEC axes, so no wrap-around is involved.)

@@ -80,6 +80,9 @@ struct fd_tile {
   const fd_desc* d;
   int i0, j0, k0, k1;
   int tidx, blk;
+  // sources, probes and flux planes that touch the tile (bit q = entry q)
+  unsigned srcmask, pmask, fmask;
+  int pad;
 };
 
 struct fd_dft_tile {

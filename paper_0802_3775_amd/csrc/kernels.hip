@@ -21,6 +21,8 @@
 // run a specialised kernel without that code.
 #include "fd_internal.h"
 
+#include <type_traits>
+
 namespace {
 
 constexpr float kTwoPiF = 6.28318530717958647692f;
@@ -70,26 +72,44 @@ typedef __attribute__((address_space(1))) double gd;
 typedef __attribute__((address_space(1))) uint8_t gu8;
 typedef __attribute__((address_space(4))) fd_desc cdesc;
 typedef __attribute__((address_space(4))) fd_mat cmat;
+typedef __attribute__((address_space(4))) const float cfloat;
 
 __device__ __forceinline__ gf* G(float* p) { return (gf*)p; }
 __device__ __forceinline__ const gf* G(const float* p) { return (const gf*)p; }
 __device__ __forceinline__ gd* G(double* p) { return (gd*)p; }
 __device__ __forceinline__ const gd* G(const double* p) { return (const gd*)p; }
 
+// A field array indexed with a 32-bit element index: the byte offset is formed
+// in 32 bits and zero-extended, so loads and stores take the scalar-base +
+// 32-bit vector-offset form (one VGPR per address, no 64-bit address adds).
+// Valid for arrays below 4 GiB, which every per-cell array is (at most 2^30
+// cells of 4 bytes).
+typedef __attribute__((address_space(1))) char gchar;
+typedef __attribute__((address_space(1))) const char gcchar;
+template <class T>
+struct R32 {
+  __attribute__((address_space(1))) T* p;
+  __device__ __forceinline__ __attribute__((address_space(1))) T& operator[](uint32_t i) const {
+    typedef __attribute__((address_space(1))) T gT;
+    typedef typename std::conditional<std::is_const<T>::value, gcchar, gchar>::type gb;
+    return *(gT*)((gb*)p + (size_t)(i * (uint32_t)sizeof(T)));
+  }
+};
+
 struct Ctx {
   int nx, ny, nz, plane;
   int px, py, pz;
   float ch;
-  const gf* Ein[3];
-  gf* Eout[3];
-  const gf* Hin[3];
-  gf* Hout[3];
+  R32<const float> Ein[3];
+  R32<float> Eout[3];
+  R32<const float> Hin[3];
+  R32<float> Hout[3];
   // CPML (used by the kernels specialised with PML)
   int lo[3], hi[3], t[3], n[3];
-  const gf* prof[3];
-  gf* psiE[3][2];
-  const gf* psiHin[3][2];
-  gf* psiHout[3][2];
+  const cfloat* prof[3];  // read-only for the kernel: scalar loads where uniform
+  R32<float> psiE[3][2];
+  R32<const float> psiHin[3][2];
+  R32<float> psiHout[3][2];
 };
 
 __device__ __forceinline__ void make_ctx(Ctx& x, const cdesc* d, int par, bool pml) {
@@ -98,22 +118,22 @@ __device__ __forceinline__ void make_ctx(Ctx& x, const cdesc* d, int par, bool p
   x.ch = d->ch;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    x.Ein[c] = G((const float*)d->E[par][c]);
-    x.Eout[c] = G(d->E[par ^ 1][c]);
-    x.Hin[c] = G((const float*)d->H[par][c]);
-    x.Hout[c] = G(d->H[par ^ 1][c]);
+    x.Ein[c].p = G((const float*)d->E[par][c]);
+    x.Eout[c].p = G(d->E[par ^ 1][c]);
+    x.Hin[c].p = G((const float*)d->H[par][c]);
+    x.Hout[c].p = G(d->H[par ^ 1][c]);
   }
   x.n[0] = d->nx; x.n[1] = d->ny; x.n[2] = d->nz;
   if (!pml) return;
 #pragma unroll
   for (int w = 0; w < 3; ++w) {
     x.lo[w] = d->pml_lo[w]; x.hi[w] = d->pml_hi[w]; x.t[w] = d->pml_t[w];
-    x.prof[w] = G(d->prof[w]);
+    x.prof[w] = (const cfloat*)d->prof[w];
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
-      x.psiE[w][f] = G(d->psiE[w][f]);
-      x.psiHin[w][f] = G((const float*)d->psiH[par][w][f]);
-      x.psiHout[w][f] = G(d->psiH[par ^ 1][w][f]);
+      x.psiE[w][f].p = G(d->psiE[w][f]);
+      x.psiHin[w][f].p = G((const float*)d->psiH[par][w][f]);
+      x.psiHout[w][f].p = G(d->psiH[par ^ 1][w][f]);
     }
   }
 }
@@ -156,7 +176,7 @@ __device__ __forceinline__ float stretch(const Ctx& x, int c, int w, int p, int 
   if (!((PM >> w) & 1)) return d;  // no slab on this axis in this tile class
   const int sp = slab(x, w, p);
   if (sp < 0) return d;
-  const gf* pr = x.prof[w] + (HSIDE ? 3 : 0) * x.n[w];
+  const cfloat* pr = x.prof[w] + (HSIDE ? 3 : 0) * x.n[w];
   const float kinv = pr[p], b = pr[x.n[w] + p], cc = pr[2 * x.n[w] + p];
   const int off = psi_off(x, w, sp, i, j, k);
   const int f = fam(c, w);
@@ -171,18 +191,40 @@ __device__ __forceinline__ float stretch(const Ctx& x, int c, int w, int p, int 
   return fmaf(d, kinv, psi);
 }
 
+// The same for a z difference when the old psi and the plane's grading
+// (pz = 1/kappa, b, c) have already been loaded: z slabs are whole planes, so
+// the slab index sz of plane k is uniform over a tile.  off2d: j*nx + i of the
+// cell.  Bit-identical to stretch<HSIDE, PM>(.., 2, k, ..).
+template <bool HSIDE>
+__device__ __forceinline__ float stretch_z(const Ctx& x, int c, const float* pz, int sz, int off2d, float d,
+                                           bool own, float psi_old) {
+  if (sz < 0) return d;
+  const float kinv = pz[0], b = pz[1], cc = pz[2];
+  const float psi = fmaf(b, psi_old, cc * d);
+  if (own) {
+    const int off = sz * x.plane + off2d;
+    if (HSIDE) x.psiHout[2][fam(c, 2)][off] = psi;
+    else x.psiE[2][fam(c, 2)][off] = psi;
+  }
+  return fmaf(d, kinv, psi);
+}
+
 // One H component from its two differences: H^{n+1/2} = H^{n-1/2} - (dt/dx)(d1 - d2),
 // each difference stretched by the CPML where the position lies in a slab.  The
 // owner and every workgroup that recomputes the value as a halo call this with
 // identical operands, so all copies agree bit for bit.
 // c: component; (w1, p1) / (w2, p2): axis and index of the two differences.
-template <int PM>
+// ZPRE: a z difference takes its old psi from zpsi (slab index sz, cell off2d).
+template <int PM, bool ZPRE = false>
 __device__ __forceinline__ float h_from(const Ctx& x, int c, int w1, int p1, int w2, int p2, int i, int j, int k,
-                                        float a1, float a0, float b1, float b0, float hold, bool own) {
+                                        float a1, float a0, float b1, float b0, float hold, bool own, int sz = -1,
+                                        int off2d = 0, float zpsi = 0.0f, const float* pz = nullptr) {
   float d1 = a1 - a0, d2 = b1 - b0;
   if (PM) {
-    d1 = stretch<true, PM>(x, c, w1, p1, i, j, k, d1, own);
-    d2 = stretch<true, PM>(x, c, w2, p2, i, j, k, d2, own);
+    d1 = (ZPRE && w1 == 2) ? stretch_z<true>(x, c, pz, sz, off2d, d1, own, zpsi)
+                           : stretch<true, PM>(x, c, w1, p1, i, j, k, d1, own);
+    d2 = (ZPRE && w2 == 2) ? stretch_z<true>(x, c, pz, sz, off2d, d2, own, zpsi)
+                           : stretch<true, PM>(x, c, w2, p2, i, j, k, d2, own);
   }
   return fmaf(-x.ch, d1 - d2, hold);
 }
@@ -248,9 +290,9 @@ struct Lds {
   float H[3][(TYM + 1) * (TX + 1)];     // H^{n+1/2} of plane k over [i0-1, i0+TX-1] x [j0-1, j0+TY-1]
   fd_mat mat[FD_MAXMAT];
   double red[FD_MAXBLOCK / 64];
+  double ftot[FD_MAXFLUX];  // T(t) partial of the tile per flux plane, stored after the z march
+  float probe[FD_MAXPROBE];  // probe samples of the tile, stored after the z march
 };
-
-constexpr int RMAX = 3;  // ring cells staged per thread (block >= 64, tile_x <= 64)
 
 template <int TX, int PM, bool GAIN>
 __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
@@ -260,12 +302,11 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   const int t = (int)threadIdx.x;
   const int tx = t % TX, ty = t / TX;
   lds_barrier();  // LDS reuse across tiles of the persistent loop
-  {
-    const int words = d->nmat * (int)(sizeof(fd_mat) / 4);
-    const gf* src = G((const float*)d->mats);
-    float* dst = reinterpret_cast<float*>(s.mat);
-    for (int q = t; q < words; q += blockDim.x) dst[q] = src[q];
-  }
+  // material table: the load is issued here and stored to LDS just before the
+  // z march, so its latency overlaps the set-up loads
+  const int mwords = d->nmat * (int)(sizeof(fd_mat) / 4);
+  const gf* msrc = G((const float*)d->mats);
+  const float mword = t < mwords ? msrc[t] : 0.0f;
   const long long n = d->step + s_rel;
   const int par = (int)(n & 1);
   Ctx x;
@@ -282,26 +323,23 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
     own_off = (gi >= 0 && gj >= 0) ? gj * x.nx + gi : -1;
   }
   const int own_slot = (ty + 1) * W + tx + 1;
-  int r_off[RMAX], r_slot[RMAX];
-  {
-    const int nring = 2 * (TX + 2) + 2 * TY;
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-      const int q = t + r * (int)blockDim.x;
-      r_slot[r] = -1;
-      r_off[r] = -1;
-      if (q < nring) {
-        int lx, ly;
-        if (q < TX + 2) { lx = q; ly = 0; }
-        else if (q < 2 * (TX + 2)) { lx = q - (TX + 2); ly = TY + 1; }
-        else if (q < 2 * (TX + 2) + TY) { lx = 0; ly = 1 + q - 2 * (TX + 2); }
-        else { lx = TX + 1; ly = 1 + q - 2 * (TX + 2) - TY; }
-        const int gi = wrap(i0 - 1 + lx, x.nx, x.px), gj = wrap(j0 - 1 + ly, x.ny, x.py);
-        r_slot[r] = ly * W + lx;
-        r_off[r] = (gi >= 0 && gj >= 0) ? gj * x.nx + gi : -1;
-      }
-    }
-  }
+  // The E staging area has a one-cell ring around the TX x TY tile: ring cell q
+  // (bottom row, top row, left column, right column) maps to an LDS slot and a
+  // plane offset (-1 beyond a PEC wall).  Thread t stages ring cell t; the
+  // launch guarantees 2 (TX + 2) + 2 TY <= blockDim.
+  const int nring = 2 * (TX + 2) + 2 * TY;
+  auto ring_cell = [&](int q, int& slot, int& off) {
+    int lx, ly;
+    if (q < TX + 2) { lx = q; ly = 0; }
+    else if (q < 2 * (TX + 2)) { lx = q - (TX + 2); ly = TY + 1; }
+    else if (q < 2 * (TX + 2) + TY) { lx = 0; ly = 1 + q - 2 * (TX + 2); }
+    else { lx = TX + 1; ly = 1 + q - 2 * (TX + 2) - TY; }
+    const int gi = wrap(i0 - 1 + lx, x.nx, x.px), gj = wrap(j0 - 1 + ly, x.ny, x.py);
+    slot = ly * W + lx;
+    off = (gi >= 0 && gj >= 0) ? gj * x.nx + gi : -1;
+  };
+  int r_slot = -1, r_off = -1;
+  if (t < nring) ring_cell(t, r_slot, r_off);
   // halo duty: threads [0, TY) own the column i0-1, threads [TY, TY+TX) the row j0-1
   const bool lh = t < TY;
   const bool bh = !lh && t < TY + TX;
@@ -310,97 +348,106 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   const bool hact = (lh || bh) && hgi >= 0 && hgj >= 0 && (lh ? (j0 + t < x.ny) : (i0 + (t - TY) < x.nx));
   const int h_off = hact ? hgj * x.nx + hgi : 0;
 
-  // ---- per-tile masks of sources, probes and flux planes that can touch it
-  const int iend = i0 + TX, jend = j0 + TY;
-  unsigned srcmask = 0u, srcmine = 0u;
-  for (int q = 0; q < d->nsrc; ++q) {
-    if (d->src_k[q] < k0 || d->src_k[q] >= k1) continue;
-    if (d->src_kind[q] == 1) {
-      srcmask |= 1u << q;
-      srcmine |= 1u << q;
-    } else {
-      const int sc = d->src_cell[q], si = sc % x.nx, sj = sc / x.nx;
-      if (si >= i0 && si < iend && sj >= j0 && sj < jend) {
-        srcmask |= 1u << q;
-        if (sc == c) srcmine |= 1u << q;
-      }
-    }
+  // ---- sources, probes and flux planes that touch the tile (set on the host);
+  // srcmine: the sources that drive this thread's column
+  const unsigned srcmask = tl.srcmask, pmask = tl.pmask, fmask = tl.fmask;
+  unsigned srcmine = 0u;
+  for (unsigned mm = srcmask; mm; mm &= mm - 1u) {
+    const int q = __builtin_ctz(mm);
+    if (d->src_kind[q] == 1 || d->src_cell[q] == c) srcmine |= 1u << q;
   }
-  unsigned pmask = 0u;
-  for (int q = 0; q < d->nprobe; ++q) {
-    const int pc = d->probe_cell[q], pi = pc % x.nx, pj = pc / x.nx;
-    if (d->probe_k[q] >= k0 && d->probe_k[q] < k1 && pi >= i0 && pi < iend && pj >= j0 && pj < jend)
-      pmask |= 1u << q;
-  }
-  unsigned fmask = 0u;
-  for (int q = 0; q < d->nflux; ++q)
-    if (d->flux_k[q] >= k0 && d->flux_k[q] < k1) fmask |= 1u << q;
   const bool edue = d->ke > 0 && (n % d->ke) == 0;
   double eacc = 0.0;
 
-  // ---- staging of E^n planes: global loads into registers (one plane ahead of
-  // use), then LDS stores.  Slots outside the grid hold the periodic image or 0.
-  struct Plane {
+  // ---- staging.  Iteration k of the z march consumes a Stage holding E^n of
+  // plane k+1 (own cell and one ring cell; stored to LDS at the top of the
+  // iteration) and the own inputs of plane k (H^{n-1/2}, the halo-duty H, the
+  // material index).  Two Stages alternate, so the loads for plane k+3 (E) and
+  // k+2 (own inputs) are in flight while plane k is computed: the global-load
+  // latency is spread over two iterations.  Slots outside the grid hold the
+  // periodic image or 0.
+  // A Stage holds raw load results; validity selects are applied where the
+  // values are used, so no instruction touches a load result before it is due.
+  struct Stage {
     float own[3];
-    float ring[RMAX][3];
-  };
-  auto load_plane = [&](int kk, Plane& P) {
-    const int kz = kk < x.nz ? kk : (x.pz ? kk - x.nz : -1);
-    const int zo = kz * x.plane;
-    const bool okz = kz >= 0;
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc) P.own[cc] = (okz && own_off >= 0) ? x.Ein[cc][zo + own_off] : 0.0f;
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r)
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc)
-        P.ring[r][cc] = (okz && r_off[r] >= 0) ? x.Ein[cc][zo + r_off[r]] : 0.0f;
-  };
-  auto store_plane = [&](int b, const Plane& P) {
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc) s.E[b][cc][own_slot] = P.own[cc];
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-      if (r_slot[r] < 0) continue;
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc) s.E[b][cc][r_slot[r]] = P.ring[r][cc];
-    }
-  };
-  const gu8* matp = (const gu8*)d->mat;
-  // per-plane own inputs: H^{n-1/2} (own and halo duty) and the material index
-  struct Cell {
-    float ho[3];
-    float hh[2];
+    float ring[3];
+    bool zok;     // plane inside the grid (or its periodic image)
+    float ho[3];  // H^{n-1/2} of the own cell
+    float hh[3];  // Hx, Hy, Hz at the halo-duty cell
     int m;
+    float ph[2];  // z-slab planes: old psi_H of Hx, Hy (own)
+    float phh[2]; // z-slab planes: old psi_H of Hx, Hy at the halo-duty cell
+    float pe[2];  // z-slab planes: old psi_E of Ex, Ey (own)
+    float gh[3];  // z-slab planes: H-side grading 1/kappa, b, c (uniform)
+    float ge[3];  // z-slab planes: E-side grading (uniform)
   };
-  auto load_cell = [&](int kk, Cell& C) {
-    const int zo = kk * x.plane;
-    C.ho[0] = C.ho[1] = C.ho[2] = 0.0f;
-    C.hh[0] = C.hh[1] = 0.0f;
-    C.m = 0;
-    if (act) {
-      C.ho[0] = x.Hin[0][zo + c];
-      C.ho[1] = x.Hin[1][zo + c];
-      C.ho[2] = x.Hin[2][zo + c];
-      C.m = matp[zo + c];
+  // Every global load of the z march is issued unconditionally (a lane with
+  // nothing to load reads element 0 and discards it), and the march stores to
+  // global memory only the fields and CPML memory: the loads in flight per
+  // iteration are then the same on every path, so the compiler waits for
+  // exactly the Stage it consumes and leaves the other one in flight.
+  // live = false: the plane is past the tile; the loads are still issued (at
+  // element 0) so that every path through the march issues the same loads.
+  auto load_e = [&](int kk, Stage& S, bool live) {
+    const int kz = kk < x.nz ? kk : (x.pz ? kk - x.nz : -1);
+    S.zok = kz >= 0;
+    const int zo = S.zok ? kz * x.plane : 0;
+    const uint32_t io = (live && own_off >= 0) ? zo + own_off : 0, ir = (live && r_off >= 0) ? zo + r_off : 0;
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) S.own[cc] = x.Ein[cc][io];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) S.ring[cc] = x.Ein[cc][ir];
+  };
+  auto store_e = [&](int b, const Stage& S) {
+    const bool oko = S.zok && own_off >= 0, okr = S.zok && r_off >= 0;
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) s.E[b][cc][own_slot] = oko ? S.own[cc] : 0.0f;
+    if (r_slot >= 0) {
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) s.E[b][cc][r_slot] = okr ? S.ring[cc] : 0.0f;
     }
-    if (hact) {
-      // the column i0-1 needs Hy, Hz; the row j0-1 needs Hx, Hz
-      C.hh[0] = lh ? x.Hin[1][zo + h_off] : x.Hin[0][zo + h_off];
-      C.hh[1] = x.Hin[2][zo + h_off];
+  };
+  const R32<const uint8_t> matp{(const gu8*)d->mat};
+  constexpr bool ZP = PM == 4;  // z-slab psi prefetched with the plane (z-only CPML tiles)
+  auto load_h = [&](int kk, Stage& S, bool live) {
+    kk = live ? kk : 0;
+    const int zo = kk * x.plane;
+    const uint32_t io = (live && act) ? zo + c : 0, ih = (live && hact) ? zo + h_off : 0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) S.ho[q] = x.Hin[q][io];
+    S.m = matp[io];  // lanes outside the grid read cell 0: a valid material
+    // the column i0-1 needs Hy, Hz; the row j0-1 needs Hx, Hz
+#pragma unroll
+    for (int q = 0; q < 3; ++q) S.hh[q] = x.Hin[q][ih];
+    if (ZP) {
+      // the z differences of Hx, Hy, Ex, Ey in a z slab carry psi: load the
+      // old values with the plane's other inputs (psi_E is touched only by the
+      // owner of the cell, so reading it early is safe); the grading is uniform
+      const int sz = slab(x, 2, kk);
+      const int nz = x.n[2];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        S.ge[q] = x.prof[2][q * nz + kk];
+        S.gh[q] = x.prof[2][(3 + q) * nz + kk];
+      }
+      const int base = (sz >= 0 ? sz : 0) * x.plane;
+      const uint32_t jo = (live && sz >= 0 && act) ? base + c : 0, jh = (live && sz >= 0 && hact) ? base + h_off : 0;
+      S.ph[0] = x.psiHin[2][fam(0, 2)][jo];
+      S.ph[1] = x.psiHin[2][fam(1, 2)][jo];
+      S.pe[0] = x.psiE[2][fam(0, 2)][jo];
+      S.pe[1] = x.psiE[2][fam(1, 2)][jo];
+      S.phh[0] = x.psiHin[2][fam(0, 2)][jh];
+      S.phh[1] = x.psiHin[2][fam(1, 2)][jh];
     }
   };
 
-  float ecur[3], enxt[3];
-  int cb = 0;
-  Plane pre;
-  load_plane(k0, pre);
-  store_plane(cb, pre);
-#pragma unroll
-  for (int q = 0; q < 3; ++q) ecur[q] = pre.own[q];
-  load_plane(k0 + 1, pre);
-  Cell cur, nxc;
-  load_cell(k0, cur);
+  Stage SA, SB;
+  load_e(k0, SA, true);
+  store_e(0, SA);
+  load_e(k0 + 1, SA, true);
+  load_h(k0, SA, true);
+  load_e(k0 + 2, SB, k0 + 1 < k1);
+  load_h(k0 + 1, SB, k0 + 1 < k1);
   float hxm = 0.0f, hym = 0.0f;
   {
     const int km = prv(k0, x.nz, x.pz);
@@ -410,22 +457,28 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
     }
   }
 
-  for (int k = k0; k < k1; ++k) {
-    const int nb = cb ^ 1;
-    // plane k+1 (loaded during the previous iteration) into LDS; issue the loads
-    // of plane k+2 and of the next plane's own inputs, consumed one iteration later
-    store_plane(nb, pre);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) enxt[q] = pre.own[q];
-    if (k + 1 < k1) {
-      load_plane(k + 2, pre);
-      load_cell(k + 1, nxc);
-    }
+  // plane k uses LDS E buffer cb = (k - k0) & 1, a compile-time constant in
+  // each of the two unrolled copies, so every LDS address is a fixed offset
+  {
+    float* mdst = reinterpret_cast<float*>(s.mat);
+    if (t < mwords) mdst[t] = mword;
+    for (int q = t + (int)blockDim.x; q < mwords; q += (int)blockDim.x) mdst[q] = msrc[q];
+  }
+
+  auto plane_step = [&](auto cbc, const int k, Stage& S) __attribute__((always_inline)) {
+    constexpr int cb = decltype(cbc)::value;
+    constexpr int nb = cb ^ 1;
+    // plane k+1 into LDS, then the loads two planes ahead into the same Stage
+    store_e(nb, S);
+    load_e(k + 3, S, k + 2 < k1);
     const int zo = k * x.plane;
     const int o = zo + c;
-    const float* ho = cur.ho;
-    const int m = cur.m;
-    const float hho0 = cur.hh[0], hho1 = cur.hh[1];
+    const int sz = ZP ? slab(x, 2, k) : -1;
+    // E^n of the own cell (plane k), read before the second barrier: after it a
+    // faster wave may already be staging plane k+2 into this buffer
+    float eo[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) eo[q] = s.E[cb][q][own_slot];
     lds_barrier();
     // ---- H^{n+1/2} of plane k: own cell and halo duty
     float hx = 0.0f, hy = 0.0f, hz = 0.0f;
@@ -433,11 +486,13 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       const float* Ex = s.E[cb][0];
       const float* Ey = s.E[cb][1];
       const float* Ez = s.E[cb][2];
+      const float* Ex1 = s.E[nb][0];
+      const float* Ey1 = s.E[nb][1];
       const int a = own_slot;
       if (act) {
-        hx = h_from<PM>(x, 0, 1, j, 2, k, i, j, k, Ez[a + W], Ez[a], enxt[1], Ey[a], ho[0], true);
-        hy = h_from<PM>(x, 1, 2, k, 0, i, i, j, k, enxt[0], Ex[a], Ez[a + 1], Ez[a], ho[1], true);
-        hz = h_from<PM>(x, 2, 0, i, 1, j, i, j, k, Ey[a + 1], Ey[a], Ex[a + W], Ex[a], ho[2], true);
+        hx = h_from<PM, ZP>(x, 0, 1, j, 2, k, i, j, k, Ez[a + W], Ez[a], Ey1[a], Ey[a], S.ho[0], true, sz, c, S.ph[0], S.gh);
+        hy = h_from<PM, ZP>(x, 1, 2, k, 0, i, i, j, k, Ex1[a], Ex[a], Ez[a + 1], Ez[a], S.ho[1], true, sz, c, S.ph[1], S.gh);
+        hz = h_from<PM, ZP>(x, 2, 0, i, 1, j, i, j, k, Ey[a + 1], Ey[a], Ex[a + W], Ex[a], S.ho[2], true, sz, c, 0.0f, S.gh);
         x.Hout[0][o] = hx;
         x.Hout[1][o] = hy;
         x.Hout[2][o] = hz;
@@ -447,20 +502,22 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       s.H[1][hs] = hy;
       s.H[2][hs] = hz;
       if (hact) {
-        const float* Ex1 = s.E[nb][0];
-        const float* Ey1 = s.E[nb][1];
         if (lh) {
           // cell (i0-1, j0+t): LDS column 0, row t+1
           const int e = (t + 1) * W;
-          const float hyv = h_from<PM>(x, 1, 2, k, 0, hgi, hgi, hgj, k, Ex1[e], Ex[e], Ez[e + 1], Ez[e], hho0, false);
-          const float hzv = h_from<PM>(x, 2, 0, hgi, 1, hgj, hgi, hgj, k, Ey[e + 1], Ey[e], Ex[e + W], Ex[e], hho1, false);
+          const float hyv = h_from<PM, ZP>(x, 1, 2, k, 0, hgi, hgi, hgj, k, Ex1[e], Ex[e], Ez[e + 1], Ez[e], S.hh[1],
+                                           false, sz, h_off, S.phh[1], S.gh);
+          const float hzv = h_from<PM, ZP>(x, 2, 0, hgi, 1, hgj, hgi, hgj, k, Ey[e + 1], Ey[e], Ex[e + W], Ex[e],
+                                           S.hh[2], false, sz, h_off, 0.0f, S.gh);
           s.H[1][(t + 1) * (TX + 1)] = hyv;
           s.H[2][(t + 1) * (TX + 1)] = hzv;
         } else {
           // cell (i0+q-1, j0-1): LDS row 0, column q
           const int q = t - TY + 1;
-          const float hxv = h_from<PM>(x, 0, 1, hgj, 2, k, hgi, hgj, k, Ez[W + q], Ez[q], Ey1[q], Ey[q], hho0, false);
-          const float hzv = h_from<PM>(x, 2, 0, hgi, 1, hgj, hgi, hgj, k, Ey[q + 1], Ey[q], Ex[W + q], Ex[q], hho1, false);
+          const float hxv = h_from<PM, ZP>(x, 0, 1, hgj, 2, k, hgi, hgj, k, Ez[W + q], Ez[q], Ey1[q], Ey[q], S.hh[0],
+                                           false, sz, h_off, S.phh[0], S.gh);
+          const float hzv = h_from<PM, ZP>(x, 2, 0, hgi, 1, hgj, hgi, hgj, k, Ey[q + 1], Ey[q], Ex[W + q], Ex[q],
+                                           S.hh[2], false, sz, h_off, 0.0f, S.gh);
           s.H[0][q] = hxv;
           s.H[2][q] = hzv;
         }
@@ -473,8 +530,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       const int hs = (ty + 1) * (TX + 1) + tx + 1;
       const float hz_im = s.H[2][hs - 1], hy_im = s.H[1][hs - 1];
       const float hx_jm = s.H[0][hs - (TX + 1)], hz_jm = s.H[2][hs - (TX + 1)];
-      const fd_mat& mt = s.mat[m];
-      const float* eo = ecur;
+      const fd_mat& mt = s.mat[S.m];
       float dP[3] = {0.0f, 0.0f, 0.0f};
       float Pnew[3] = {0.0f, 0.0f, 0.0f};
       const bool g = GAIN && mt.is_gain;
@@ -506,28 +562,28 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         }
       }
       float cx = 0.0f, cy = 0.0f, cz = 0.0f;  // source terms dx*J of this cell
-      if (srcmask) {
-        for (int q = 0; q < FD_MAXSRC; ++q) {
-          if (!((srcmine >> q) & 1u) || d->src_k[q] != k) continue;
-          const float v = n < d->src_len[q] ? G((const float*)d->src_tab[q])[n] : 0.0f;
-          const int sc = d->src_comp[q];
-          if (sc == 0) cx += v;
-          else if (sc == 1) cy += v;
-          else cz += v;
-        }
+      for (unsigned mm = srcmask; mm; mm &= mm - 1u) {  // uniform; scalar loads only
+        const int q = __builtin_ctz(mm);
+        if (d->src_k[q] != k) continue;
+        const float v = n < d->src_len[q] ? ((const cfloat*)d->src_tab[q])[n] : 0.0f;
+        if (!((srcmine >> q) & 1u)) continue;
+        const int sc = d->src_comp[q];
+        if (sc == 0) cx += v;
+        else if (sc == 1) cy += v;
+        else cz += v;
       }
       if (!((!x.py && j == 0) || (!x.pz && k == 0))) {  // Ex: d/dy Hz - d/dz Hy
         float d1 = hz - hz_jm, d2 = hy - hym;
         if (PM) {
           d1 = stretch<false, PM>(x, 0, 1, j, i, j, k, d1, true);
-          d2 = stretch<false, PM>(x, 0, 2, k, i, j, k, d2, true);
+          d2 = ZP ? stretch_z<false>(x, 0, S.ge, sz, c, d2, true, S.pe[0]) : stretch<false, PM>(x, 0, 2, k, i, j, k, d2, true);
         }
         ex_n = fmaf(mt.cb, (d1 - d2) - cx, eo[0]) - dP[0] * mt.inv_eps;
       }
       if (!((!x.pz && k == 0) || (!x.px && i == 0))) {  // Ey: d/dz Hx - d/dx Hz
         float d1 = hx - hxm, d2 = hz - hz_im;
         if (PM) {
-          d1 = stretch<false, PM>(x, 1, 2, k, i, j, k, d1, true);
+          d1 = ZP ? stretch_z<false>(x, 1, S.ge, sz, c, d1, true, S.pe[1]) : stretch<false, PM>(x, 1, 2, k, i, j, k, d1, true);
           d2 = stretch<false, PM>(x, 1, 0, i, i, j, k, d2, true);
         }
         ey_n = fmaf(mt.cb, (d1 - d2) - cy, eo[1]) - dP[1] * mt.inv_eps;
@@ -564,40 +620,51 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
 #pragma unroll
         for (int q = 0; q < 3; ++q) G(d->P[par ^ 1][q])[o] = Pnew[q];
       }
-      if (pmask) {
-        for (int p = 0; p < FD_MAXPROBE; ++p) {
-          if (!((pmask >> p) & 1u) || d->probe_k[p] != k || d->probe_cell[p] != c) continue;
-          const int cp = d->probe_comp[p];
-          const float v = cp == 0 ? ex_n : cp == 1 ? ey_n : cp == 2 ? ez_n : cp == 3 ? hx : cp == 4 ? hy : hz;
-          G(d->probe_ring)[(long long)p * d->max_steps + n] = v;
-        }
+      for (unsigned mm = pmask; mm; mm &= mm - 1u) {  // uniform
+        const int p = __builtin_ctz(mm);
+        if (d->probe_k[p] != k || d->probe_cell[p] != c) continue;
+        const int cp = d->probe_comp[p];
+        s.probe[p] = cp == 0 ? ex_n : cp == 1 ? ey_n : cp == 2 ? ez_n : cp == 3 ? hx : cp == 4 ? hy : hz;
       }
       if (edue) {
         const float e2 = fmaf(eo[0], eo[0], fmaf(eo[1], eo[1], eo[2] * eo[2]));
-        const float hh = fmaf(ho[0], hx, fmaf(ho[1], hy, ho[2] * hz));
+        const float hh = fmaf(S.ho[0], hx, fmaf(S.ho[1], hy, S.ho[2] * hz));
         eacc += (double)(mt.eps * e2) + (double)hh;
       }
     }
+    // own inputs two planes ahead into the Stage just consumed
+    load_h(k + 2, S, k + 2 < k1);
     // transmitted power through flux planes at this k (uniform branch)
     if (fmask) {
       for (int f = 0; f < FD_MAXFLUX; ++f) {
         if (!((fmask >> f) & 1u) || d->flux_k[f] != k) continue;
         double v = 0.0;
         if (act) {
-          const float sx = 0.5f * (ecur[0] + ex_n), sy = 0.5f * (ecur[1] + ey_n);
+          const float sx = 0.5f * (eo[0] + ex_n), sy = 0.5f * (eo[1] + ey_n);
           const float hyc = 0.5f * (hym + hy), hxc = 0.5f * (hxm + hx);
           v = (double)(sx * hyc) - (double)(sy * hxc);
         }
         const double tot = block_sum(v, s.red);
-        if (t == 0) G(d->flux_T[f])[n * d->nblk + tl.blk] = tot;
+        if (t == 0) s.ftot[f] = tot;
       }
     }
     hxm = hx;
     hym = hy;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) ecur[q] = enxt[q];
-    cur = nxc;
-    cb = nb;
+  };
+
+  // the loop body is both copies unconditionally (a path that skips the second
+  // copy would make the compiler wait for every load at the loop head)
+  int k = k0;
+  for (; k + 1 < k1; k += 2) {
+    plane_step(std::integral_constant<int, 0>(), k, SA);
+    plane_step(std::integral_constant<int, 1>(), k + 1, SB);
+  }
+  if (k < k1) plane_step(std::integral_constant<int, 0>(), k, SA);
+  // probe samples and T(t) partials gathered during the march
+  if (pmask | fmask) {
+    lds_barrier();
+    if (t < FD_MAXPROBE && ((pmask >> t) & 1u)) G(d->probe_ring)[(long long)t * d->max_steps + n] = s.probe[t];
+    if (t < FD_MAXFLUX && ((fmask >> t) & 1u)) G(d->flux_T[t])[n * d->nblk + tl.blk] = s.ftot[t];
   }
   if (edue) {
     const double tot = block_sum(eacc, s.red);
@@ -806,7 +873,8 @@ static hipError_t launch_tx(int cls, const fd_tile* tiles, int ntiles, int block
 hipError_t fd_launch_step(int cls, const fd_tile* tiles, int ntiles, int tile_x, int block, int grid, int s,
                           const fd_xcd* part, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  if (block < 64 || block > FD_MAXBLOCK || (block & 63) != 0 || grid <= 0 || block % tile_x != 0)
+  if (block < 64 || block > FD_MAXBLOCK || (block & 63) != 0 || grid <= 0 || block % tile_x != 0 ||
+      2 * (tile_x + 2) + 2 * (block / tile_x) > block)
     return hipErrorInvalidValue;
   fd_xcd pz{};
   int use = 0;

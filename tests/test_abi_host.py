@@ -66,6 +66,10 @@ def test_add_calls_reject_out_of_range():
     assert L.fdtd_add_flux_plane(h, 5, F._ptr(fr, C.c_double), 1, 0, None) == -1  # decim 0
     t = F.Tuning(100, 8, 0, 0)
     assert L.fdtd_set_tuning(h, C.byref(t)) == -1  # block not a multiple of 64
+    # the tile's halo ring must fit one cell per thread: 2 (tx+2) + 2 block/tx <= block
+    for block, tx, ok in ((64, 16, True), (64, 32, False), (128, 32, True), (128, 64, False), (256, 64, True)):
+        t = F.Tuning(block, 4, 0, 0, tx, 1, 0)
+        assert (L.fdtd_set_tuning(h, C.byref(t)) == 0) == ok, (block, tx)
     size = C.c_size_t()
     assert L.fdtd_required_bytes(h, 100, C.byref(size)) == 0 and size.value > 0
     L.fdtd_plan_destroy(h)

@@ -77,7 +77,7 @@ def test_tiling_does_not_change_fields():
     steps = 60
     cfg = _cfgs(steps)[2]  # gain + CPML on all faces
     base = None
-    for tune in ({"block": 64, "zchunk": 1, "graph_steps": 0},
+    for tune in ({"block": 64, "tile_x": 16, "zchunk": 1, "graph_steps": 0},
                  {"block": 128, "zchunk": 5, "graph_steps": 12, "max_blocks": 7},
                  {"block": 256, "zchunk": 64, "graph_steps": 60}):
         p = F.Plan(cfg, max_steps=steps, tuning=tune)

@@ -143,7 +143,7 @@ def test_edge_shapes_random_fields(shape, periodic, pml):
     cfg["probes"] = [(0, 0, 0, shape[2] - 1), (5, shape[0] - 1, shape[1] - 1, 0)]
     _say("edge", shape, periodic, pml)
     orc = run_oracle(cfg, steps)
-    for tune in ({"block": 64, "zchunk": 1, "graph_steps": 0},
+    for tune in ({"block": 64, "tile_x": 16, "zchunk": 1, "graph_steps": 0},
                  {"block": 256, "zchunk": 4, "graph_steps": 16, "max_blocks": 3}):
         gpu = run_gpu(cfg, steps, tuning=tune)
         err = field_rel_l2(gpu.fields(), orc.fields())
