@@ -61,7 +61,7 @@ struct Layout {
   size_t prof[3], psiE[3][2], psiH[2][3][2];
   size_t src[FD_MAXSRC];
   size_t probe;
-  size_t fluxT[FD_MAXFLUX], fluxf[FD_MAXFLUX], fluxacc[FD_MAXFLUX];
+  size_t fluxT[FD_MAXFLUX], fluxf[FD_MAXFLUX], fluxacc[FD_MAXFLUX], fluxring[FD_MAXFLUX], fluxprev[FD_MAXFLUX];
   size_t energy;
   size_t tiles[FD_NCLASS];
   size_t dft;
@@ -312,11 +312,17 @@ std::vector<std::pair<int, int>> z_chunks(const fdtd_plan* p, int zchunk) {
     if (p->g.pml_hi[2] > 0 && nz - p->g.pml_hi[2] > cuts.back()) cuts.push_back(nz - p->g.pml_hi[2]);
   }
   cuts.push_back(nz);
+  // A plane in a z slab moves 81 bytes per cell instead of 49 (the two psi
+  // arrays of each field), so slab segments get proportionally shorter chunks
+  // and their tiles take about as long as interior tiles.
+  const int zslab = std::max(1, (zchunk * 49 + 40) / 81);
   std::vector<std::pair<int, int>> out;
   for (size_t s = 0; s + 1 < cuts.size(); ++s) {
     const int a = cuts[s], b = cuts[s + 1];
     if (b <= a) continue;
-    const int pieces = (b - a + zchunk - 1) / zchunk;
+    const bool in_slab = pml_t(p, 2) > 0 && ((a == 0 && p->g.pml_lo[2] > 0) || (b == nz && p->g.pml_hi[2] > 0 && a >= nz - p->g.pml_hi[2]));
+    const int zc = in_slab ? zslab : zchunk;
+    const int pieces = (b - a + zc - 1) / zc;
     for (int q = 0; q < pieces; ++q) {
       const int k0 = a + (int)((int64_t)(b - a) * q / pieces);
       const int k1 = a + (int)((int64_t)(b - a) * (q + 1) / pieces);
@@ -379,15 +385,18 @@ int compute_layout(fdtd_plan* p, int64_t max_steps, Layout& L) {
       L.fluxT[f] = take(sizeof(double) * (size_t)p->nblk * (size_t)std::max<int64_t>(max_steps, 1));
       L.fluxf[f] = take(sizeof(double) * std::max<size_t>(p->flux[f].f.size(), 1));
       L.fluxacc[f] = take(sizeof(double) * 2 * 4 * p->flux[f].f.size() * (size_t)plane);
+      const bool dft = !p->flux[f].f.empty();
+      L.fluxring[f] = dft ? take(sizeof(float) * FD_DFT_RING * 4 * (size_t)plane) : 0;
+      L.fluxprev[f] = dft ? take(sizeof(double) * 2 * 4 * p->flux[f].f.size() * (size_t)plane) : 0;
     } else {
-      L.fluxT[f] = L.fluxf[f] = L.fluxacc[f] = 0;
+      L.fluxT[f] = L.fluxf[f] = L.fluxacc[f] = L.fluxring[f] = L.fluxprev[f] = 0;
     }
   }
   L.energy = p->ke > 0 ? take(sizeof(double) * (size_t)(max_steps / p->ke + 1) * (size_t)p->ntiles) : 0;
   for (int c = 0; c < FD_NCLASS; ++c) L.tiles[c] = take(sizeof(fd_tile) * (size_t)p->ntiles);
   size_t ndft = 0;
   for (const Flux& f : p->flux)
-    if (f.nf > 0) ndft += (size_t)((plane + 255) / 256);
+    if (f.nf > 0) ndft += (size_t)((plane + 63) / 64) * (size_t)((f.nf + FD_DFT_QB - 1) / FD_DFT_QB);
   L.dft = take(sizeof(fd_dft_tile) * std::max<size_t>(ndft, 1));
   if (p->have_opal) {
     size_t ns = 1;
@@ -431,7 +440,8 @@ int enqueue_step(fd_tile* const dtiles[FD_NCLASS], const std::vector<fd_tile>* t
   }
   if (par)
     for (int u = 1; u < nused; ++u) HIPCHK(hipStreamWaitEvent(st, fk->join[used[u]], 0));
-  if (dft_due && ndft > 0) HIPCHK(fd_launch_dft(ddft, ndft, maxnf, 256, s, st));
+  (void)maxnf;
+  if (dft_due && ndft > 0) HIPCHK(fd_launch_dft(ddft, ndft, s, st));
   return FDTD_OK;
 }
 
@@ -799,6 +809,8 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
     d.flux_decim[f] = fl.decim;
     d.flux_f[f] = at<double>(p, L.fluxf[f]);
     d.flux_acc[f] = at<double>(p, L.fluxacc[f]);
+    d.flux_ring[f] = fl.nf > 0 ? at<float>(p, L.fluxring[f]) : nullptr;
+    d.flux_prev[f] = fl.nf > 0 ? at<double>(p, L.fluxprev[f]) : nullptr;
     if (fl.nf > 0) {
       HIPCHK(hipMemcpyAsync(p->arena + L.fluxf[f], fl.f.data(), sizeof(double) * fl.nf, hipMemcpyHostToDevice, st));
       HIPCHK(hipStreamSynchronize(st));
@@ -963,13 +975,15 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
   p->dft.clear();
   for (int f = 0; f < d.nflux; ++f) {
     if (p->flux[f].nf == 0) continue;
-    for (int p0 = 0; p0 < plane; p0 += 256) {
-      fd_dft_tile t{};
-      t.d = p->ddesc;
-      t.flux = f;
-      t.p0 = p0;
-      p->dft.push_back(t);
-    }
+    for (int p0 = 0; p0 < plane; p0 += 64)
+      for (int q0 = 0; q0 < p->flux[f].nf; q0 += FD_DFT_QB) {
+        fd_dft_tile t{};
+        t.d = p->ddesc;
+        t.flux = f;
+        t.p0 = p0;
+        t.q0 = q0;
+        p->dft.push_back(t);
+      }
   }
   p->ddft = at<fd_dft_tile>(p, L.dft);
   if (!p->dft.empty())
@@ -1100,7 +1114,16 @@ int fdtd_read_flux(fdtd_plan* p, int32_t id, double* T, double* spec, int64_t* n
   if (spec && fl.nf > 0) {
     const size_t plane = (size_t)p->g.nx * p->g.ny;
     std::vector<double> acc(2 * 4 * (size_t)fl.nf * plane);
-    HIPCHK(hipMemcpyAsync(acc.data(), p->arena + p->L.fluxacc[id], sizeof(double) * acc.size(), hipMemcpyDeviceToHost, st));
+    // samples taken at steps 0, decim, ... < step; complete rings are already in
+    // the sums, the rest is added into a copy
+    const int64_t nsamp = (p->step + fl.decim - 1) / fl.decim;
+    const int pending = (int)(nsamp % FD_DFT_RING);
+    size_t src = p->L.fluxacc[id];
+    if (pending > 0) {
+      HIPCHK(fd_launch_dft_preview(p->ddft, (int)p->dft.size(), id, nsamp - pending, pending, st));
+      src = p->L.fluxprev[id];
+    }
+    HIPCHK(hipMemcpyAsync(acc.data(), p->arena + src, sizeof(double) * acc.size(), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     for (int q = 0; q < fl.nf; ++q) {
       double sum = 0.0;
@@ -1240,8 +1263,11 @@ int fdtd_class_bytes(const fdtd_plan* p, double* bytes) {
           }
     bytes[c] = acc;
   }
+  // per DFT launch: the sample (24 bytes read, 16 written per point), and once
+  // per ring the accumulators (128 bytes per point and frequency) and the ring
   double dft = 0.0;
-  for (const Flux& f : p->flux) dft += 128.0 * (double)f.nf * nx * ny;
+  for (const Flux& f : p->flux)
+    if (f.nf > 0) dft += (double)nx * ny * (40.0 + (128.0 * f.nf + 16.0 * FD_DFT_RING) / FD_DFT_RING);
   bytes[FD_NCLASS] = dft;
   return FDTD_OK;
 }
@@ -1284,7 +1310,7 @@ int fdtd_time_kernels(fdtd_plan* p, int64_t n, void* stream, double* ms, int64_t
       if (r) { cleanup(); return r; }
     }
     if (plan_dft_due(p, p->step + s) && !p->dft.empty()) {
-      const int r = record(FD_NCLASS, [&]() { return fd_launch_dft(p->ddft, (int)p->dft.size(), p->maxnf, 256, (int)s, st); });
+      const int r = record(FD_NCLASS, [&]() { return fd_launch_dft(p->ddft, (int)p->dft.size(), (int)s, st); });
       if (r) { cleanup(); return r; }
     }
   }

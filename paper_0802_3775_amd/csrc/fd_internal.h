@@ -8,6 +8,8 @@
 #define FD_MAXSRC 4
 #define FD_MAXPROBE 16
 #define FD_MAXFLUX 4
+#define FD_DFT_RING 32  // flux-plane samples buffered per DFT flush
+#define FD_DFT_QB 16    // frequencies per DFT work unit
 #define FD_MAXBLOCK 256   // threads per workgroup upper bound (launch bounds)
 
 // Per-material coefficients, FP32 (built in FP64 on the host, rounded once).
@@ -66,6 +68,8 @@ struct fd_desc {
   int flux_nf[FD_MAXFLUX], flux_decim[FD_MAXFLUX];
   const double* flux_f[FD_MAXFLUX];
   double* flux_acc[FD_MAXFLUX];  // [4][nf][plane][2]
+  float* flux_ring[FD_MAXFLUX];   // [FD_DFT_RING][4][plane] samples not yet added to flux_acc
+  double* flux_prev[FD_MAXFLUX];  // [4][nf][plane][2] flux_acc plus pending samples (reads)
   // energy
   int ke;
   int ntiles;
@@ -85,11 +89,13 @@ struct fd_tile {
   int pad;
 };
 
+// DFT work unit: 64 plane cells x 4 components x FD_DFT_QB frequencies.
 struct fd_dft_tile {
   const fd_desc* d;
   int flux;
   int p0;
-  long long pad;
+  int q0;
+  int pad;
 };
 
 // Tile classes: kernels specialised on the CPML slabs a tile touches (none, z
@@ -110,8 +116,9 @@ struct fd_xcd {
 // part == nullptr: grid-stride loop over the tiles with the plain XCD renumbering
 hipError_t fd_launch_step(int cls, const fd_tile* tiles, int ntiles, int tile_x, int block, int grid,
                           int s, const fd_xcd* part, hipStream_t st);
-hipError_t fd_launch_dft(const fd_dft_tile* tiles, int ntiles, int maxnf, int block, int s,
-                         hipStream_t st);
+hipError_t fd_launch_dft(const fd_dft_tile* tiles, int ntiles, int s, hipStream_t st);
+hipError_t fd_launch_dft_preview(const fd_dft_tile* tiles, int ntiles, int flux, long long first, int count,
+                                 hipStream_t st);
 hipError_t fd_launch_advance(fd_desc* const* descs, int n, long long k, hipStream_t st);
 hipError_t fd_launch_advance_one(fd_desc* d, long long k, hipStream_t st);
 hipError_t fd_launch_fill(void* p, size_t bytes, hipStream_t st);

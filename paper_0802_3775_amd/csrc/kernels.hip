@@ -229,25 +229,6 @@ __device__ __forceinline__ float h_from(const Ctx& x, int c, int w1, int p1, int
   return fmaf(-x.ch, d1 - d2, hold);
 }
 
-// The same values from global memory (used for the plane below a tile's z range).
-template <int PM>
-__device__ __forceinline__ float h_x(const Ctx& x, int i, int j, int k) {
-  const int o = k * x.plane + j * x.nx + i;
-  const int jp = nxt(j, x.ny, x.py), kp = nxt(k, x.nz, x.pz);
-  const float ez1 = jp >= 0 ? x.Ein[2][k * x.plane + jp * x.nx + i] : 0.0f;
-  const float ey1 = kp >= 0 ? x.Ein[1][kp * x.plane + j * x.nx + i] : 0.0f;
-  return h_from<PM>(x, 0, 1, j, 2, k, i, j, k, ez1, x.Ein[2][o], ey1, x.Ein[1][o], x.Hin[0][o], false);
-}
-
-template <int PM>
-__device__ __forceinline__ float h_y(const Ctx& x, int i, int j, int k) {
-  const int o = k * x.plane + j * x.nx + i;
-  const int ip = nxt(i, x.nx, x.px), kp = nxt(k, x.nz, x.pz);
-  const float ex1 = kp >= 0 ? x.Ein[0][kp * x.plane + j * x.nx + i] : 0.0f;
-  const float ez1 = ip >= 0 ? x.Ein[2][k * x.plane + j * x.nx + ip] : 0.0f;
-  return h_from<PM>(x, 1, 2, k, 0, i, i, j, k, ex1, x.Ein[0][o], ez1, x.Ein[2][o], x.Hin[1][o], false);
-}
-
 // Workgroup barrier for LDS traffic only.  Within a step no workgroup reads
 // global memory that another thread of the step writes (inputs and outputs are
 // separate buffers), so the barrier waits for outstanding LDS operations but
@@ -441,20 +422,40 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
     }
   };
 
+  // Loads are issued in the order their values are consumed (the memory
+  // counter retires in order): plane k0, the inputs of H^{n+1/2} at plane
+  // k0-1 (the march carries H of the plane below), then the two Stages.
   Stage SA, SB;
   load_e(k0, SA, true);
+  const int km = prv(k0, x.nz, x.pz);
+  const bool pro = act && km >= 0;
+  const int jp = nxt(j, x.ny, x.py), ip = nxt(i, x.nx, x.px);
+  float pEz, pEzj, pEzi, pEy, pEx, pHx, pHy;
+  {
+    const int zm = pro ? km * x.plane : 0;
+    const uint32_t om = pro ? zm + c : 0;
+    const uint32_t ojp = (pro && jp >= 0) ? zm + jp * x.nx + i : 0;
+    const uint32_t oip = (pro && ip >= 0) ? zm + j * x.nx + ip : 0;
+    pEz = x.Ein[2][om];
+    pEzj = x.Ein[2][ojp];
+    pEzi = x.Ein[2][oip];
+    pEy = x.Ein[1][om];
+    pEx = x.Ein[0][om];
+    pHx = x.Hin[0][om];
+    pHy = x.Hin[1][om];
+  }
   store_e(0, SA);
   load_e(k0 + 1, SA, true);
   load_h(k0, SA, true);
   load_e(k0 + 2, SB, k0 + 1 < k1);
   load_h(k0 + 1, SB, k0 + 1 < k1);
+  // H^{n+1/2} at (i, j, k0-1); E^n at (i, j, k0) is already in LDS buffer 0
   float hxm = 0.0f, hym = 0.0f;
-  {
-    const int km = prv(k0, x.nz, x.pz);
-    if (act && km >= 0) {
-      hxm = h_x<PM>(x, i, j, km);
-      hym = h_y<PM>(x, i, j, km);
-    }
+  if (pro) {
+    const float ey1 = s.E[0][1][own_slot], ex1 = s.E[0][0][own_slot];
+    const float ezj = jp >= 0 ? pEzj : 0.0f, ezi = ip >= 0 ? pEzi : 0.0f;
+    hxm = h_from<PM>(x, 0, 1, j, 2, km, i, j, km, ezj, pEz, ey1, pEy, pHx, false);
+    hym = h_from<PM>(x, 1, 2, km, 0, i, i, j, km, ex1, pEx, ezi, pEz, pHy, false);
   }
 
   // plane k uses LDS E buffer cb = (k - k0) & 1, a compile-time constant in
@@ -704,43 +705,117 @@ __global__ __launch_bounds__(FD_MAXBLOCK) void step_kernel(const fd_tile* __rest
   }
 }
 
-// Running DFT of the flux-plane fields, every decim steps of each realization.
-__global__ __launch_bounds__(FD_MAXBLOCK) void dft_kernel(const fd_dft_tile* __restrict__ tiles, int s) {
-  const fd_dft_tile t = tiles[blockIdx.x];
-  const cdesc* d = (const cdesc*)t.d;
-  const int fl = t.flux;
-  const int q = blockIdx.y;
-  if (q >= d->flux_nf[fl]) return;
-  const long long n = d->step + s;
-  if (n % d->flux_decim[fl] != 0) return;
-  const int p = t.p0 + (int)threadIdx.x;
-  if (p >= d->plane) return;
+// ------------------------------------------------------------- flux DFT
+// Running DFT of the flux-plane fields (E^n at the plane, H^{n+1/2} averaged
+// onto it), sampled every decim steps.  Samples go to a ring of FD_DFT_RING
+// planes; the launch that takes the ring's last sample adds the whole ring to
+// the FP64 accumulators, so each accumulator (16 bytes per point, component and
+// frequency) is read and written once per ring rather than once per sample.
+// The flush is a small dense product (samples x weights e^{i 2 pi f t_m});
+// the weights of one frequency block are tabulated in LDS.
+
+// Sample of component c (0 Ex, 1 Ey, 2 Hx, 3 Hy) at plane point p after step n.
+__device__ __forceinline__ float dft_sample(const cdesc* d, int fl, int c, int p, long long n) {
   const int par = (int)(n & 1);
   const int kf = d->flux_k[fl];
   const int km = kf > 0 ? kf - 1 : d->nz - 1;
-  const int of = kf * d->plane + p, om = km * d->plane + p;
-  const gf* ex = G((const float*)d->E[par][0]);
-  const gf* ey = G((const float*)d->E[par][1]);
-  const gf* hx = G((const float*)d->H[par ^ 1][0]);
-  const gf* hy = G((const float*)d->H[par ^ 1][1]);
-  const double v[4] = {(double)ex[of], (double)ey[of], 0.5 * ((double)hx[om] + (double)hx[of]),
-                       0.5 * ((double)hy[om] + (double)hy[of])};
-  const double f = G((const double*)d->flux_f[fl])[q];
-  const double w = (double)d->flux_decim[fl] * d->dt;
-  double sE, cE, sH, cH;
-  sincos(kTwoPi * f * (double)n * d->dt, &sE, &cE);
-  sincos(kTwoPi * f * ((double)n + 0.5) * d->dt, &sH, &cH);
-  const int nf = d->flux_nf[fl];
-  gd* acc = G(d->flux_acc[fl]);
-#pragma unroll
-  for (int cpt = 0; cpt < 4; ++cpt) {
-    const size_t at = 2 * (((size_t)cpt * nf + q) * d->plane + p);
-    const double cr = cpt < 2 ? cE : cH, si = cpt < 2 ? sE : sH;
-    const double re = acc[at] + v[cpt] * cr * w;
-    const double im = acc[at + 1] + v[cpt] * si * w;
-    acc[at] = re;
-    acc[at + 1] = im;
+  if (c < 2) return G((const float*)d->E[par][c])[(size_t)kf * d->plane + p];
+  const gf* h = G((const float*)d->H[par ^ 1][c - 2]);
+  return 0.5f * (h[(size_t)km * d->plane + p] + h[(size_t)kf * d->plane + p]);
+}
+
+// out = in + sum over the samples m < count (sample index first + m, step
+// (first + m) decim) of v_m e^{i 2 pi f t_m} decim dt, for the work unit's 64
+// points, 4 components and FD_DFT_QB frequencies.  Sample m == fresh is taken
+// from the fields after step nfresh instead of the ring.
+__device__ void dft_flush(const cdesc* d, int fl, int q0, int p0, long long first, int count, int fresh,
+                          long long nfresh, const gd* in, gd* out, double (*tab)[FD_DFT_RING][4]) {
+  const int nf = d->flux_nf[fl], plane = d->plane, decim = d->flux_decim[fl];
+  const double dt = d->dt;
+  const gd* fr = G((const double*)d->flux_f[fl]);
+  for (int idx = threadIdx.x; idx < FD_DFT_QB * FD_DFT_RING; idx += blockDim.x) {
+    const int qq = idx / FD_DFT_RING, m = idx % FD_DFT_RING;
+    const int q = q0 + qq;
+    double se = 0.0, ce = 0.0, sh = 0.0, ch = 0.0;
+    if (q < nf && m < count) {
+      const double f = fr[q];
+      const long long nm = (first + m) * decim;
+      sincos(kTwoPi * f * (double)nm * dt, &se, &ce);
+      sincos(kTwoPi * f * ((double)nm + 0.5) * dt, &sh, &ch);
+    }
+    tab[qq][m][0] = ce;
+    tab[qq][m][1] = se;
+    tab[qq][m][2] = ch;
+    tab[qq][m][3] = sh;
   }
+  __syncthreads();
+  const gf* ring = G((const float*)d->flux_ring[fl]);
+  const double w = (double)decim * dt;
+  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const int p = p0 + lane;
+  if (p >= plane) return;
+  for (int c = threadIdx.x >> 6; c < 4; c += nw) {
+    double sv[FD_DFT_RING];
+#pragma unroll
+    for (int m = 0; m < FD_DFT_RING; ++m) {
+      float v = 0.0f;
+      if (m == fresh) v = dft_sample(d, fl, c, p, nfresh);
+      else if (m < count) v = ring[((size_t)m * 4 + c) * plane + p];
+      sv[m] = (double)v;
+    }
+    const int ph = c < 2 ? 0 : 2;
+    for (int qq = 0; qq < FD_DFT_QB; ++qq) {
+      const int q = q0 + qq;
+      if (q >= nf) break;
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int m = 0; m < FD_DFT_RING; ++m) {
+        re = fma(sv[m], tab[qq][m][ph], re);
+        im = fma(sv[m], tab[qq][m][ph + 1], im);
+      }
+      const size_t at = 2 * (((size_t)c * nf + q) * plane + p);
+      out[at] = in[at] + re * w;
+      out[at + 1] = in[at + 1] + im * w;
+    }
+  }
+}
+
+// In the step sequence: every decim steps of each realization, store the sample
+// in its ring slot, or (last slot) add the ring and the sample to the sums.
+__global__ __launch_bounds__(256) void dft_kernel(const fd_dft_tile* __restrict__ tiles, int s) {
+  __shared__ double tab[FD_DFT_QB][FD_DFT_RING][4];
+  const fd_dft_tile t = tiles[blockIdx.x];
+  const cdesc* d = (const cdesc*)t.d;
+  const int fl = t.flux;
+  if (d->flux_nf[fl] == 0) return;
+  const long long n = d->step + s;
+  const int decim = d->flux_decim[fl];
+  if (n % decim != 0) return;
+  const long long si = n / decim;
+  const int slot = (int)(si % FD_DFT_RING);
+  if (slot < FD_DFT_RING - 1) {
+    if (t.q0 != 0) return;
+    const int plane = d->plane, p = t.p0 + (int)(threadIdx.x & 63);
+    if (p >= plane) return;
+    gf* ring = G(d->flux_ring[fl]);
+    for (int c = threadIdx.x >> 6; c < 4; c += blockDim.x >> 6)
+      ring[((size_t)slot * 4 + c) * plane + p] = dft_sample(d, fl, c, p, n);
+    return;
+  }
+  gd* acc = G(d->flux_acc[fl]);
+  dft_flush(d, fl, t.q0, t.p0, si - (FD_DFT_RING - 1), FD_DFT_RING, FD_DFT_RING - 1, n, acc, acc, tab);
+}
+
+// For reads: flux_prev = flux_acc + the count samples waiting in the ring
+// (sample indices first ...), for flux plane fl; the sums themselves are kept.
+__global__ __launch_bounds__(256) void dft_preview_kernel(const fd_dft_tile* __restrict__ tiles, int fl,
+                                                          long long first, int count) {
+  __shared__ double tab[FD_DFT_QB][FD_DFT_RING][4];
+  const fd_dft_tile t = tiles[blockIdx.x];
+  if (t.flux != fl) return;
+  const cdesc* d = (const cdesc*)t.d;
+  if (d->flux_nf[fl] == 0) return;
+  dft_flush(d, fl, t.q0, t.p0, first, count, -1, 0, G((const double*)d->flux_acc[fl]), G(d->flux_prev[fl]), tab);
 }
 
 __global__ void advance_kernel(fd_desc* const* descs, int n, long long k) {
@@ -898,9 +973,17 @@ hipError_t fd_launch_step(int cls, const fd_tile* tiles, int ntiles, int tile_x,
   }
 }
 
-hipError_t fd_launch_dft(const fd_dft_tile* tiles, int ntiles, int maxnf, int block, int s, hipStream_t st) {
-  if (ntiles <= 0 || maxnf <= 0) return hipSuccess;
-  dft_kernel<<<dim3(ntiles, maxnf), block, 0, st>>>(tiles, s);
+hipError_t fd_launch_dft(const fd_dft_tile* tiles, int ntiles, int s, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  dft_kernel<<<ntiles, 256, 0, st>>>(tiles, s);
+  return hipGetLastError();
+}
+
+hipError_t fd_launch_dft_preview(const fd_dft_tile* tiles, int ntiles, int flux, long long first, int count,
+                                 hipStream_t st) {
+  if (ntiles <= 0 || count <= 0) return hipSuccess;
+  if (count > FD_DFT_RING || first < 0) return hipErrorInvalidValue;
+  dft_preview_kernel<<<ntiles, 256, 0, st>>>(tiles, flux, first, count);
   return hipGetLastError();
 }
 
