@@ -82,8 +82,9 @@ def copy_calibration():
 def kernel_table(plan, nsteps):
     """Per kernel class: average launch duration (hipEvents around each launch on
     the launch stream) and the algorithmic bytes of one launch (libfdtd counts
-    them per cell: 49 B, +32 B per CPML slab axis, +84 B per gain cell; DFT
-    128 B per plane point and frequency)."""
+    them per cell: 49 B, +32 B per CPML slab axis, +84 B per gain cell; a DFT
+    launch stores a 40 B/point plane sample and, once per 32-sample ring, moves
+    128 B per plane point and frequency: averaged per launch)."""
     from paper_0802_3775_amd import fdtd
     ms, cnt = plan.time_kernels(nsteps)
     cells = plan.class_cells()

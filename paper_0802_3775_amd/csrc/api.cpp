@@ -62,6 +62,7 @@ struct Layout {
   size_t src[FD_MAXSRC];
   size_t probe;
   size_t fluxT[FD_MAXFLUX], fluxf[FD_MAXFLUX], fluxacc[FD_MAXFLUX], fluxring[FD_MAXFLUX], fluxprev[FD_MAXFLUX];
+  size_t fluxrot[FD_MAXFLUX];
   size_t energy;
   size_t tiles[FD_NCLASS];
   size_t dft;
@@ -388,15 +389,16 @@ int compute_layout(fdtd_plan* p, int64_t max_steps, Layout& L) {
       const bool dft = !p->flux[f].f.empty();
       L.fluxring[f] = dft ? take(sizeof(float) * FD_DFT_RING * 4 * (size_t)plane) : 0;
       L.fluxprev[f] = dft ? take(sizeof(double) * 2 * 4 * p->flux[f].f.size() * (size_t)plane) : 0;
+      L.fluxrot[f] = dft ? take(sizeof(double) * 6 * p->flux[f].f.size()) : 0;
     } else {
-      L.fluxT[f] = L.fluxf[f] = L.fluxacc[f] = L.fluxring[f] = L.fluxprev[f] = 0;
+      L.fluxT[f] = L.fluxf[f] = L.fluxacc[f] = L.fluxring[f] = L.fluxprev[f] = L.fluxrot[f] = 0;
     }
   }
   L.energy = p->ke > 0 ? take(sizeof(double) * (size_t)(max_steps / p->ke + 1) * (size_t)p->ntiles) : 0;
   for (int c = 0; c < FD_NCLASS; ++c) L.tiles[c] = take(sizeof(fd_tile) * (size_t)p->ntiles);
   size_t ndft = 0;
   for (const Flux& f : p->flux)
-    if (f.nf > 0) ndft += (size_t)((plane + 63) / 64) * (size_t)((f.nf + FD_DFT_QB - 1) / FD_DFT_QB);
+    if (f.nf > 0) ndft += (size_t)((plane + FD_DFT_PTS - 1) / FD_DFT_PTS) * (size_t)((f.nf + FD_DFT_QB - 1) / FD_DFT_QB);
   L.dft = take(sizeof(fd_dft_tile) * std::max<size_t>(ndft, 1));
   if (p->have_opal) {
     size_t ns = 1;
@@ -811,6 +813,21 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
     d.flux_acc[f] = at<double>(p, L.fluxacc[f]);
     d.flux_ring[f] = fl.nf > 0 ? at<float>(p, L.fluxring[f]) : nullptr;
     d.flux_prev[f] = fl.nf > 0 ? at<double>(p, L.fluxprev[f]) : nullptr;
+    d.flux_rot[f] = fl.nf > 0 ? at<double>(p, L.fluxrot[f]) : nullptr;
+    if (fl.nf > 0) {
+      // unit phasors of one ring, one sample interval and half a step, per frequency
+      std::vector<double> rot(6 * (size_t)fl.nf);
+      for (int q = 0; q < fl.nf; ++q) {
+        const double w = 2.0 * kPi * fl.f[(size_t)q] * p->dt;
+        const double a[3] = {w * (double)fl.decim * FD_DFT_RING, w * (double)fl.decim, 0.5 * w};
+        for (int r = 0; r < 3; ++r) {
+          rot[6 * (size_t)q + 2 * r] = std::cos(a[r]);
+          rot[6 * (size_t)q + 2 * r + 1] = std::sin(a[r]);
+        }
+      }
+      HIPCHK(hipMemcpyAsync(p->arena + L.fluxrot[f], rot.data(), sizeof(double) * rot.size(), hipMemcpyHostToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
     if (fl.nf > 0) {
       HIPCHK(hipMemcpyAsync(p->arena + L.fluxf[f], fl.f.data(), sizeof(double) * fl.nf, hipMemcpyHostToDevice, st));
       HIPCHK(hipStreamSynchronize(st));
@@ -975,7 +992,7 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
   p->dft.clear();
   for (int f = 0; f < d.nflux; ++f) {
     if (p->flux[f].nf == 0) continue;
-    for (int p0 = 0; p0 < plane; p0 += 64)
+    for (int p0 = 0; p0 < plane; p0 += FD_DFT_PTS)
       for (int q0 = 0; q0 < p->flux[f].nf; q0 += FD_DFT_QB) {
         fd_dft_tile t{};
         t.d = p->ddesc;

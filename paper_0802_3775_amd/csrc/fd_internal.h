@@ -9,7 +9,8 @@
 #define FD_MAXPROBE 16
 #define FD_MAXFLUX 4
 #define FD_DFT_RING 32  // flux-plane samples buffered per DFT flush
-#define FD_DFT_QB 16    // frequencies per DFT work unit
+#define FD_DFT_QB 8     // frequencies per DFT work unit
+#define FD_DFT_PTS 64   // plane points per DFT work unit (one per lane)
 #define FD_MAXBLOCK 256   // threads per workgroup upper bound (launch bounds)
 
 // Per-material coefficients, FP32 (built in FP64 on the host, rounded once).
@@ -69,6 +70,7 @@ struct fd_desc {
   const double* flux_f[FD_MAXFLUX];
   double* flux_acc[FD_MAXFLUX];  // [4][nf][plane][2]
   float* flux_ring[FD_MAXFLUX];   // [FD_DFT_RING][4][plane] samples not yet added to flux_acc
+  const double* flux_rot[FD_MAXFLUX];  // [nf][6]: e^{i 2pi f RING decim dt}, e^{i 2pi f decim dt}, e^{i pi f dt}
   double* flux_prev[FD_MAXFLUX];  // [4][nf][plane][2] flux_acc plus pending samples (reads)
   // energy
   int ke;
@@ -89,7 +91,7 @@ struct fd_tile {
   int pad;
 };
 
-// DFT work unit: 64 plane cells x 4 components x FD_DFT_QB frequencies.
+// DFT work unit: FD_DFT_PTS plane points x 4 components x FD_DFT_QB frequencies.
 struct fd_dft_tile {
   const fd_desc* d;
   int flux;

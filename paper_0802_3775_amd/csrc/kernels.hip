@@ -26,7 +26,6 @@
 namespace {
 
 constexpr float kTwoPiF = 6.28318530717958647692f;
-constexpr double kTwoPi = 6.283185307179586476925286766559;
 
 // ------------------------------------------------------------------ Philox
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
@@ -724,58 +723,114 @@ __device__ __forceinline__ float dft_sample(const cdesc* d, int fl, int c, int p
   return 0.5f * (h[(size_t)km * d->plane + p] + h[(size_t)kf * d->plane + p]);
 }
 
+// complex product and integer power (square and multiply)
+__device__ __forceinline__ void cmul(double ar, double ai, double br, double bi, double& cr, double& ci) {
+  cr = ar * br - ai * bi;
+  ci = ar * bi + ai * br;
+}
+__device__ __forceinline__ void cpow(double br, double bi, long long e, double& rr, double& ri) {
+  rr = 1.0;
+  ri = 0.0;
+  while (e > 0) {
+    if (e & 1) cmul(rr, ri, br, bi, rr, ri);
+    cmul(br, bi, br, bi, br, bi);
+    e >>= 1;
+  }
+}
+
 // out = in + sum over the samples m < count (sample index first + m, step
-// (first + m) decim) of v_m e^{i 2 pi f t_m} decim dt, for the work unit's 64
-// points, 4 components and FD_DFT_QB frequencies.  Sample m == fresh is taken
-// from the fields after step nfresh instead of the ring.
+// (first + m) decim) of v_m e^{i 2 pi f t_m} decim dt, for the work unit's
+// FD_DFT_PTS points (one per lane), 4 components (one per wave) and FD_DFT_QB
+// frequencies.  Sample m == fresh is taken from the fields after step nfresh
+// instead of the ring.  first is a multiple of FD_DFT_RING; the weights are
+// built from three unit phasors per frequency set up on the host (a ring, one
+// sample and half a step of rotation): e^{i 2 pi f t_m} = R^(first/RING) S^m,
+// and H samples carry the extra half step.
 __device__ void dft_flush(const cdesc* d, int fl, int q0, int p0, long long first, int count, int fresh,
-                          long long nfresh, const gd* in, gd* out, double (*tab)[FD_DFT_RING][4]) {
+                          long long nfresh, const gd* in, gd* out, double (*tab)[FD_DFT_RING][4],
+                          double (*base)[4], float (*samp)[FD_DFT_RING][64]) {
   const int nf = d->flux_nf[fl], plane = d->plane, decim = d->flux_decim[fl];
   const double dt = d->dt;
-  const gd* fr = G((const double*)d->flux_f[fl]);
+  const gd* rot = G((const double*)d->flux_rot[fl]);  // [nf][6]: R, S, half step
+  if (threadIdx.x < FD_DFT_QB) {
+    const int q = q0 + (int)threadIdx.x;
+    double br = 1.0, bi = 0.0, hr = 1.0, hi = 0.0;
+    if (q < nf) {
+      cpow(rot[6 * q], rot[6 * q + 1], first / FD_DFT_RING, br, bi);
+      hr = rot[6 * q + 4];
+      hi = rot[6 * q + 5];
+    }
+    base[threadIdx.x][0] = br;
+    base[threadIdx.x][1] = bi;
+    base[threadIdx.x][2] = hr;
+    base[threadIdx.x][3] = hi;
+  }
+  __syncthreads();
   for (int idx = threadIdx.x; idx < FD_DFT_QB * FD_DFT_RING; idx += blockDim.x) {
     const int qq = idx / FD_DFT_RING, m = idx % FD_DFT_RING;
     const int q = q0 + qq;
-    double se = 0.0, ce = 0.0, sh = 0.0, ch = 0.0;
+    double ce = 0.0, se = 0.0, chh = 0.0, shh = 0.0;
     if (q < nf && m < count) {
-      const double f = fr[q];
-      const long long nm = (first + m) * decim;
-      sincos(kTwoPi * f * (double)nm * dt, &se, &ce);
-      sincos(kTwoPi * f * ((double)nm + 0.5) * dt, &sh, &ch);
+      double sr, si;
+      cpow(rot[6 * q + 2], rot[6 * q + 3], m, sr, si);
+      const double* b0 = base[qq];
+      cmul(b0[0], b0[1], sr, si, ce, se);
+      cmul(ce, se, b0[2], b0[3], chh, shh);
     }
     tab[qq][m][0] = ce;
     tab[qq][m][1] = se;
-    tab[qq][m][2] = ch;
-    tab[qq][m][3] = sh;
+    tab[qq][m][2] = chh;
+    tab[qq][m][3] = shh;
   }
   __syncthreads();
   const gf* ring = G((const float*)d->flux_ring[fl]);
   const double w = (double)decim * dt;
-  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int p = p0 + lane;
   if (p >= plane) return;
-  for (int c = threadIdx.x >> 6; c < 4; c += nw) {
-    double sv[FD_DFT_RING];
+  const int wv = threadIdx.x >> 6;
+  for (int c = wv; c < 4; c += blockDim.x >> 6) {  // one component per wave
+    // the wave's samples go to LDS (8 loads in flight at a time); samples
+    // m >= count have zero weight but must be finite
+    float* sm = samp[wv][0];
+    for (int m0 = 0; m0 < FD_DFT_RING; m0 += 8) {
+      float v8[8];
 #pragma unroll
-    for (int m = 0; m < FD_DFT_RING; ++m) {
-      float v = 0.0f;
-      if (m == fresh) v = dft_sample(d, fl, c, p, nfresh);
-      else if (m < count) v = ring[((size_t)m * 4 + c) * plane + p];
-      sv[m] = (double)v;
+      for (int u = 0; u < 8; ++u) {
+        const int m = m0 + u;
+        v8[u] = ring[((size_t)(m < count ? m : 0) * 4 + c) * plane + p];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sm[(m0 + u) * 64 + lane] = v8[u];
+    }
+    if (fresh >= 0) sm[fresh * 64 + lane] = dft_sample(d, fl, c, p, nfresh);
+    // the block's sums, loaded ahead of the products
+    const int nq = min(FD_DFT_QB, nf - q0);
+    double ar[FD_DFT_QB], ai[FD_DFT_QB], re[FD_DFT_QB], im[FD_DFT_QB];
+#pragma unroll
+    for (int qq = 0; qq < FD_DFT_QB; ++qq) {
+      const size_t at = 2 * (((size_t)c * nf + q0 + (qq < nq ? qq : 0)) * plane + p);
+      ar[qq] = in[at];
+      ai[qq] = in[at + 1];
+      re[qq] = im[qq] = 0.0;
     }
     const int ph = c < 2 ? 0 : 2;
-    for (int qq = 0; qq < FD_DFT_QB; ++qq) {
-      const int q = q0 + qq;
-      if (q >= nf) break;
-      double re = 0.0, im = 0.0;
+#pragma unroll 2
+    for (int m = 0; m < FD_DFT_RING; ++m) {
+      const double v = (double)sm[m * 64 + lane];
 #pragma unroll
-      for (int m = 0; m < FD_DFT_RING; ++m) {
-        re = fma(sv[m], tab[qq][m][ph], re);
-        im = fma(sv[m], tab[qq][m][ph + 1], im);
+      for (int qq = 0; qq < FD_DFT_QB; ++qq) {
+        re[qq] = fma(v, tab[qq][m][ph], re[qq]);
+        im[qq] = fma(v, tab[qq][m][ph + 1], im[qq]);
       }
-      const size_t at = 2 * (((size_t)c * nf + q) * plane + p);
-      out[at] = in[at] + re * w;
-      out[at + 1] = in[at + 1] + im * w;
+    }
+#pragma unroll
+    for (int qq = 0; qq < FD_DFT_QB; ++qq) {
+      if (qq < nq) {
+        const size_t at = 2 * (((size_t)c * nf + q0 + qq) * plane + p);
+        out[at] = ar[qq] + re[qq] * w;
+        out[at + 1] = ai[qq] + im[qq] * w;
+      }
     }
   }
 }
@@ -802,8 +857,10 @@ __global__ __launch_bounds__(256) void dft_kernel(const fd_dft_tile* __restrict_
       ring[((size_t)slot * 4 + c) * plane + p] = dft_sample(d, fl, c, p, n);
     return;
   }
+  __shared__ double base[FD_DFT_QB][4];
+  __shared__ float samp[4][FD_DFT_RING][64];
   gd* acc = G(d->flux_acc[fl]);
-  dft_flush(d, fl, t.q0, t.p0, si - (FD_DFT_RING - 1), FD_DFT_RING, FD_DFT_RING - 1, n, acc, acc, tab);
+  dft_flush(d, fl, t.q0, t.p0, si - (FD_DFT_RING - 1), FD_DFT_RING, FD_DFT_RING - 1, n, acc, acc, tab, base, samp);
 }
 
 // For reads: flux_prev = flux_acc + the count samples waiting in the ring
@@ -815,7 +872,10 @@ __global__ __launch_bounds__(256) void dft_preview_kernel(const fd_dft_tile* __r
   if (t.flux != fl) return;
   const cdesc* d = (const cdesc*)t.d;
   if (d->flux_nf[fl] == 0) return;
-  dft_flush(d, fl, t.q0, t.p0, first, count, -1, 0, G((const double*)d->flux_acc[fl]), G(d->flux_prev[fl]), tab);
+  __shared__ double base[FD_DFT_QB][4];
+  __shared__ float samp[4][FD_DFT_RING][64];
+  dft_flush(d, fl, t.q0, t.p0, first, count, -1, 0, G((const double*)d->flux_acc[fl]), G(d->flux_prev[fl]), tab,
+            base, samp);
 }
 
 __global__ void advance_kernel(fd_desc* const* descs, int n, long long k) {
