@@ -942,6 +942,7 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
         }
         for (int q = 0; q < d.nflux; ++q)
           if (d.flux_k[q] >= t.k0 && d.flux_k[q] < t.k1) t.fmask |= 1u << q;
+        if (d.pml_t[2] && (t.k0 < d.pml_lo[2] || t.k1 > p->g.nz - d.pml_hi[2])) t.flags |= FD_TILE_ZSLAB;
         // A tile needs the CPML code if any H value it evaluates lies in a slab:
         // its own cells, the x-1 / y-1 neighbours it recomputes, and plane k0-1.
         // (Slabs only exist on PEC axes, so no wrap-around is involved.)

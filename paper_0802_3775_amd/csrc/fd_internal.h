@@ -88,8 +88,9 @@ struct fd_tile {
   int tidx, blk;
   // sources, probes and flux planes that touch the tile (bit q = entry q)
   unsigned srcmask, pmask, fmask;
-  int pad;
+  int flags;  // FD_TILE_ZSLAB: some plane of [k0, k1) lies in a z CPML slab
 };
+#define FD_TILE_ZSLAB 1
 
 // DFT work unit: FD_DFT_PTS plane points x 4 components x FD_DFT_QB frequencies.
 struct fd_dft_tile {

@@ -274,7 +274,11 @@ struct Lds {
   float probe[FD_MAXPROBE];  // probe samples of the tile, stored after the z march
 };
 
-template <int TX, int PM, bool GAIN>
+// ZT: the tile's z range holds z-slab planes.  Without them the z march drops
+// every z-CPML test (PMM), so interior tiles of a CPML launch run the same
+// code as tiles of a plain launch; the plane below the range still takes the
+// general path.
+template <int TX, int PM, bool GAIN, bool ZT>
 __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   const cdesc* d = (const cdesc*)tl.d;
   constexpr int W = Lds<TX>::W;
@@ -388,7 +392,8 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
     }
   };
   const R32<const uint8_t> matp{(const gu8*)d->mat};
-  constexpr bool ZP = PM == 4;  // z-slab psi prefetched with the plane (z-only CPML tiles)
+  constexpr int PMM = ZT ? PM : (PM & 3);  // CPML axes the march handles
+  constexpr bool ZP = ZT && PM == 4;       // z-slab psi prefetched with the plane (z-only CPML tiles)
   auto load_h = [&](int kk, Stage& S, bool live) {
     kk = live ? kk : 0;
     const int zo = kk * x.plane;
@@ -490,9 +495,9 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       const float* Ey1 = s.E[nb][1];
       const int a = own_slot;
       if (act) {
-        hx = h_from<PM, ZP>(x, 0, 1, j, 2, k, i, j, k, Ez[a + W], Ez[a], Ey1[a], Ey[a], S.ho[0], true, sz, c, S.ph[0], S.gh);
-        hy = h_from<PM, ZP>(x, 1, 2, k, 0, i, i, j, k, Ex1[a], Ex[a], Ez[a + 1], Ez[a], S.ho[1], true, sz, c, S.ph[1], S.gh);
-        hz = h_from<PM, ZP>(x, 2, 0, i, 1, j, i, j, k, Ey[a + 1], Ey[a], Ex[a + W], Ex[a], S.ho[2], true, sz, c, 0.0f, S.gh);
+        hx = h_from<PMM, ZP>(x, 0, 1, j, 2, k, i, j, k, Ez[a + W], Ez[a], Ey1[a], Ey[a], S.ho[0], true, sz, c, S.ph[0], S.gh);
+        hy = h_from<PMM, ZP>(x, 1, 2, k, 0, i, i, j, k, Ex1[a], Ex[a], Ez[a + 1], Ez[a], S.ho[1], true, sz, c, S.ph[1], S.gh);
+        hz = h_from<PMM, ZP>(x, 2, 0, i, 1, j, i, j, k, Ey[a + 1], Ey[a], Ex[a + W], Ex[a], S.ho[2], true, sz, c, 0.0f, S.gh);
         x.Hout[0][o] = hx;
         x.Hout[1][o] = hy;
         x.Hout[2][o] = hz;
@@ -505,18 +510,18 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         if (lh) {
           // cell (i0-1, j0+t): LDS column 0, row t+1
           const int e = (t + 1) * W;
-          const float hyv = h_from<PM, ZP>(x, 1, 2, k, 0, hgi, hgi, hgj, k, Ex1[e], Ex[e], Ez[e + 1], Ez[e], S.hh[1],
+          const float hyv = h_from<PMM, ZP>(x, 1, 2, k, 0, hgi, hgi, hgj, k, Ex1[e], Ex[e], Ez[e + 1], Ez[e], S.hh[1],
                                            false, sz, h_off, S.phh[1], S.gh);
-          const float hzv = h_from<PM, ZP>(x, 2, 0, hgi, 1, hgj, hgi, hgj, k, Ey[e + 1], Ey[e], Ex[e + W], Ex[e],
+          const float hzv = h_from<PMM, ZP>(x, 2, 0, hgi, 1, hgj, hgi, hgj, k, Ey[e + 1], Ey[e], Ex[e + W], Ex[e],
                                            S.hh[2], false, sz, h_off, 0.0f, S.gh);
           s.H[1][(t + 1) * (TX + 1)] = hyv;
           s.H[2][(t + 1) * (TX + 1)] = hzv;
         } else {
           // cell (i0+q-1, j0-1): LDS row 0, column q
           const int q = t - TY + 1;
-          const float hxv = h_from<PM, ZP>(x, 0, 1, hgj, 2, k, hgi, hgj, k, Ez[W + q], Ez[q], Ey1[q], Ey[q], S.hh[0],
+          const float hxv = h_from<PMM, ZP>(x, 0, 1, hgj, 2, k, hgi, hgj, k, Ez[W + q], Ez[q], Ey1[q], Ey[q], S.hh[0],
                                            false, sz, h_off, S.phh[0], S.gh);
-          const float hzv = h_from<PM, ZP>(x, 2, 0, hgi, 1, hgj, hgi, hgj, k, Ey[q + 1], Ey[q], Ex[W + q], Ex[q],
+          const float hzv = h_from<PMM, ZP>(x, 2, 0, hgi, 1, hgj, hgi, hgj, k, Ey[q + 1], Ey[q], Ex[W + q], Ex[q],
                                            S.hh[2], false, sz, h_off, 0.0f, S.gh);
           s.H[0][q] = hxv;
           s.H[2][q] = hzv;
@@ -574,25 +579,25 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       }
       if (!((!x.py && j == 0) || (!x.pz && k == 0))) {  // Ex: d/dy Hz - d/dz Hy
         float d1 = hz - hz_jm, d2 = hy - hym;
-        if (PM) {
-          d1 = stretch<false, PM>(x, 0, 1, j, i, j, k, d1, true);
-          d2 = ZP ? stretch_z<false>(x, 0, S.ge, sz, c, d2, true, S.pe[0]) : stretch<false, PM>(x, 0, 2, k, i, j, k, d2, true);
+        if (PMM) {
+          d1 = stretch<false, PMM>(x, 0, 1, j, i, j, k, d1, true);
+          d2 = ZP ? stretch_z<false>(x, 0, S.ge, sz, c, d2, true, S.pe[0]) : stretch<false, PMM>(x, 0, 2, k, i, j, k, d2, true);
         }
         ex_n = fmaf(mt.cb, (d1 - d2) - cx, eo[0]) - dP[0] * mt.inv_eps;
       }
       if (!((!x.pz && k == 0) || (!x.px && i == 0))) {  // Ey: d/dz Hx - d/dx Hz
         float d1 = hx - hxm, d2 = hz - hz_im;
-        if (PM) {
-          d1 = ZP ? stretch_z<false>(x, 1, S.ge, sz, c, d1, true, S.pe[1]) : stretch<false, PM>(x, 1, 2, k, i, j, k, d1, true);
-          d2 = stretch<false, PM>(x, 1, 0, i, i, j, k, d2, true);
+        if (PMM) {
+          d1 = ZP ? stretch_z<false>(x, 1, S.ge, sz, c, d1, true, S.pe[1]) : stretch<false, PMM>(x, 1, 2, k, i, j, k, d1, true);
+          d2 = stretch<false, PMM>(x, 1, 0, i, i, j, k, d2, true);
         }
         ey_n = fmaf(mt.cb, (d1 - d2) - cy, eo[1]) - dP[1] * mt.inv_eps;
       }
       if (!((!x.px && i == 0) || (!x.py && j == 0))) {  // Ez: d/dx Hy - d/dy Hx
         float d1 = hy - hy_im, d2 = hx - hx_jm;
-        if (PM) {
-          d1 = stretch<false, PM>(x, 2, 0, i, i, j, k, d1, true);
-          d2 = stretch<false, PM>(x, 2, 1, j, i, j, k, d2, true);
+        if (PMM) {
+          d1 = stretch<false, PMM>(x, 2, 0, i, i, j, k, d1, true);
+          d2 = stretch<false, PMM>(x, 2, 1, j, i, j, k, d2, true);
         }
         ez_n = fmaf(mt.cb, (d1 - d2) - cz, eo[2]) - dP[2] * mt.inv_eps;
       }
@@ -690,17 +695,23 @@ template <int TX, int PM, bool GAIN>
 __global__ __launch_bounds__(FD_MAXBLOCK) void step_kernel(const fd_tile* __restrict__ tiles, int ntiles, int s,
                                                            fd_xcd part, int use_part) {
   __shared__ Lds<TX> lds;
+  // z-only CPML launches specialise their interior tiles; the all-axes kernel
+  // keeps one general march (two would not fit its register budget)
+  auto run = [&](const fd_tile& tl) {
+    if (PM == 4 && !(tl.flags & FD_TILE_ZSLAB)) run_tile<TX, PM, GAIN, false>(tl, s, lds);
+    else run_tile<TX, PM, GAIN, (PM & 4) != 0>(tl, s, lds);
+  };
   if (use_part) {
     const int x = (int)blockIdx.x % 8, q = (int)blockIdx.x / 8;
     if (q < part.count[x]) {
       const fd_tile tl = tiles[part.start[x] + q];
-      run_tile<TX, PM, GAIN>(tl, s, lds);
+      run(tl);
     }
     return;
   }
   for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
     const fd_tile tl = tiles[xcd_tile(w, ntiles)];
-    run_tile<TX, PM, GAIN>(tl, s, lds);
+    run(tl);
   }
 }
 
