@@ -11,7 +11,7 @@ default run is the workload's 20,000 steps.
 
 Prints one JSON line: cell-updates/s of the plain stepper (inputs resident in
 HBM, autotuned launch shape, hipGraph replay), the roofline of the dominant
-kernel measured live with hipEvents around its launches, the CPU oracle timed
+kernel measured live with hipEvents bound to its launches, the CPU oracle timed
 on a bounded sample of the same workload, and beside them the batched ensemble
 (64 uneven realizations, one launch per tile class per step), the served
 request stream (p50/p99 latency), the lasing box and the 320^3 grid.
@@ -80,8 +80,8 @@ def copy_calibration():
 
 
 def kernel_table(plan, nsteps):
-    """Per kernel class: average launch duration (hipEvents around each launch on
-    the launch stream) and the algorithmic bytes of one launch (libfdtd counts
+    """Per kernel class: average launch duration (a hipEvent pair bound to each
+    launch on the launch stream: the kernel's own begin and end timestamps) and the algorithmic bytes of one launch (libfdtd counts
     them per cell: 49 B, +32 B per CPML slab axis, +84 B per gain cell; a DFT
     launch stores a 40 B/point plane sample and, once per 32-sample ring, moves
     128 B per plane point and frequency: averaged per launch)."""

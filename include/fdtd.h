@@ -224,11 +224,14 @@ int fdtd_class_cells(const fdtd_plan* p, int64_t* cells /* 7 */);
    (E, H and the material index in, E and H out) + 32 per cell and CPML axis
    whose slab holds it (2 E-side psi read+write, 2 H-side psi read + write) + 84
    per gain cell (P^n, P^{n-1}, populations in; P^{n+1}, populations out); the
-   DFT entry is the bytes of one call (4 complex FP64 accumulators read + write
-   per plane point and frequency). */
+   DFT entry is the average bytes of one call: the plane sample (24 bytes read,
+   16 written per point) and, once per 32 samples, the 4 complex FP64
+   accumulators read + written per plane point and frequency plus the sample
+   ring read. */
 int fdtd_class_bytes(const fdtd_plan* p, double* bytes /* 7 */);
-/* Advance n steps without graphs, bracketing every kernel launch with a pair of
-   hipEvents on the stream; ms[c] = summed milliseconds and launches[c] = number of
+/* Advance n steps without graphs, launching every kernel with a pair of hipEvents
+   bound to the launch (hipExtLaunchKernelGGL start/stop: the kernel's own begin
+   and end timestamps); ms[c] = summed milliseconds and launches[c] = number of
    launches of class c (7 entries each, as above). */
 int fdtd_time_kernels(fdtd_plan* p, int64_t n, void* stream, double* ms, int64_t* launches);
 

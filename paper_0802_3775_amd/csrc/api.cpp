@@ -1306,14 +1306,14 @@ int fdtd_time_kernels(fdtd_plan* p, int64_t n, void* stream, double* ms, int64_t
       (void)hipEventDestroy(r.b);
     }
   };
+  // the events are bound to the launch itself (begin and end timestamps of the
+  // kernel), so a duration excludes the gaps between launches
   auto record = [&](int cls, auto&& launch) -> int {
     Rec r{cls, nullptr, nullptr};
     HIPCHK(hipEventCreate(&r.a));
     HIPCHK(hipEventCreate(&r.b));
     recs.push_back(r);
-    HIPCHK(hipEventRecord(r.a, st));
-    HIPCHK(launch());
-    HIPCHK(hipEventRecord(r.b, st));
+    HIPCHK(launch(r.a, r.b));
     return FDTD_OK;
   };
   for (int64_t s = 0; s < n; ++s) {
@@ -1322,13 +1322,15 @@ int fdtd_time_kernels(fdtd_plan* p, int64_t n, void* stream, double* ms, int64_t
       if (nt == 0) continue;
       const int grid = p->tune.max_blocks > 0 ? std::min(nt, p->tune.max_blocks) : p->pgrid[c];
       const fd_xcd* pc = p->tune.max_blocks > 0 ? nullptr : &p->part[c];
-      const int r = record(c, [&]() {
-        return fd_launch_step(c, p->dtiles[c], nt, p->tune.tile_x, p->tune.block, grid, (int)s, pc, st);
+      const int r = record(c, [&](hipEvent_t a, hipEvent_t b) {
+        return fd_launch_step(c, p->dtiles[c], nt, p->tune.tile_x, p->tune.block, grid, (int)s, pc, st, a, b);
       });
       if (r) { cleanup(); return r; }
     }
     if (plan_dft_due(p, p->step + s) && !p->dft.empty()) {
-      const int r = record(FD_NCLASS, [&]() { return fd_launch_dft(p->ddft, (int)p->dft.size(), (int)s, st); });
+      const int r = record(FD_NCLASS, [&](hipEvent_t a, hipEvent_t b) {
+        return fd_launch_dft(p->ddft, (int)p->dft.size(), (int)s, st, a, b);
+      });
       if (r) { cleanup(); return r; }
     }
   }

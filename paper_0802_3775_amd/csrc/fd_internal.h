@@ -117,9 +117,12 @@ struct fd_xcd {
 };
 
 // part == nullptr: grid-stride loop over the tiles with the plain XCD renumbering
+// start / stop (optional): events that take the kernel's own begin and end timestamps
 hipError_t fd_launch_step(int cls, const fd_tile* tiles, int ntiles, int tile_x, int block, int grid,
-                          int s, const fd_xcd* part, hipStream_t st);
-hipError_t fd_launch_dft(const fd_dft_tile* tiles, int ntiles, int s, hipStream_t st);
+                          int s, const fd_xcd* part, hipStream_t st, hipEvent_t start = nullptr,
+                          hipEvent_t stop = nullptr);
+hipError_t fd_launch_dft(const fd_dft_tile* tiles, int ntiles, int s, hipStream_t st, hipEvent_t start = nullptr,
+                         hipEvent_t stop = nullptr);
 hipError_t fd_launch_dft_preview(const fd_dft_tile* tiles, int ntiles, int flux, long long first, int count,
                                  hipStream_t st);
 hipError_t fd_launch_advance(fd_desc* const* descs, int n, long long k, hipStream_t st);

@@ -21,6 +21,8 @@
 // run a specialised kernel without that code.
 #include "fd_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 namespace {
@@ -1001,23 +1003,31 @@ __global__ void init_pop_kernel(const uint8_t* __restrict__ map, const float* __
 
 }  // namespace
 
+// start/stop (optional) take the kernel's own begin and end timestamps
+template <int TX, int PM, bool GAIN>
+static void launch_one(const fd_tile* tiles, int ntiles, int block, int grid, int s, const fd_xcd& part, int use,
+                       hipStream_t st, hipEvent_t start, hipEvent_t stop) {
+  hipExtLaunchKernelGGL(step_kernel<TX, PM, GAIN>, dim3(grid), dim3(block), 0, st, start, stop, 0, tiles, ntiles, s,
+                        part, use);
+}
+
 template <int TX>
 static hipError_t launch_tx(int cls, const fd_tile* tiles, int ntiles, int block, int grid, int s,
-                            const fd_xcd& part, int use, hipStream_t st) {
+                            const fd_xcd& part, int use, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
   switch (cls) {
-    case FD_CLASS_PLAIN: step_kernel<TX, 0, false><<<grid, block, 0, st>>>(tiles, ntiles, s, part, use); break;
-    case FD_CLASS_PMLZ: step_kernel<TX, 4, false><<<grid, block, 0, st>>>(tiles, ntiles, s, part, use); break;
-    case FD_CLASS_PML: step_kernel<TX, 7, false><<<grid, block, 0, st>>>(tiles, ntiles, s, part, use); break;
-    case FD_CLASS_GAIN: step_kernel<TX, 0, true><<<grid, block, 0, st>>>(tiles, ntiles, s, part, use); break;
-    case FD_CLASS_PMLZ_GAIN: step_kernel<TX, 4, true><<<grid, block, 0, st>>>(tiles, ntiles, s, part, use); break;
-    case FD_CLASS_PML_GAIN: step_kernel<TX, 7, true><<<grid, block, 0, st>>>(tiles, ntiles, s, part, use); break;
+    case FD_CLASS_PLAIN: launch_one<TX, 0, false>(tiles, ntiles, block, grid, s, part, use, st, start, stop); break;
+    case FD_CLASS_PMLZ: launch_one<TX, 4, false>(tiles, ntiles, block, grid, s, part, use, st, start, stop); break;
+    case FD_CLASS_PML: launch_one<TX, 7, false>(tiles, ntiles, block, grid, s, part, use, st, start, stop); break;
+    case FD_CLASS_GAIN: launch_one<TX, 0, true>(tiles, ntiles, block, grid, s, part, use, st, start, stop); break;
+    case FD_CLASS_PMLZ_GAIN: launch_one<TX, 4, true>(tiles, ntiles, block, grid, s, part, use, st, start, stop); break;
+    case FD_CLASS_PML_GAIN: launch_one<TX, 7, true>(tiles, ntiles, block, grid, s, part, use, st, start, stop); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t fd_launch_step(int cls, const fd_tile* tiles, int ntiles, int tile_x, int block, int grid, int s,
-                          const fd_xcd* part, hipStream_t st) {
+                          const fd_xcd* part, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
   if (ntiles <= 0) return hipSuccess;
   if (block < 64 || block > FD_MAXBLOCK || (block & 63) != 0 || grid <= 0 || block % tile_x != 0 ||
       2 * (tile_x + 2) + 2 * (block / tile_x) > block)
@@ -1037,16 +1047,17 @@ hipError_t fd_launch_step(int cls, const fd_tile* tiles, int ntiles, int tile_x,
     use = 1;
   }
   switch (tile_x) {
-    case 16: return launch_tx<16>(cls, tiles, ntiles, block, grid, s, pz, use, st);
-    case 32: return launch_tx<32>(cls, tiles, ntiles, block, grid, s, pz, use, st);
-    case 64: return launch_tx<64>(cls, tiles, ntiles, block, grid, s, pz, use, st);
+    case 16: return launch_tx<16>(cls, tiles, ntiles, block, grid, s, pz, use, st, start, stop);
+    case 32: return launch_tx<32>(cls, tiles, ntiles, block, grid, s, pz, use, st, start, stop);
+    case 64: return launch_tx<64>(cls, tiles, ntiles, block, grid, s, pz, use, st, start, stop);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t fd_launch_dft(const fd_dft_tile* tiles, int ntiles, int s, hipStream_t st) {
+hipError_t fd_launch_dft(const fd_dft_tile* tiles, int ntiles, int s, hipStream_t st, hipEvent_t start,
+                         hipEvent_t stop) {
   if (ntiles <= 0) return hipSuccess;
-  dft_kernel<<<ntiles, 256, 0, st>>>(tiles, s);
+  hipExtLaunchKernelGGL(dft_kernel, dim3(ntiles), dim3(256), 0, st, start, stop, 0, tiles, s);
   return hipGetLastError();
 }
 
