@@ -547,8 +547,8 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         const gf* pop = G(d->pop);
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          nh[q] = pop[q * nc + o];
-          nl[q] = pop[(3 + q) * nc + o];
+          nh[q] = pop[(size_t)q * nc + o];
+          nl[q] = pop[(size_t)(3 + q) * nc + o];
         }
         const float n1 = nh[0] + nl[0], n2 = nh[1] + nl[1];
         float F[3] = {0.0f, 0.0f, 0.0f};
@@ -621,8 +621,8 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) inc = fmaf(mt.MI[r][q], nn[q], inc);
           two_sum(nh[r], nl[r], inc);
-          pop[r * nc + o] = nh[r];
-          pop[(3 + r) * nc + o] = nl[r];
+          pop[(size_t)r * nc + o] = nh[r];
+          pop[(size_t)(3 + r) * nc + o] = nl[r];
         }
 #pragma unroll
         for (int q = 0; q < 3; ++q) G(d->P[par ^ 1][q])[o] = Pnew[q];
