@@ -61,7 +61,7 @@ extern "C" {
 #define FDTD_MAX_FLUX 4
 
 enum { FDTD_BC_PERIODIC = 0, FDTD_BC_PEC = 1 };
-enum { FDTD_SRC_DIPOLE = 0, FDTD_SRC_PLANE = 1 };
+enum { FDTD_SRC_DIPOLE = 0, FDTD_SRC_PLANE = 1, FDTD_SRC_BEAM = 2 };
 enum { FDTD_WIDTH_FWHM_POWER = 0, FDTD_WIDTH_FWHM_INTENSITY = 1, FDTD_WIDTH_SIGMA_T = 2 };
 enum { FDTD_DISORDER_NONE = 0, FDTD_DISORDER_UNIFORM_RADIUS = 1, FDTD_DISORDER_GAUSS_JITTER = 2 };
 
@@ -98,12 +98,18 @@ typedef struct {
 /* Source: s(t) = amp sin(2 pi f0 (t - t0)) exp(-(t - t0)^2 / (2 sigma_t^2)),
    t0 = delay * sigma_t.  Width: FWHM of the power spectrum (c/a), FWHM of the
    intensity envelope (a/c), or sigma_t (a/c).  DIPOLE: current s/dx^3 on E_comp
-   of cell (i,j,k).  PLANE: sheet current s on E_comp over the whole z = k plane. */
+   of cell (i,j,k).  PLANE: sheet current s on E_comp over the whole z = k plane.
+   BEAM (the paper's linearly polarised TEM00 beam at its waist, launched along
+   z): the PLANE sheet weighted by exp(-((x - x0)^2 + (y - y0)^2) / waist^2), with
+   x, y the driven component's own Yee position (Ex at ((i + 1/2) dx, j dx), Ey at
+   (i dx, (j + 1/2) dx), Ez at (i dx, j dx)) and x0, y0, waist in units of a;
+   waist > 0.  x0, y0, waist are ignored by the other kinds. */
 typedef struct {
   int32_t kind, comp, i, j, k;
   double f0;
   int32_t width_kind;
   double width, delay, amp;
+  double x0, y0, waist;
 } fdtd_source_desc;
 
 /* Inverted opal: cells[3] cubic fcc cells starting at grid index origin[3];

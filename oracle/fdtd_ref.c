@@ -278,6 +278,8 @@ int orc_add_source(orc_sim* s, const orc_source* src) {
       return -1;
   } else if (src->kind == ORC_SRC_PLANE) {
     if (src->k < 0 || src->k >= s->nz) return -1;
+  } else if (src->kind == ORC_SRC_BEAM) {
+    if (src->k < 0 || src->k >= s->nz || !(src->waist > 0.0)) return -1;
   } else {
     return -1;
   }
@@ -344,6 +346,16 @@ static double source_dxJ(const orc_sim* s, int q, int64_t n) {
   const double sig = s->sig_t[q];
   const double w = src->amp * sin(2.0 * PI * src->f0 * tau) * exp(-tau * tau / (2.0 * sig * sig));
   return src->kind == ORC_SRC_DIPOLE ? w / (s->dx * s->dx) : w;
+}
+
+/* TEM00 waist profile of a BEAM sheet at component c of cell (i, j): the
+   Gaussian exp(-r^2 / w^2) of the distance from the beam axis (x0, y0), taken
+   at the component's own position in the Yee cell (units of a). */
+static double beam_weight(const orc_sim* s, const orc_source* src, int c, int64_t i, int64_t j) {
+  const double x = ((double)i + (c == 0 ? 0.5 : 0.0)) * s->dx;
+  const double y = ((double)j + (c == 1 ? 0.5 : 0.0)) * s->dx;
+  const double rx = x - src->x0, ry = y - src->y0;
+  return exp(-(rx * rx + ry * ry) / (src->waist * src->waist));
 }
 
 /* ------------------------------------------------------------------- step */
@@ -443,8 +455,8 @@ static void update_E_and_matter(orc_sim* s, int64_t n) {
             const orc_source* src = &s->src[r];
             if (src->comp != c) continue;
             if (src->kind == ORC_SRC_DIPOLE && (src->i != i || src->j != j || src->k != k)) continue;
-            if (src->kind == ORC_SRC_PLANE && src->k != k) continue;
-            curl -= dxJ[r];
+            if (src->kind != ORC_SRC_DIPOLE && src->k != k) continue;
+            curl -= src->kind == ORC_SRC_BEAM ? dxJ[r] * beam_weight(s, src, c, i, j) : dxJ[r];
           }
           s->E[c][q] = Eold[c] + cb * curl - (Pnew[c] - Pcur[c]) / eps;
         }

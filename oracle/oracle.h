@@ -66,18 +66,23 @@ typedef struct {
   double n_init[4];             /* initial fractional populations n0..n3 */
 } orc_material;
 
-enum { ORC_SRC_DIPOLE = 0, ORC_SRC_PLANE = 1 };
+enum { ORC_SRC_DIPOLE = 0, ORC_SRC_PLANE = 1, ORC_SRC_BEAM = 2 };
 enum { ORC_W_FWHM_POWER = 0, ORC_W_FWHM_INTENSITY = 1, ORC_W_SIGMA_T = 2 };
 
 typedef struct {
-  int32_t kind;                 /* ORC_SRC_DIPOLE or ORC_SRC_PLANE (plane normal z) */
+  int32_t kind;                 /* ORC_SRC_DIPOLE, ORC_SRC_PLANE or ORC_SRC_BEAM (sheets normal to z) */
   int32_t comp;                 /* 0 Ex, 1 Ey, 2 Ez */
-  int32_t i, j, k;              /* dipole cell; plane uses k only */
+  int32_t i, j, k;              /* dipole cell; sheets use k only */
   double f0;                    /* carrier frequency, c/a */
   int32_t width_kind;
   double width;                 /* see width_kind */
   double delay;                 /* t0 = delay * sigma_t */
   double amp;
+  /* BEAM: a sheet like PLANE whose current is weighted by the TEM00 waist
+     profile exp(-((x - x0)^2 + (y - y0)^2) / waist^2), x and y (units of a)
+     taken at the driven component's own Yee position (Ex at ((i + 1/2) dx, j dx),
+     Ey at (i dx, (j + 1/2) dx), Ez at (i dx, j dx)) */
+  double x0, y0, waist;
 } orc_source;
 
 enum { ORC_DIS_NONE = 0, ORC_DIS_UNIFORM_RADIUS = 1, ORC_DIS_GAUSS_JITTER = 2 };

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 DIS = {"none": 0, "uniform": 1, "gauss": 2}
-SRC = {"dipole": 0, "plane": 1}
+SRC = {"dipole": 0, "plane": 1, "beam": 2}
 WIDTH = {"fwhm_power": 0, "fwhm_intensity": 1, "sigma_t": 2}
 
 
@@ -40,7 +40,8 @@ class Material(C.Structure):
 class Source(C.Structure):
     _fields_ = [("kind", C.c_int32), ("comp", C.c_int32), ("i", C.c_int32), ("j", C.c_int32),
                 ("k", C.c_int32), ("f0", C.c_double), ("width_kind", C.c_int32),
-                ("width", C.c_double), ("delay", C.c_double), ("amp", C.c_double)]
+                ("width", C.c_double), ("delay", C.c_double), ("amp", C.c_double),
+                ("x0", C.c_double), ("y0", C.c_double), ("waist", C.c_double)]
 
 
 class Opal(C.Structure):
@@ -152,6 +153,7 @@ def make_source(d):
     s.width = d["width"]
     s.delay = d["delay"]
     s.amp = d.get("amp", 1.0)
+    s.x0, s.y0, s.waist = d.get("x0", 0.0), d.get("y0", 0.0), d.get("waist", 0.0)
     return s
 
 

@@ -59,7 +59,7 @@ struct Layout {
   size_t map;
   size_t P[2][3], pop;
   size_t prof[3], psiE[3][2], psiH[2][3][2];
-  size_t src[FD_MAXSRC];
+  size_t src[FD_MAXSRC], srcprof[FD_MAXSRC];
   size_t probe;
   size_t fluxT[FD_MAXFLUX], fluxf[FD_MAXFLUX], fluxacc[FD_MAXFLUX], fluxring[FD_MAXFLUX], fluxprev[FD_MAXFLUX];
   size_t fluxrot[FD_MAXFLUX];
@@ -370,9 +370,11 @@ int compute_layout(fdtd_plan* p, int64_t max_steps, Layout& L) {
       len = std::min<int64_t>(std::max<int64_t>(len, 1), std::max<int64_t>(max_steps, 1));
       p->src_len[q] = (int)len;
       L.src[q] = take(sizeof(float) * (size_t)len);
+      L.srcprof[q] = s.kind == FDTD_SRC_BEAM ? take(sizeof(float) * (size_t)p->g.nx * p->g.ny) : 0;
     } else {
       p->src_len[q] = 0;
       L.src[q] = 0;
+      L.srcprof[q] = 0;
     }
   }
   const int plane = p->g.nx * p->g.ny;
@@ -614,6 +616,10 @@ int fdtd_add_source(fdtd_plan* p, const fdtd_source_desc* s, int32_t* id) {
       return fail(FDTD_EINVAL, "dipole outside the grid");
   } else if (s->kind == FDTD_SRC_PLANE) {
     if (s->k < 0 || s->k >= p->g.nz) return fail(FDTD_EINVAL, "source plane outside the grid");
+  } else if (s->kind == FDTD_SRC_BEAM) {
+    if (s->k < 0 || s->k >= p->g.nz) return fail(FDTD_EINVAL, "source plane outside the grid");
+    if (!(s->waist > 0.0) || !std::isfinite(s->x0) || !std::isfinite(s->y0))
+      return fail(FDTD_EINVAL, "beam waist must be > 0 and its axis finite");
   } else {
     return fail(FDTD_EINVAL, "bad source kind");
   }
@@ -790,6 +796,22 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
     d.src_cell[q] = s.kind == FDTD_SRC_DIPOLE ? s.j * p->g.nx + s.i : -1;
     d.src_len[q] = p->src_len[q];
     d.src_tab[q] = at<float>(p, L.src[q]);
+    d.src_prof[q] = nullptr;
+    if (s.kind == FDTD_SRC_BEAM) {
+      // TEM00 waist profile at the driven component's Yee position (FP64, stored FP32)
+      std::vector<float> prof((size_t)p->g.nx * p->g.ny);
+      for (int j = 0; j < p->g.ny; ++j)
+        for (int i = 0; i < p->g.nx; ++i) {
+          const double x = ((double)i + (s.comp == 0 ? 0.5 : 0.0)) * p->dx;
+          const double y = ((double)j + (s.comp == 1 ? 0.5 : 0.0)) * p->dx;
+          const double rx = x - s.x0, ry = y - s.y0;
+          prof[(size_t)j * p->g.nx + i] = (float)std::exp(-(rx * rx + ry * ry) / (s.waist * s.waist));
+        }
+      HIPCHK(hipMemcpyAsync(p->arena + L.srcprof[q], prof.data(), sizeof(float) * prof.size(),
+                            hipMemcpyHostToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));
+      d.src_prof[q] = at<float>(p, L.srcprof[q]);
+    }
   }
   // probes
   d.nprobe = (int)p->probes.size();

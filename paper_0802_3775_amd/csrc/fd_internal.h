@@ -57,6 +57,7 @@ struct fd_desc {
   int src_kind[FD_MAXSRC], src_comp[FD_MAXSRC], src_cell[FD_MAXSRC], src_k[FD_MAXSRC];
   int src_len[FD_MAXSRC];
   const float* src_tab[FD_MAXSRC];   // dx * J(t_{n+1/2}) per step
+  const float* src_prof[FD_MAXSRC];  // BEAM: transverse weight per plane cell [ny][nx]
   // probes
   int nprobe;
   int probe_comp[FD_MAXPROBE], probe_cell[FD_MAXPROBE], probe_k[FD_MAXPROBE];

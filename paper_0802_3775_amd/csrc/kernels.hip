@@ -340,7 +340,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   unsigned srcmine = 0u;
   for (unsigned mm = srcmask; mm; mm &= mm - 1u) {
     const int q = __builtin_ctz(mm);
-    if (d->src_kind[q] == 1 || d->src_cell[q] == c) srcmine |= 1u << q;
+    if (d->src_kind[q] != 0 || d->src_cell[q] == c) srcmine |= 1u << q;  // sheets drive every column
   }
   const bool edue = d->ke > 0 && (n % d->ke) == 0;
   double eacc = 0.0;
@@ -572,8 +572,9 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       for (unsigned mm = srcmask; mm; mm &= mm - 1u) {  // uniform; scalar loads only
         const int q = __builtin_ctz(mm);
         if (d->src_k[q] != k) continue;
-        const float v = n < d->src_len[q] ? ((const cfloat*)d->src_tab[q])[n] : 0.0f;
+        float v = n < d->src_len[q] ? ((const cfloat*)d->src_tab[q])[n] : 0.0f;
         if (!((srcmine >> q) & 1u)) continue;
+        if (d->src_kind[q] == 2) v *= G(d->src_prof[q])[c];  // beam: transverse waist profile
         const int sc = d->src_comp[q];
         if (sc == 0) cx += v;
         else if (sc == 1) cy += v;

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfdtd.so")
 
 BC_PERIODIC, BC_PEC = 0, 1
-SRC = {"dipole": 0, "plane": 1}
+SRC = {"dipole": 0, "plane": 1, "beam": 2}
 WIDTH = {"fwhm_power": 0, "fwhm_intensity": 1, "sigma_t": 2}
 DIS = {"none": 0, "uniform": 1, "gauss": 2}
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "EUNSTABLE", -6: "EUNSUPPORTED"}
@@ -45,7 +45,8 @@ class Material(C.Structure):
 class SourceDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("comp", C.c_int32), ("i", C.c_int32), ("j", C.c_int32),
                 ("k", C.c_int32), ("f0", C.c_double), ("width_kind", C.c_int32),
-                ("width", C.c_double), ("delay", C.c_double), ("amp", C.c_double)]
+                ("width", C.c_double), ("delay", C.c_double), ("amp", C.c_double),
+                ("x0", C.c_double), ("y0", C.c_double), ("waist", C.c_double)]
 
 
 class OpalDesc(C.Structure):
@@ -209,6 +210,7 @@ class Plan:
             d.width = s["width"]
             d.delay = s["delay"]
             d.amp = s.get("amp", 1.0)
+            d.x0, d.y0, d.waist = s.get("x0", 0.0), s.get("y0", 0.0), s.get("waist", 0.0)
             _check(lib().fdtd_add_source(self.h, C.byref(d), None))
         self.nprobe = 0
         for p in cfg.get("probes", []):

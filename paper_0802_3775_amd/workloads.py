@@ -21,8 +21,9 @@ Config dict schema::
      "opal": {"cells", "origin", "r0", "disorder": none|uniform|gauss, "strength",
               "mat_bg", "mat_void", "mat_out"} or None,
      "map": optional uint8 [nz, ny, nx],
-     "sources": [{"kind": dipole|plane, "comp", "i", "j", "k", "f0",
-                  "width_kind": fwhm_power|fwhm_intensity|sigma_t, "width", "delay", "amp"}],
+     "sources": [{"kind": dipole|plane|beam, "comp", "i", "j", "k", "f0",
+                  "width_kind": fwhm_power|fwhm_intensity|sigma_t, "width", "delay", "amp",
+                  "x0", "y0", "waist" (beam: axis and waist, units of a)}],
      "probes": [(comp, i, j, k)], "flux": [{"k", "freqs", "decim"}],
      "energy_interval": int, "steps": int, "init_fields": {comp: array}}
 """
@@ -117,6 +118,50 @@ def slab(delta=0.05, seed=11, res=20, cells=(4, 4, 8), steps=20000, nf=100, deci
         "energy_interval": energy_interval,
         "steps": steps,
         "layout": {"z0": z0, "k_src": k_src, "k_tr": k_tr, "k_ref": k_ref},
+    }
+
+
+C_OVER_A_THZ = 299792458.0 / A_METERS / 1e12   # 1 c/a in THz (624.57 at a = 480 nm)
+
+
+def paper_beam(gamma=0.0, seed=31, res=16, cells=8, margin=None, pml=PML, steps=58000, realization=0,
+               eps=12.0, waist_um=2.0, f_thz=484.0, nf=0, box_um=6.0):
+    """The paper's linear workload: a box of (cells a + 2 margins + 2 CPML) per
+    axis (6 um = 200 cells at 16 cells/a for the defaults: 8 cubic cells of
+    inverted opal, 36-cell margins, 12-cell CPML on all faces), eps 12 background,
+    air spheres r0 = a/(2 sqrt 2) with uniform-radius disorder r0 (1 + gamma xi);
+    a linearly polarised (Ey) single-cycle TEM00 beam (waist 2 um, 484 THz,
+    intensity FWHM one period) launched along z ([100]) from the middle of the
+    front margin, axis at the box centre; an Ey probe at a seeded low-symmetry
+    point inside the crystal; T(t) through the middle of the back margin."""
+    if margin is None:  # fill a box of box_um (6 um: 200 cells at 16 cells/a)
+        margin = max(1, (int(round(box_um * 1e-6 / A_METERS * res)) - 2 * pml - cells * res) // 2)
+    n = cells * res + 2 * margin + 2 * pml
+    z0 = pml + margin
+    k_src = pml + margin // 2
+    k_tr = z0 + cells * res + margin // 2
+    f0 = f_thz / C_OVER_A_THZ
+    rng = np.random.default_rng(seed + 104729)
+    lo, hi = z0 + 1, z0 + cells * res - 1
+    pi_, pj_, pk_ = (int(v) for v in rng.integers(lo, hi, size=3))
+    centre = 0.5 * n / res
+    return {
+        "name": "beam_%d^3_R%d_g%.3f" % (n, res, gamma),
+        "grid": _grid((n, n, n), (0, 0, 0), res, pml=(pml, pml, pml), seed=seed, realization=realization),
+        "materials": [{"eps": float(eps)}, {"eps": 1.0}],
+        "opal": {"cells": (cells, cells, cells), "origin": (z0, z0, z0), "r0": 1.0 / (2.0 * np.sqrt(2.0)),
+                 "disorder": "uniform" if gamma > 0 else "none", "strength": float(gamma),
+                 "mat_bg": 0, "mat_void": 1, "mat_out": 1},
+        "map": None,
+        "sources": [{"kind": "beam", "comp": 1, "k": int(k_src), "f0": f0, "width_kind": "fwhm_intensity",
+                     "width": 1.0 / f0, "delay": 5.0, "amp": 1.0,
+                     "x0": centre, "y0": centre, "waist": waist_um * 1e-6 / A_METERS}],
+        "probes": [(1, pi_, pj_, pk_)],
+        "flux": [{"k": int(k_tr), "freqs": tuple(float(f) for f in np.linspace(0.6, 1.0, nf)) if nf else (),
+                  "decim": 8}],
+        "energy_interval": 0,
+        "steps": steps,
+        "layout": {"z0": z0, "k_src": k_src, "k_tr": k_tr, "f0": f0},
     }
 
 

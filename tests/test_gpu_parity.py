@@ -132,6 +132,40 @@ def test_flux_spectra_between_dft_flushes():
         assert np.array_equal(quiet.flux(f)[1], gpu.flux(f)[1])
 
 
+def test_beam_reduced_parity():
+    """The paper's linear workload at reduced size (TEM00 beam sheet, uniform-radius
+    disorder, CPML on all six faces): fields, probe and T(t) against the oracle."""
+    steps = 500
+    cfg = W.paper_beam(gamma=0.1, seed=5, res=8, cells=2, margin=6, pml=6, steps=steps)
+    _say("beam reduced", cfg["grid"]["n"], steps)
+    orc = run_oracle(cfg, steps)
+    gpu = run_gpu(cfg, steps, tuning={"block": 128, "zchunk": 4, "graph_steps": 50, "tile_x": 16})
+    assert np.array_equal(gpu.material_map(), orc.map)
+    err = field_rel_l2(gpu.fields(), orc.fields())
+    _say("fields", err)
+    assert err <= 1e-4
+    assert rel_l2(gpu.probe(0), orc.probe(0)) <= 1e-4
+    assert rel_l2(gpu.flux(0)[0], orc.flux(0)[0]) <= 1e-3
+
+
+def test_beam_full_box_parity():
+    """The paper's 200^3 box at 16 cells/a (8^3 cells of inverted opal, gamma 0.05)
+    for 300 steps, in the launch configuration the autotuner picks for it: every
+    field against the oracle, and the probe."""
+    from paper_0802_3775_amd import tune
+    steps = 300
+    cfg = W.paper_beam(gamma=0.05, seed=9, steps=steps)
+    _say("beam full", cfg["grid"]["n"], steps)
+    tuning = tune.autotune(dict(cfg, steps=steps), budget_s=4.0, quick=True, use_cache=False)
+    orc = run_oracle(cfg, steps)
+    gpu = run_gpu(cfg, steps, tuning=tuning)
+    assert np.array_equal(gpu.material_map(), orc.map)
+    err = field_rel_l2(gpu.fields(), orc.fields())
+    _say("fields", err, tuning)
+    assert err <= 1e-4
+    assert rel_l2(gpu.probe(0), orc.probe(0)) <= 1e-4
+
+
 def test_slab_full_size_random_fields():
     """Full slab grid (80x80x224, z-CPML) from random initial fields: every cell,
     the CPML slabs and the periodic wrap are exercised at the benchmark's size and

@@ -163,3 +163,57 @@ def test_airy_slab_transmission_converges():
         assert T.min() < 0.7 and T.max() > 0.99   # the fringes are resolved
     assert errs[-1] < 2e-3
     assert 3.0 < errs[0] / errs[1] < 5.0
+
+
+def _beam_box(n, res, waist, x0, y0, kind="beam", comp=1, steps=1):
+    cfg = W.homogeneous_box(n=(n, n, 6), periodic=(0, 0, 0), res=res, steps=steps)
+    cfg["sources"] = [{"kind": kind, "comp": comp, "k": 3, "f0": 0.8, "width_kind": "sigma_t",
+                       "width": 2.0, "delay": -0.25, "amp": 1.0, "x0": x0, "y0": y0, "waist": waist}]
+    return cfg
+
+
+def test_beam_weights_gaussian_integral_and_axis():
+    """TEM00 sheet (section "Wide-band excitation and gap filling": a linearly
+    polarised TEM00 beam of given waist launched along [100]).  After one step from
+    rest E = -(dt/dx) dxJ w(i, j) on the source plane, so the ratio to a uniform
+    sheet's field is the transverse weight w.  Checks: w = 1 exactly on the beam
+    axis at the driven component's own Yee position (Ey sits at (i, j + 1/2)), the
+    sampled Gaussian sums to pi waist^2 / dx^2 (Poisson summation: exact to
+    rounding once the box holds the tails), and w is mirror-symmetric about the
+    axis."""
+    res, n = 4, 48
+    dx = 1.0 / res
+    waist = 3.0 * dx
+    x0, y0 = 24 * dx, 20.5 * dx            # Ey of cell (24, 20) sits on the axis
+    beam = O.OracleSim(_beam_box(n, res, waist, x0, y0), max_steps=1)
+    beam.step(1)
+    plane = O.OracleSim(_beam_box(n, res, waist, x0, y0, kind="plane"), max_steps=1)
+    plane.step(1)
+    eb, ep = beam.fields()[1][3], plane.fields()[1][3]      # Ey on the source plane [y][x]
+    assert np.all(ep[1:-1, 1:-1] != 0.0)
+    w = np.zeros_like(eb)
+    w[1:-1, 1:-1] = eb[1:-1, 1:-1] / ep[1:-1, 1:-1]
+    assert w[20, 24] == 1.0
+    assert abs(w.sum() - math.pi * waist ** 2 / dx ** 2) <= 1e-12 * w.sum()
+    assert np.allclose(w[20, 24 - 5:24], w[20, 24 + 5:24:-1], rtol=0, atol=1e-15)   # x mirror about i = 24
+    assert np.allclose(w[20 - 5:20, 24], w[20 + 5:20:-1, 24], rtol=0, atol=1e-15)   # y mirror about j = 20
+
+
+def test_beam_with_infinite_waist_is_the_plane_sheet():
+    """A waist far larger than the box makes every weight exp(-tiny) = 1 in FP64:
+    the beam run equals the uniform-sheet run bit for bit after many steps (CPML
+    and PEC walls included), for every driven component."""
+    for comp in (0, 1, 2):
+        cfgs = []
+        for kind in ("beam", "plane"):
+            c = W.homogeneous_box(n=(10, 12, 30), periodic=(0, 0, 0), res=8, pml=(4, 4, 4), steps=60)
+            c["sources"] = [{"kind": kind, "comp": comp, "k": 9, "f0": 0.8, "width_kind": "fwhm_intensity",
+                             "width": 1.25, "delay": 5.0, "amp": 1.0, "x0": 0.7, "y0": 0.6, "waist": 1e30}]
+            cfgs.append(c)
+        a = O.OracleSim(cfgs[0], max_steps=60)
+        a.step(60)
+        b = O.OracleSim(cfgs[1], max_steps=60)
+        b.step(60)
+        fa, fb = a.fields(), b.fields()
+        assert np.abs(fb).max() > 0
+        assert np.array_equal(fa, fb), comp
