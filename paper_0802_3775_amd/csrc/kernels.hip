@@ -130,11 +130,15 @@ __device__ __forceinline__ void make_ctx(Ctx& x, const cdesc* d, int par, bool p
   for (int w = 0; w < 3; ++w) {
     x.lo[w] = d->pml_lo[w]; x.hi[w] = d->pml_hi[w]; x.t[w] = d->pml_t[w];
     x.prof[w] = (const cfloat*)d->prof[w];
+    // an axis without CPML has no psi arrays: its pointers are set to E so
+    // that the unconditional reads of the all-axes march stay in bounds (their
+    // values are never used; stores happen only inside slabs)
+    float* const spare = d->E[par][0];
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
-      x.psiE[w][f].p = G(d->psiE[w][f]);
-      x.psiHin[w][f].p = G((const float*)d->psiH[par][w][f]);
-      x.psiHout[w][f].p = G(d->psiH[par ^ 1][w][f]);
+      x.psiE[w][f].p = G(d->psiE[w][f] ? d->psiE[w][f] : spare);
+      x.psiHin[w][f].p = G((const float*)(d->psiH[par][w][f] ? d->psiH[par][w][f] : spare));
+      x.psiHout[w][f].p = G(d->psiH[par ^ 1][w][f] ? d->psiH[par ^ 1][w][f] : spare);
     }
   }
 }
@@ -210,6 +214,17 @@ __device__ __forceinline__ float stretch_z(const Ctx& x, int c, const float* pz,
   return fmaf(d, kinv, psi);
 }
 
+// A CPML difference whose old psi and grading are already in registers (sp: slab
+// index, -1 outside): returns d/kappa + psi with psi = b psi_old + c d and stores
+// psi at dst[off] when own.  Bit-identical to stretch<HSIDE, PM>.
+__device__ __forceinline__ float stretch_v(float d, int sp, float kinv, float b, float cc, float psi_old, bool own,
+                                           const R32<float>& dst, uint32_t off) {
+  if (sp < 0) return d;
+  const float psi = fmaf(b, psi_old, cc * d);
+  if (own) dst[off] = psi;
+  return fmaf(d, kinv, psi);
+}
+
 // One H component from its two differences: H^{n+1/2} = H^{n-1/2} - (dt/dx)(d1 - d2),
 // each difference stretched by the CPML where the position lies in a slab.  The
 // owner and every workgroup that recomputes the value as a halo call this with
@@ -274,6 +289,10 @@ struct Lds {
   double red[FD_MAXBLOCK / 64];
   double ftot[FD_MAXFLUX];  // T(t) partial of the tile per flux plane, stored after the z march
   float probe[FD_MAXPROBE];  // probe samples of the tile, stored after the z march
+  // all-axes CPML tiles: x and y grading (1/kappa, b, c at E then H positions) of
+  // columns i0-1 .. i0+TX-1 and rows j0-1 .. j0+TYM-1 (0 outside the slabs)
+  float gx[6][TX + 1];
+  float gy[6][TYM + 1];
 };
 
 // ZT: the tile's z range holds z-slab planes.  Without them the z march drops
@@ -396,6 +415,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   const R32<const uint8_t> matp{(const gu8*)d->mat};
   constexpr int PMM = ZT ? PM : (PM & 3);  // CPML axes the march handles
   constexpr bool ZP = ZT && PM == 4;       // z-slab psi prefetched with the plane (z-only CPML tiles)
+  constexpr bool AX = PMM == 7;            // all-axes CPML tiles: psi of the plane issued up front
   auto load_h = [&](int kk, Stage& S, bool live) {
     kk = live ? kk : 0;
     const int zo = kk * x.plane;
@@ -471,16 +491,70 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
     if (t < mwords) mdst[t] = mword;
     for (int q = t + (int)blockDim.x; q < mwords; q += (int)blockDim.x) mdst[q] = msrc[q];
   }
+  // all-axes CPML: slab indices of the own column and of the halo-duty cell along
+  // x and y (fixed over the march), and the tile's x / y grading tables in LDS
+  int sxo = -1, syo = -1, sxh = -1, syh = -1;
+  if (AX) {
+    sxo = slab(x, 0, i);
+    syo = slab(x, 1, j);
+    if (hact) {
+      sxh = slab(x, 0, hgi);
+      syh = slab(x, 1, hgj);
+    }
+    for (int q = t; q < 6 * (TX + 1); q += (int)blockDim.x) {
+      const int r = q / (TX + 1), ii = i0 - 1 + q % (TX + 1);
+      s.gx[r][q % (TX + 1)] = (ii >= 0 && ii < x.nx && slab(x, 0, ii) >= 0) ? x.prof[0][r * x.nx + ii] : 0.0f;
+    }
+    for (int q = t; q < 6 * (Lds<TX>::TYM + 1); q += (int)blockDim.x) {
+      const int r = q / (Lds<TX>::TYM + 1), jj = j0 - 1 + q % (Lds<TX>::TYM + 1);
+      s.gy[r][q % (Lds<TX>::TYM + 1)] = (jj >= 0 && jj < x.ny && slab(x, 1, jj) >= 0) ? x.prof[1][r * x.ny + jj] : 0.0f;
+    }
+  }
 
   auto plane_step = [&](auto cbc, const int k, Stage& S) __attribute__((always_inline)) {
     constexpr int cb = decltype(cbc)::value;
     constexpr int nb = cb ^ 1;
-    // plane k+1 into LDS, then the loads two planes ahead into the same Stage
+    // plane k+1 into LDS; the loads two planes ahead reuse the same Stage
     store_e(nb, S);
-    load_e(k + 3, S, k + 2 < k1);
     const int zo = k * x.plane;
     const int o = zo + c;
-    const int sz = ZP ? slab(x, 2, k) : -1;
+    const int sz = (ZP || AX) ? slab(x, 2, k) : -1;
+    // all-axes CPML: every old psi the plane needs, issued before the barriers
+    // (lanes outside a slab read element 0); z grading is uniform over the plane
+    float aH[6] = {}, aE[6] = {}, aHh[4] = {}, gzE[3] = {}, gzH[3] = {};
+    uint32_t ox = 0, oy = 0, oz = 0, ohx = 0, ohy = 0, ohz = 0;
+    if (AX) {
+      ox = (act && sxo >= 0) ? (uint32_t)((k * x.ny + j) * x.t[0] + sxo) : 0u;
+      oy = (act && syo >= 0) ? (uint32_t)((k * x.t[1] + syo) * x.nx + i) : 0u;
+      oz = (act && sz >= 0) ? (uint32_t)(sz * x.plane + c) : 0u;
+      ohx = (hact && sxh >= 0) ? (uint32_t)((k * x.ny + hgj) * x.t[0] + sxh) : 0u;
+      ohy = (hact && syh >= 0) ? (uint32_t)((k * x.t[1] + syh) * x.nx + hgi) : 0u;
+      ohz = (hact && sz >= 0) ? (uint32_t)(sz * x.plane + h_off) : 0u;
+      // own H: Hx(y, z), Hy(z, x), Hz(x, y); own E in the same order
+      aH[0] = x.psiHin[1][1][oy]; aH[1] = x.psiHin[2][0][oz];
+      aH[2] = x.psiHin[2][1][oz]; aH[3] = x.psiHin[0][0][ox];
+      aH[4] = x.psiHin[0][1][ox]; aH[5] = x.psiHin[1][0][oy];
+      aE[0] = x.psiE[1][1][oy]; aE[1] = x.psiE[2][0][oz];
+      aE[2] = x.psiE[2][1][oz]; aE[3] = x.psiE[0][0][ox];
+      aE[4] = x.psiE[0][1][ox]; aE[5] = x.psiE[1][0][oy];
+      // halo: column cells (lh) need Hy(z, x), row cells Hx(y, z); both need Hz(x, y)
+      const gf* pc1z = lh ? x.psiHin[2][1].p : x.psiHin[2][0].p;
+      const gf* pc1o = lh ? x.psiHin[0][0].p : x.psiHin[1][1].p;
+      aHh[0] = pc1z[ohz];
+      aHh[1] = pc1o[lh ? ohx : ohy];
+      aHh[2] = x.psiHin[0][1][ohx];
+      aHh[3] = x.psiHin[1][0][ohy];
+      if (sz >= 0) {  // uniform: the z grading exists only with z slabs
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          gzE[q] = x.prof[2][q * x.nz + k];
+          gzH[q] = x.prof[2][(3 + q) * x.nz + k];
+        }
+      }
+    }
+    // the loads two planes ahead go out after this plane's psi: the memory
+    // counter retires in order, so waiting for the psi does not wait for them
+    load_e(k + 3, S, k + 2 < k1);
     // E^n of the own cell (plane k), read before the second barrier: after it a
     // faster wave may already be staging plane k+2 into this buffer
     float eo[3];
@@ -496,7 +570,28 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       const float* Ex1 = s.E[nb][0];
       const float* Ey1 = s.E[nb][1];
       const int a = own_slot;
-      if (act) {
+      if (act && AX) {
+        const int xi = tx + 1, yj = ty + 1;
+        const float* gxh[3] = {s.gx[3], s.gx[4], s.gx[5]};
+        const float* gyh[3] = {s.gy[3], s.gy[4], s.gy[5]};
+        float d1 = Ez[a + W] - Ez[a], d2 = Ey1[a] - Ey[a];
+        d1 = stretch_v(d1, syo, gyh[0][yj], gyh[1][yj], gyh[2][yj], aH[0], true, x.psiHout[1][1], oy);
+        d2 = stretch_v(d2, sz, gzH[0], gzH[1], gzH[2], aH[1], true, x.psiHout[2][0], oz);
+        hx = fmaf(-x.ch, d1 - d2, S.ho[0]);
+        d1 = Ex1[a] - Ex[a];
+        d2 = Ez[a + 1] - Ez[a];
+        d1 = stretch_v(d1, sz, gzH[0], gzH[1], gzH[2], aH[2], true, x.psiHout[2][1], oz);
+        d2 = stretch_v(d2, sxo, gxh[0][xi], gxh[1][xi], gxh[2][xi], aH[3], true, x.psiHout[0][0], ox);
+        hy = fmaf(-x.ch, d1 - d2, S.ho[1]);
+        d1 = Ey[a + 1] - Ey[a];
+        d2 = Ex[a + W] - Ex[a];
+        d1 = stretch_v(d1, sxo, gxh[0][xi], gxh[1][xi], gxh[2][xi], aH[4], true, x.psiHout[0][1], ox);
+        d2 = stretch_v(d2, syo, gyh[0][yj], gyh[1][yj], gyh[2][yj], aH[5], true, x.psiHout[1][0], oy);
+        hz = fmaf(-x.ch, d1 - d2, S.ho[2]);
+        x.Hout[0][o] = hx;
+        x.Hout[1][o] = hy;
+        x.Hout[2][o] = hz;
+      } else if (act) {
         hx = h_from<PMM, ZP>(x, 0, 1, j, 2, k, i, j, k, Ez[a + W], Ez[a], Ey1[a], Ey[a], S.ho[0], true, sz, c, S.ph[0], S.gh);
         hy = h_from<PMM, ZP>(x, 1, 2, k, 0, i, i, j, k, Ex1[a], Ex[a], Ez[a + 1], Ez[a], S.ho[1], true, sz, c, S.ph[1], S.gh);
         hz = h_from<PMM, ZP>(x, 2, 0, i, 1, j, i, j, k, Ey[a + 1], Ey[a], Ex[a + W], Ex[a], S.ho[2], true, sz, c, 0.0f, S.gh);
@@ -512,19 +607,47 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         if (lh) {
           // cell (i0-1, j0+t): LDS column 0, row t+1
           const int e = (t + 1) * W;
-          const float hyv = h_from<PMM, ZP>(x, 1, 2, k, 0, hgi, hgi, hgj, k, Ex1[e], Ex[e], Ez[e + 1], Ez[e], S.hh[1],
-                                           false, sz, h_off, S.phh[1], S.gh);
-          const float hzv = h_from<PMM, ZP>(x, 2, 0, hgi, 1, hgj, hgi, hgj, k, Ey[e + 1], Ey[e], Ex[e + W], Ex[e],
-                                           S.hh[2], false, sz, h_off, 0.0f, S.gh);
+          float hyv, hzv;
+          if (AX) {
+            const int yj = t + 1;  // hgj = j0 + t; the column i0-1 is x-table entry 0
+            float d1 = Ex1[e] - Ex[e], d2 = Ez[e + 1] - Ez[e];
+            d1 = stretch_v(d1, sz, gzH[0], gzH[1], gzH[2], aHh[0], false, x.psiHout[2][1], 0u);
+            d2 = stretch_v(d2, sxh, s.gx[3][0], s.gx[4][0], s.gx[5][0], aHh[1], false, x.psiHout[0][0], 0u);
+            hyv = fmaf(-x.ch, d1 - d2, S.hh[1]);
+            d1 = Ey[e + 1] - Ey[e];
+            d2 = Ex[e + W] - Ex[e];
+            d1 = stretch_v(d1, sxh, s.gx[3][0], s.gx[4][0], s.gx[5][0], aHh[2], false, x.psiHout[0][1], 0u);
+            d2 = stretch_v(d2, syh, s.gy[3][yj], s.gy[4][yj], s.gy[5][yj], aHh[3], false, x.psiHout[1][0], 0u);
+            hzv = fmaf(-x.ch, d1 - d2, S.hh[2]);
+          } else {
+            hyv = h_from<PMM, ZP>(x, 1, 2, k, 0, hgi, hgi, hgj, k, Ex1[e], Ex[e], Ez[e + 1], Ez[e], S.hh[1],
+                                  false, sz, h_off, S.phh[1], S.gh);
+            hzv = h_from<PMM, ZP>(x, 2, 0, hgi, 1, hgj, hgi, hgj, k, Ey[e + 1], Ey[e], Ex[e + W], Ex[e],
+                                  S.hh[2], false, sz, h_off, 0.0f, S.gh);
+          }
           s.H[1][(t + 1) * (TX + 1)] = hyv;
           s.H[2][(t + 1) * (TX + 1)] = hzv;
         } else {
           // cell (i0+q-1, j0-1): LDS row 0, column q
           const int q = t - TY + 1;
-          const float hxv = h_from<PMM, ZP>(x, 0, 1, hgj, 2, k, hgi, hgj, k, Ez[W + q], Ez[q], Ey1[q], Ey[q], S.hh[0],
-                                           false, sz, h_off, S.phh[0], S.gh);
-          const float hzv = h_from<PMM, ZP>(x, 2, 0, hgi, 1, hgj, hgi, hgj, k, Ey[q + 1], Ey[q], Ex[W + q], Ex[q],
-                                           S.hh[2], false, sz, h_off, 0.0f, S.gh);
+          float hxv, hzv;
+          if (AX) {
+            // hgi = i0 + q - 1: x-table entry q; the row j0-1 is y-table entry 0
+            float d1 = Ez[W + q] - Ez[q], d2 = Ey1[q] - Ey[q];
+            d1 = stretch_v(d1, syh, s.gy[3][0], s.gy[4][0], s.gy[5][0], aHh[1], false, x.psiHout[1][1], 0u);
+            d2 = stretch_v(d2, sz, gzH[0], gzH[1], gzH[2], aHh[0], false, x.psiHout[2][0], 0u);
+            hxv = fmaf(-x.ch, d1 - d2, S.hh[0]);
+            d1 = Ey[q + 1] - Ey[q];
+            d2 = Ex[W + q] - Ex[q];
+            d1 = stretch_v(d1, sxh, s.gx[3][q], s.gx[4][q], s.gx[5][q], aHh[2], false, x.psiHout[0][1], 0u);
+            d2 = stretch_v(d2, syh, s.gy[3][0], s.gy[4][0], s.gy[5][0], aHh[3], false, x.psiHout[1][0], 0u);
+            hzv = fmaf(-x.ch, d1 - d2, S.hh[2]);
+          } else {
+            hxv = h_from<PMM, ZP>(x, 0, 1, hgj, 2, k, hgi, hgj, k, Ez[W + q], Ez[q], Ey1[q], Ey[q], S.hh[0],
+                                  false, sz, h_off, S.phh[0], S.gh);
+            hzv = h_from<PMM, ZP>(x, 2, 0, hgi, 1, hgj, hgi, hgj, k, Ey[q + 1], Ey[q], Ex[W + q], Ex[q],
+                                  S.hh[2], false, sz, h_off, 0.0f, S.gh);
+          }
           s.H[0][q] = hxv;
           s.H[2][q] = hzv;
         }
@@ -582,7 +705,10 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       }
       if (!((!x.py && j == 0) || (!x.pz && k == 0))) {  // Ex: d/dy Hz - d/dz Hy
         float d1 = hz - hz_jm, d2 = hy - hym;
-        if (PMM) {
+        if (AX) {
+          d1 = stretch_v(d1, syo, s.gy[0][ty + 1], s.gy[1][ty + 1], s.gy[2][ty + 1], aE[0], true, x.psiE[1][1], oy);
+          d2 = stretch_v(d2, sz, gzE[0], gzE[1], gzE[2], aE[1], true, x.psiE[2][0], oz);
+        } else if (PMM) {
           d1 = stretch<false, PMM>(x, 0, 1, j, i, j, k, d1, true);
           d2 = ZP ? stretch_z<false>(x, 0, S.ge, sz, c, d2, true, S.pe[0]) : stretch<false, PMM>(x, 0, 2, k, i, j, k, d2, true);
         }
@@ -590,7 +716,10 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       }
       if (!((!x.pz && k == 0) || (!x.px && i == 0))) {  // Ey: d/dz Hx - d/dx Hz
         float d1 = hx - hxm, d2 = hz - hz_im;
-        if (PMM) {
+        if (AX) {
+          d1 = stretch_v(d1, sz, gzE[0], gzE[1], gzE[2], aE[2], true, x.psiE[2][1], oz);
+          d2 = stretch_v(d2, sxo, s.gx[0][tx + 1], s.gx[1][tx + 1], s.gx[2][tx + 1], aE[3], true, x.psiE[0][0], ox);
+        } else if (PMM) {
           d1 = ZP ? stretch_z<false>(x, 1, S.ge, sz, c, d1, true, S.pe[1]) : stretch<false, PMM>(x, 1, 2, k, i, j, k, d1, true);
           d2 = stretch<false, PMM>(x, 1, 0, i, i, j, k, d2, true);
         }
@@ -598,7 +727,10 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       }
       if (!((!x.px && i == 0) || (!x.py && j == 0))) {  // Ez: d/dx Hy - d/dy Hx
         float d1 = hy - hy_im, d2 = hx - hx_jm;
-        if (PMM) {
+        if (AX) {
+          d1 = stretch_v(d1, sxo, s.gx[0][tx + 1], s.gx[1][tx + 1], s.gx[2][tx + 1], aE[4], true, x.psiE[0][1], ox);
+          d2 = stretch_v(d2, syo, s.gy[0][ty + 1], s.gy[1][ty + 1], s.gy[2][ty + 1], aE[5], true, x.psiE[1][0], oy);
+        } else if (PMM) {
           d1 = stretch<false, PMM>(x, 2, 0, i, i, j, k, d1, true);
           d2 = stretch<false, PMM>(x, 2, 1, j, i, j, k, d2, true);
         }

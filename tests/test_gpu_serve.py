@@ -8,7 +8,8 @@ pytestmark = pytest.mark.gpu
 
 def _trace():
     return [
-        {"id": 0, "arrival": 0.00, "kind": "linear", "n": 1, "res": 10, "delta": 0.05, "seed": 501, "steps": 600, "nf": 12},
+        # long enough (several 10 ms) that the later arrivals join while it runs
+        {"id": 0, "arrival": 0.00, "kind": "linear", "n": 1, "res": 10, "delta": 0.05, "seed": 501, "steps": 8000, "nf": 12},
         {"id": 1, "arrival": 0.00, "kind": "lasing", "n": 1, "res": 8, "delta": 0.08, "seed": 502, "steps": 400},
         {"id": 2, "arrival": 0.02, "kind": "linear", "n": 2, "res": 8, "delta": 0.00, "seed": 503, "steps": 400, "nf": 8},
         {"id": 3, "arrival": 0.05, "kind": "linear", "n": 1, "res": 12, "delta": 0.10, "seed": 504, "steps": 800, "nf": 10},
