@@ -742,6 +742,9 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
   d.ch = (float)(p->dt / p->dx);
   d.nmat = (int)p->mats.size();
   d.has_gain = p->has_gain ? 1 : 0;
+  d.gainmask = 0u;
+  for (size_t m = 0; m < p->mats.size(); ++m)
+    if (p->mats[m].gain) d.gainmask |= 1u << m;
   d.block = p->tune.block;
   d.step = 0;
   d.max_steps = max_steps;

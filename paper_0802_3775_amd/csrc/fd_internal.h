@@ -37,6 +37,7 @@ struct fd_desc {
   float ch;                    // dt / dx
   int nmat;
   int has_gain;
+  unsigned gainmask;  // bit m: material m is a gain medium
   int block;                   // threads per workgroup used for this plan's tiles
   long long step;              // absolute step at batch step 0 (advanced on the device)
   long long max_steps;

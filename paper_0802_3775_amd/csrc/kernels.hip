@@ -317,6 +317,8 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   Ctx x;
   make_ctx(x, d, par, PM != 0);
   const int i0 = tl.i0, j0 = tl.j0, k0 = tl.k0, k1 = tl.k1;
+  const unsigned gmask = GAIN ? d->gainmask : 0u;
+  const size_t ncs = (size_t)d->ncell;
   const int i = i0 + tx, j = j0 + ty;
   const bool act = i < x.nx && j < x.ny;
   const int c = j * x.nx + i;
@@ -552,8 +554,25 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         }
       }
     }
-    // the loads two planes ahead go out after this plane's psi: the memory
-    // counter retires in order, so waiting for the psi does not wait for them
+    // gain-cell inputs of plane k (populations, P^n, P^{n-1}), consumed in the E
+    // update; other lanes read element 0
+    float gnh[3], gnl[3], gPn[3], gPm[3];
+    bool gk = false;
+    if (GAIN) {
+      gk = act && ((gmask >> S.m) & 1u);
+      const uint32_t ig = gk ? (uint32_t)o : 0u;
+      const gf* pop = G(d->pop);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        gnh[q] = pop[(size_t)q * ncs + ig];
+        gnl[q] = pop[(size_t)(3 + q) * ncs + ig];
+        gPn[q] = G((const float*)d->P[par][q])[ig];
+        gPm[q] = G((const float*)d->P[par ^ 1][q])[ig];
+      }
+    }
+    // the loads two planes ahead go out after this plane's psi and gain inputs:
+    // the memory counter retires in order, so waiting for those does not wait
+    // for them
     load_e(k + 3, S, k + 2 < k1);
     // E^n of the own cell (plane k), read before the second barrier: after it a
     // faster wave may already be staging plane k+2 into this buffer
@@ -663,15 +682,13 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       const fd_mat& mt = s.mat[S.m];
       float dP[3] = {0.0f, 0.0f, 0.0f};
       float Pnew[3] = {0.0f, 0.0f, 0.0f};
-      const bool g = GAIN && mt.is_gain;
+      const bool g = GAIN && gk;
       float nh[3] = {0.0f, 0.0f, 0.0f}, nl[3] = {0.0f, 0.0f, 0.0f};
       if (g) {
-        const int nc = d->ncell;
-        const gf* pop = G(d->pop);
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          nh[q] = pop[(size_t)q * nc + o];
-          nl[q] = pop[(size_t)(3 + q) * nc + o];
+          nh[q] = gnh[q];
+          nl[q] = gnl[q];
         }
         const float n1 = nh[0] + nl[0], n2 = nh[1] + nl[1];
         float F[3] = {0.0f, 0.0f, 0.0f};
@@ -685,8 +702,8 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         const float dn = n1 - n2;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          const float Pn = G((const float*)d->P[par][q])[o];
-          const float Pm = G((const float*)d->P[par ^ 1][q])[o];
+          const float Pn = gPn[q];
+          const float Pm = gPm[q];
           Pnew[q] = fmaf(mt.C1, Pn, fmaf(mt.C2, Pm, fmaf(mt.C3k * dn, eo[q], mt.C3 * F[q])));
           dP[q] = Pnew[q] - Pn;
         }
