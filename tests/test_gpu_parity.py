@@ -166,6 +166,35 @@ def test_beam_full_box_parity():
     assert rel_l2(gpu.probe(0), orc.probe(0)) <= 1e-4
 
 
+def test_tail_fit_and_decay_times_from_gpu_and_oracle_agree():
+    """The host analysis of T(t) (leading decay time tau0 and D = L^2/(pi^2 tau0),
+    decay-time distribution g(tau)) gives the same answers from the GPU's T(t)
+    as from the oracle's, on a reduced disordered slab long enough for a tail."""
+    from paper_0802_3775_amd import analysis as A
+    steps = 4000
+    cfg = W.slab(delta=0.08, seed=23, res=10, cells=(2, 2, 3), steps=steps, nf=0, decim=8)
+    _say("tail", cfg["grid"]["n"], steps)
+    orc = run_oracle(cfg, steps)
+    gpu = run_gpu(cfg, steps, tuning={"block": 128, "zchunk": 8, "graph_steps": 50, "tile_x": 16})
+    dt = 0.5 / 10
+    t = A.time_axis(steps, dt)
+    Tg, To = gpu.flux(0)[0], orc.flux(0)[0]
+    assert rel_l2(Tg, To) <= 1e-3
+    win = A.tail_window(To, hi=0.3, lo=1e-3)
+    tg, _, _ = A.fit_tau0(t, Tg, window=win)
+    to, _, _ = A.fit_tau0(t, To, window=win)
+    _say("tau0", tg, to)
+    assert abs(tg - to) <= 1e-3 * abs(to)
+    L = A.to_seconds(3.0, 480e-9) * 299792458.0      # 3 cells of a = 480 nm, in metres
+    Dg = A.diffusion_constant(L, A.to_seconds(tg, 480e-9))
+    Do = A.diffusion_constant(L, A.to_seconds(to, 480e-9))
+    assert abs(Dg - Do) <= 1e-3 * Do
+    taus = np.geomspace(1.0, 400.0, 24)
+    gg, _ = A.decay_time_distribution(t, Tg, taus, window=win)
+    go, _ = A.decay_time_distribution(t, To, taus, window=win)
+    assert rel_l2(gg, go) <= 1e-2
+
+
 def test_slab_full_size_random_fields():
     """Full slab grid (80x80x224, z-CPML) from random initial fields: every cell,
     the CPML slabs and the periodic wrap are exercised at the benchmark's size and
