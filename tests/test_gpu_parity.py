@@ -172,7 +172,7 @@ def test_tail_fit_and_decay_times_from_gpu_and_oracle_agree():
     as from the oracle's, on a reduced disordered slab long enough for a tail."""
     from paper_0802_3775_amd import analysis as A
     steps = 4000
-    cfg = W.slab(delta=0.08, seed=23, res=10, cells=(2, 2, 3), steps=steps, nf=0, decim=8)
+    cfg = W.slab(delta=0.08, seed=23, res=10, cells=(2, 2, 3), steps=steps, nf=4, decim=8)
     _say("tail", cfg["grid"]["n"], steps)
     orc = run_oracle(cfg, steps)
     gpu = run_gpu(cfg, steps, tuning={"block": 128, "zchunk": 8, "graph_steps": 50, "tile_x": 16})
