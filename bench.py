@@ -208,16 +208,21 @@ def measure_batched(args, steps=300):
     from paper_0802_3775_amd import fdtd, tune
     from paper_0802_3775_amd import workloads as W
     cfgs = W.ensemble(count=64, steps=10000)
-    tuning = tune.common_tuning(cfgs, budget_s=args.tune_seconds)
+    tuning = tune.tune_batch(cfgs, budget_s=args.tune_seconds)
+    seq_tuning = tune.common_tuning(cfgs, budget_s=args.tune_seconds)  # tuned for plain runs
     total = 2 * steps + 100
+    cells = 0
+    seq = 0.0
+    for c in cfgs:           # sequential plain: each realization alone
+        p = fdtd.Plan(c, max_steps=steps + 50, tuning=seq_tuning)
+        cells += p.ncell
+        p.step(50)
+        seq += timed_run(p, steps)
+        p.close()
     plans = [fdtd.Plan(c, max_steps=total, tuning=tuning) for c in cfgs]
-    cells = sum(p.ncell for p in plans)
-    log("batched: %d realizations, %d cells, tuning %s" % (len(plans), cells, tuning))
+    log("batched: %d realizations, %d cells, tuning %s (sequential runs: %s)" % (len(plans), cells, tuning, seq_tuning))
     for p in plans:
         p.step(50)
-    seq = 0.0
-    for p in plans:          # sequential plain: each realization alone
-        seq += timed_run(p, steps)
     b = fdtd.Batch(plans)
     b.step(50)
     torch.cuda.synchronize()
@@ -230,6 +235,7 @@ def measure_batched(args, steps=300):
         p.close()
     scale = 10000.0 / steps
     return {"realizations": len(cfgs), "cells": cells, "steps_timed": steps, "tuning": tuning,
+            "sequential_tuning": seq_tuning,
             "cell_updates_per_s": cells * steps / tb,
             "sequential_cell_updates_per_s": cells * steps / seq,
             "realizations_per_hour": 3600.0 * len(cfgs) / (tb * scale),

@@ -140,3 +140,68 @@ def common_tuning(cfgs, budget_s=30.0, verbose=False):
     member, keep its tile shape for all."""
     big = max(cfgs, key=lambda c: c["grid"]["n"][0] * c["grid"]["n"][1] * c["grid"]["n"][2])
     return autotune(big, budget_s=budget_s, verbose=verbose)
+
+
+def _cells(c):
+    n = c["grid"]["n"]
+    return n[0] * n[1] * n[2]
+
+
+def _time_batch(cfgs, tune, steps, warm):
+    import torch
+    from . import fdtd
+    plans = [fdtd.Plan(dict(c, steps=steps + warm), max_steps=steps + warm, tuning=tune) for c in cfgs]
+    b = None
+    try:
+        b = fdtd.Batch(plans)
+        b.step(warm)
+        torch.cuda.synchronize()
+        return b.time_steps(steps) / steps
+    finally:
+        if b is not None:
+            b.close()
+        for p in plans:
+            p.close()
+
+
+def tune_batch(cfgs, budget_s=20.0, sample=8, use_cache=True, verbose=False):
+    """One tuning for a batch of uneven realizations, timed on the batch itself:
+    a sample of members spread over the size range is stepped as a Batch for
+    every candidate tile shape (members share tile_x and block, and a tile wider
+    than a member's grid wastes lanes, so the largest member's own best is not
+    the batch's), then for each class grouping and graph length."""
+    members = sorted(cfgs, key=_cells)
+    if len(members) > sample:
+        idx = [round(q * (len(members) - 1) / (sample - 1)) for q in range(sample)]
+        members = [members[q] for q in sorted(set(idx))]
+    key = "batch|" + "|".join(sorted(shape_key(c) for c in members))
+    cache = _load_cache() if use_cache else {}
+    if key in cache:
+        return dict(cache[key]["tuning"])
+    total = sum(_cells(c) for c in members)
+    steps = int(max(8, min(100, 2e8 / max(total, 1))))
+    t_end = time.perf_counter() + budget_s
+    best, best_ms = None, float("inf")
+    for cand in candidates(members[-1]):
+        if time.perf_counter() > t_end and best is not None:
+            break
+        tune = dict(cand, graph_steps=50)
+        ms = _time_batch(members, tune, steps, 4)
+        if verbose:
+            print("batch tune %s: %.2f us/step" % (tune, ms * 1e3), flush=True)
+        if ms < best_ms:
+            best, best_ms = tune, ms
+    for merge, par in ((0, 0), (2, 0)):
+        if time.perf_counter() > t_end:
+            break
+        tune = dict(best, merge=merge, parallel=par)
+        ms = _time_batch(members, tune, steps, 4)
+        if verbose:
+            print("batch tune %s: %.2f us/step" % (tune, ms * 1e3), flush=True)
+        if ms < best_ms:
+            best, best_ms = tune, ms
+    if use_cache:
+        cache = _load_cache()
+        cache[key] = {"tuning": best, "us_per_step": best_ms * 1e3}
+        _save_cache(cache)
+    return dict(best)
