@@ -153,6 +153,7 @@ struct fdtd_plan {
   std::vector<double> tcost[FD_NCLASS];  // algorithmic bytes of each tile (XCD balancing)
   fd_xcd part[FD_NCLASS] = {};
   int pgrid[FD_NCLASS] = {};
+  int ntst = 0;  // non-temporal field stores: state well beyond the Infinity Cache
   fd_tile* dtiles[FD_NCLASS] = {};
   std::vector<fd_dft_tile> dft;
   fd_dft_tile* ddft = nullptr;
@@ -174,6 +175,7 @@ struct fdtd_batch {
   std::vector<fd_tile> tiles[FD_NCLASS];
   fd_xcd part[FD_NCLASS] = {};
   int pgrid[FD_NCLASS] = {};
+  int ntst = 0;
   std::vector<fd_dft_tile> dft;
   int maxnf = 0;
   void* dmem = nullptr;  // tile tables + desc pointer list (setup-time allocation)
@@ -303,6 +305,19 @@ size_t psi_elems(const fdtd_plan* p, int w) {
   return nz * t * nx;
 }
 
+// Bytes a step streams through: both field buffers, the material map, the psi
+// slabs and the gain arrays.  Above four times the Infinity Cache (256 MB on
+// MI355X) the field stores go out non-temporal; between one and four times it
+// part of the next step's reads still hit there (measured on a 0.46 GB grid).
+constexpr size_t kInfinityCacheBytes = (size_t)256 << 20;
+constexpr size_t kNonTemporalBytes = 4 * kInfinityCacheBytes;
+size_t step_state_bytes(const fdtd_plan* p) {
+  size_t b = (size_t)p->ncell * 49;
+  for (int w = 0; w < 3; ++w) b += 6 * 4 * psi_elems(p, w);
+  if (p->has_gain) b += (size_t)p->ncell * 48;
+  return b;
+}
+
 // z ranges of the tiles: split at the CPML slab interfaces, then into chunks.
 std::vector<std::pair<int, int>> z_chunks(const fdtd_plan* p, int zchunk) {
   std::vector<int> cuts = {0};
@@ -423,7 +438,7 @@ T* at(fdtd_plan* p, size_t off) {
 // Fork (graph capture) the non-empty classes become parallel graph branches.
 int enqueue_step(fd_tile* const dtiles[FD_NCLASS], const std::vector<fd_tile>* tiles, const fd_xcd* part,
                  const int* pgrid, int tile_x, int block, int max_blocks, const fd_dft_tile* ddft, int ndft,
-                 int maxnf, bool dft_due, int s, hipStream_t st, Fork* fk) {
+                 int maxnf, bool dft_due, int s, int ntst, hipStream_t st, Fork* fk) {
   int used[FD_NCLASS], nused = 0;
   for (int c = 0; c < FD_NCLASS; ++c)
     if (!tiles[c].empty()) used[nused++] = c;
@@ -439,7 +454,7 @@ int enqueue_step(fd_tile* const dtiles[FD_NCLASS], const std::vector<fd_tile>* t
       on = fk->side[c];
       HIPCHK(hipStreamWaitEvent(on, fk->fork, 0));
     }
-    HIPCHK(fd_launch_step(c, dtiles[c], nt, tile_x, block, grid, s, pc, on));
+    HIPCHK(fd_launch_step(c, dtiles[c], nt, tile_x, block, grid, s, pc, ntst, on));
     if (par && u > 0) HIPCHK(hipEventRecord(fk->join[c], on));
   }
   if (par)
@@ -466,7 +481,7 @@ int plan_enqueue(fdtd_plan* p, int64_t n, hipStream_t st, Fork* fk) {
   for (int64_t s = 0; s < n; ++s) {
     const int r = enqueue_step(p->dtiles, p->tiles, p->part, p->pgrid, p->tune.tile_x, p->tune.block,
                                p->tune.max_blocks, p->ddft, (int)p->dft.size(), p->maxnf,
-                               plan_dft_due(p, p->step + s), (int)s, st, fk);
+                               plan_dft_due(p, p->step + s), (int)s, p->ntst, st, fk);
     if (r) return r;
   }
   HIPCHK(fd_launch_advance_one(p->ddesc, n, st));
@@ -1033,6 +1048,7 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
     HIPCHK(hipMemcpyAsync(p->ddft, p->dft.data(), sizeof(fd_dft_tile) * p->dft.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
   p->step = 0;
+  p->ntst = step_state_bytes(p) > kNonTemporalBytes ? 1 : 0;
   p->bound = true;
   return FDTD_OK;
 }
@@ -1348,7 +1364,7 @@ int fdtd_time_kernels(fdtd_plan* p, int64_t n, void* stream, double* ms, int64_t
       const int grid = p->tune.max_blocks > 0 ? std::min(nt, p->tune.max_blocks) : p->pgrid[c];
       const fd_xcd* pc = p->tune.max_blocks > 0 ? nullptr : &p->part[c];
       const int r = record(c, [&](hipEvent_t a, hipEvent_t b) {
-        return fd_launch_step(c, p->dtiles[c], nt, p->tune.tile_x, p->tune.block, grid, (int)s, pc, st, a, b);
+        return fd_launch_step(c, p->dtiles[c], nt, p->tune.tile_x, p->tune.block, grid, (int)s, pc, p->ntst, st, a, b);
       });
       if (r) { cleanup(); return r; }
     }
@@ -1412,6 +1428,9 @@ int fdtd_batch_create(fdtd_plan* const* plans, int32_t n, fdtd_batch** out) {
     b->maxnf = std::max(b->maxnf, p->maxnf);
   }
   for (int c = 0; c < FD_NCLASS; ++c) b->part[c] = xcd_partition(bcost[c], &b->pgrid[c]);
+  // Batches keep ordinary stores: over a 64-member ensemble of 1.9 GB the
+  // non-temporal form measured about 10% slower, while a single 2 GB grid gains.
+  b->ntst = 0;
   size_t bytes = 0;
   size_t off_t[FD_NCLASS];
   for (int c = 0; c < FD_NCLASS; ++c) {
@@ -1471,7 +1490,7 @@ static bool batch_dft_due(const fdtd_batch* b, int64_t s) {
 static int batch_enqueue(fdtd_batch* b, int64_t n, hipStream_t st, Fork* fk) {
   for (int64_t s = 0; s < n; ++s) {
     const int r = enqueue_step(b->dtiles, b->tiles, b->part, b->pgrid, b->tile_x, b->block, b->max_blocks, b->ddft,
-                               (int)b->dft.size(), b->maxnf, batch_dft_due(b, s), (int)s, st, fk);
+                               (int)b->dft.size(), b->maxnf, batch_dft_due(b, s), (int)s, b->ntst, st, fk);
     if (r) return r;
   }
   HIPCHK(fd_launch_advance(b->ddescs, (int)b->plans.size(), n, st));

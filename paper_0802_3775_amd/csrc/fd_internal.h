@@ -120,8 +120,9 @@ struct fd_xcd {
 
 // part == nullptr: grid-stride loop over the tiles with the plain XCD renumbering
 // start / stop (optional): events that take the kernel's own begin and end timestamps
+// nt: non-temporal field stores (the launch's working set exceeds the Infinity Cache)
 hipError_t fd_launch_step(int cls, const fd_tile* tiles, int ntiles, int tile_x, int block, int grid,
-                          int s, const fd_xcd* part, hipStream_t st, hipEvent_t start = nullptr,
+                          int s, const fd_xcd* part, int nt, hipStream_t st, hipEvent_t start = nullptr,
                           hipEvent_t stop = nullptr);
 hipError_t fd_launch_dft(const fd_dft_tile* tiles, int ntiles, int s, hipStream_t st, hipEvent_t start = nullptr,
                          hipEvent_t stop = nullptr);

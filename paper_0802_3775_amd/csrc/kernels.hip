@@ -299,7 +299,7 @@ struct Lds {
 // every z-CPML test (PMM), so interior tiles of a CPML launch run the same
 // code as tiles of a plain launch; the plane below the range still takes the
 // general path.
-template <int TX, int PM, bool GAIN, bool ZT>
+template <int TX, int PM, bool GAIN, bool ZT, bool NT>
 __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   const cdesc* d = (const cdesc*)tl.d;
   constexpr int W = Lds<TX>::W;
@@ -319,6 +319,14 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   const int i0 = tl.i0, j0 = tl.j0, k0 = tl.k0, k1 = tl.k1;
   const unsigned gmask = GAIN ? d->gainmask : 0u;
   const size_t ncs = (size_t)d->ncell;
+  // field stores: non-temporal (NT) when the launch's working set exceeds the
+  // Infinity Cache, so they stream to HBM without displacing lines that are
+  // still to be read; a compile-time choice (a runtime branch between the two
+  // forms of the same store is merged into the plain one by the compiler)
+  auto put = [&](const R32<float>& a, int idx, float v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, &a[idx]);
+    else a[idx] = v;
+  };
   const int i = i0 + tx, j = j0 + ty;
   const bool act = i < x.nx && j < x.ny;
   const int c = j * x.nx + i;
@@ -607,16 +615,16 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         d1 = stretch_v(d1, sxo, gxh[0][xi], gxh[1][xi], gxh[2][xi], aH[4], true, x.psiHout[0][1], ox);
         d2 = stretch_v(d2, syo, gyh[0][yj], gyh[1][yj], gyh[2][yj], aH[5], true, x.psiHout[1][0], oy);
         hz = fmaf(-x.ch, d1 - d2, S.ho[2]);
-        x.Hout[0][o] = hx;
-        x.Hout[1][o] = hy;
-        x.Hout[2][o] = hz;
+        put(x.Hout[0], o, hx);
+        put(x.Hout[1], o, hy);
+        put(x.Hout[2], o, hz);
       } else if (act) {
         hx = h_from<PMM, ZP>(x, 0, 1, j, 2, k, i, j, k, Ez[a + W], Ez[a], Ey1[a], Ey[a], S.ho[0], true, sz, c, S.ph[0], S.gh);
         hy = h_from<PMM, ZP>(x, 1, 2, k, 0, i, i, j, k, Ex1[a], Ex[a], Ez[a + 1], Ez[a], S.ho[1], true, sz, c, S.ph[1], S.gh);
         hz = h_from<PMM, ZP>(x, 2, 0, i, 1, j, i, j, k, Ey[a + 1], Ey[a], Ex[a + W], Ex[a], S.ho[2], true, sz, c, 0.0f, S.gh);
-        x.Hout[0][o] = hx;
-        x.Hout[1][o] = hy;
-        x.Hout[2][o] = hz;
+        put(x.Hout[0], o, hx);
+        put(x.Hout[1], o, hy);
+        put(x.Hout[2], o, hz);
       }
       const int hs = (ty + 1) * (TX + 1) + tx + 1;
       s.H[0][hs] = hx;
@@ -753,9 +761,9 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         }
         ez_n = fmaf(mt.cb, (d1 - d2) - cz, eo[2]) - dP[2] * mt.inv_eps;
       }
-      x.Eout[0][o] = ex_n;
-      x.Eout[1][o] = ey_n;
-      x.Eout[2][o] = ez_n;
+      put(x.Eout[0], o, ex_n);
+      put(x.Eout[1], o, ey_n);
+      put(x.Eout[2], o, ez_n);
       if (g) {
         const float en[3] = {ex_n, ey_n, ez_n};
         float u = 0.0f;
@@ -843,15 +851,15 @@ __device__ __forceinline__ int xcd_tile(int w, int n) {
 // With a cost-balanced partition (use_part), workgroup w takes tile
 // part.start[x] + w/8 of XCD x = w mod 8, or nothing if that part is shorter;
 // otherwise the workgroups loop over the renumbered tile list.
-template <int TX, int PM, bool GAIN>
+template <int TX, int PM, bool GAIN, bool NT>
 __global__ __launch_bounds__(FD_MAXBLOCK) void step_kernel(const fd_tile* __restrict__ tiles, int ntiles, int s,
                                                            fd_xcd part, int use_part) {
   __shared__ Lds<TX> lds;
   // z-only CPML launches specialise their interior tiles; the all-axes kernel
   // keeps one general march (two would not fit its register budget)
   auto run = [&](const fd_tile& tl) {
-    if (PM == 4 && !(tl.flags & FD_TILE_ZSLAB)) run_tile<TX, PM, GAIN, false>(tl, s, lds);
-    else run_tile<TX, PM, GAIN, (PM & 4) != 0>(tl, s, lds);
+    if (PM == 4 && !(tl.flags & FD_TILE_ZSLAB)) run_tile<TX, PM, GAIN, false, NT>(tl, s, lds);
+    else run_tile<TX, PM, GAIN, (PM & 4) != 0, NT>(tl, s, lds);
   };
   if (use_part) {
     const int x = (int)blockIdx.x % 8, q = (int)blockIdx.x / 8;
@@ -1156,28 +1164,32 @@ __global__ void init_pop_kernel(const uint8_t* __restrict__ map, const float* __
 // start/stop (optional) take the kernel's own begin and end timestamps
 template <int TX, int PM, bool GAIN>
 static void launch_one(const fd_tile* tiles, int ntiles, int block, int grid, int s, const fd_xcd& part, int use,
-                       hipStream_t st, hipEvent_t start, hipEvent_t stop) {
-  hipExtLaunchKernelGGL(step_kernel<TX, PM, GAIN>, dim3(grid), dim3(block), 0, st, start, stop, 0, tiles, ntiles, s,
-                        part, use);
+                       int nt, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
+  if (nt)
+    hipExtLaunchKernelGGL(step_kernel<TX, PM, GAIN, true>, dim3(grid), dim3(block), 0, st, start, stop, 0, tiles,
+                          ntiles, s, part, use);
+  else
+    hipExtLaunchKernelGGL(step_kernel<TX, PM, GAIN, false>, dim3(grid), dim3(block), 0, st, start, stop, 0, tiles,
+                          ntiles, s, part, use);
 }
 
 template <int TX>
 static hipError_t launch_tx(int cls, const fd_tile* tiles, int ntiles, int block, int grid, int s,
-                            const fd_xcd& part, int use, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
+                            const fd_xcd& part, int use, int nt, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
   switch (cls) {
-    case FD_CLASS_PLAIN: launch_one<TX, 0, false>(tiles, ntiles, block, grid, s, part, use, st, start, stop); break;
-    case FD_CLASS_PMLZ: launch_one<TX, 4, false>(tiles, ntiles, block, grid, s, part, use, st, start, stop); break;
-    case FD_CLASS_PML: launch_one<TX, 7, false>(tiles, ntiles, block, grid, s, part, use, st, start, stop); break;
-    case FD_CLASS_GAIN: launch_one<TX, 0, true>(tiles, ntiles, block, grid, s, part, use, st, start, stop); break;
-    case FD_CLASS_PMLZ_GAIN: launch_one<TX, 4, true>(tiles, ntiles, block, grid, s, part, use, st, start, stop); break;
-    case FD_CLASS_PML_GAIN: launch_one<TX, 7, true>(tiles, ntiles, block, grid, s, part, use, st, start, stop); break;
+    case FD_CLASS_PLAIN: launch_one<TX, 0, false>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
+    case FD_CLASS_PMLZ: launch_one<TX, 4, false>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
+    case FD_CLASS_PML: launch_one<TX, 7, false>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
+    case FD_CLASS_GAIN: launch_one<TX, 0, true>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
+    case FD_CLASS_PMLZ_GAIN: launch_one<TX, 4, true>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
+    case FD_CLASS_PML_GAIN: launch_one<TX, 7, true>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t fd_launch_step(int cls, const fd_tile* tiles, int ntiles, int tile_x, int block, int grid, int s,
-                          const fd_xcd* part, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
+                          const fd_xcd* part, int nt, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
   if (ntiles <= 0) return hipSuccess;
   if (block < 64 || block > FD_MAXBLOCK || (block & 63) != 0 || grid <= 0 || block % tile_x != 0 ||
       2 * (tile_x + 2) + 2 * (block / tile_x) > block)
@@ -1197,9 +1209,9 @@ hipError_t fd_launch_step(int cls, const fd_tile* tiles, int ntiles, int tile_x,
     use = 1;
   }
   switch (tile_x) {
-    case 16: return launch_tx<16>(cls, tiles, ntiles, block, grid, s, pz, use, st, start, stop);
-    case 32: return launch_tx<32>(cls, tiles, ntiles, block, grid, s, pz, use, st, start, stop);
-    case 64: return launch_tx<64>(cls, tiles, ntiles, block, grid, s, pz, use, st, start, stop);
+    case 16: return launch_tx<16>(cls, tiles, ntiles, block, grid, s, pz, use, nt, st, start, stop);
+    case 32: return launch_tx<32>(cls, tiles, ntiles, block, grid, s, pz, use, nt, st, start, stop);
+    case 64: return launch_tx<64>(cls, tiles, ntiles, block, grid, s, pz, use, nt, st, start, stop);
     default: return hipErrorInvalidValue;
   }
 }

@@ -15,7 +15,7 @@ import json
 import os
 import time
 
-CACHE_VERSION = 4
+CACHE_VERSION = 5
 
 
 def _cache_path():
@@ -41,7 +41,7 @@ def candidates(cfg, quick=False):
     tiles = [(16, 256), (32, 256), (64, 256), (16, 128), (32, 128)]
     if quick:
         tiles = [(16, 256), (32, 256), (64, 256)]
-    chunks = [1, 2, 4, 8, 16, 32]
+    chunks = [1, 2, 4, 8, 16, 32, 48, 64]
     out = []
     for (tx, b), z in itertools.product(tiles, chunks):
         if tx > 16 and tx > 2 * nx:
