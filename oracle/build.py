@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["philox.c", "opal.c", "fdtd_ref.c"]
+SOURCES = ["philox.c", "opal.c", "bloch_ref.c", "fdtd_ref.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

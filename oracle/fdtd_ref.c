@@ -11,6 +11,12 @@
  *   4. E^{n+1} = E^n + dt/(eps dx) (curl H^{n+1/2} - dx J^{n+1/2}) - (P^{n+1}-P^n)/eps.
  *   5. four-level populations by Crank-Nicolson with the stimulated transfer
  *        u = sum_c (E_c^n + E_c^{n+1})/2 (P_c^{n+1} - P_c^n)/dt   (-u from n1, +u to n2).
+ * Density-matrix gain cells (bloch_ref.h) replace 2-5 by: the noise current
+ * sigma_N sqrt(rho_cc) g_c / sqrt(dt dx^3) on E_c, A = E^n + dt/(eps dx) (curl H -
+ * dx J), and one predictor-corrector pass of the implicit midpoint coupling
+ *        E^(0) = (E^n + A)/2,  rho* = S(rho^n; E^(0)),  E* = A - (P(rho*) - P^n)/eps,
+ *        E^(1) = (E^n + E*)/2, rho^{n+1} = S(rho^n; E^(1)),
+ *        E^{n+1} = A - (P(rho^{n+1}) - P^n)/eps,   P_c(rho) = 2 kappa Re rho_0c.
  *   6. diagnostics: probes E^{n+1}; transmitted power T at the flux plane
  *      (paper, section "Dynamical diffusion and localization": transversely
  *      integrated Poynting vector); running DFT of the plane fields; energy.
@@ -26,6 +32,7 @@
 #include <omp.h>
 #endif
 #include "oracle.h"
+#include "bloch_ref.h"
 
 #define PI 3.141592653589793238462643383279502884
 #define C_LIGHT 299792458.0
@@ -62,6 +69,10 @@ struct orc_sim {
   double* N[4];
   double C1[ORC_MAXMAT], C2[ORC_MAXMAT], C3[ORC_MAXMAT], kap[ORC_MAXMAT];
   double M[ORC_MAXMAT][4][4], B[ORC_MAXMAT][4][4];
+  /* density-matrix gain */
+  int has_bloch;
+  orc_bloch_c bc[ORC_MAXMAT];
+  orc_z* rho;       /* [ncell][4][4], zero outside gain-2 cells */
   /* sources */
   int nsrc;
   orc_source src[ORC_MAXSRC];
@@ -225,11 +236,20 @@ orc_sim* orc_create(const orc_grid* g, const orc_material* mats, int32_t nmat, i
     }
   }
   s->has_gain = 0;
-  for (int m = 0; m < nmat; ++m)
-    if (mats[m].gain) {
+  s->has_bloch = 0;
+  for (int m = 0; m < nmat; ++m) {
+    if (mats[m].gain == 1) {
       s->has_gain = 1;
       if (setup_gain(s, m)) { orc_destroy(s); return NULL; }
+    } else if (mats[m].gain == 2) {
+      s->has_bloch = 1;
+      if (orc_bloch_setup(&mats[m], s->dt, s->dx, g->a_meters, &s->bc[m])) { orc_destroy(s); return NULL; }
+    } else if (mats[m].gain != 0) {
+      orc_destroy(s);
+      return NULL;
     }
+  }
+  if (s->has_bloch) s->rho = (orc_z*)calloc((size_t)s->ncell * 16, sizeof(orc_z));
   if (s->has_gain) {
     for (int c = 0; c < 3; ++c) { s->P[c] = zalloc(s->ncell); s->Pold[c] = zalloc(s->ncell); }
     for (int q = 0; q < 4; ++q) s->N[q] = zalloc(s->ncell);
@@ -248,6 +268,7 @@ void orc_destroy(orc_sim* s) {
     free(s->kH[c]); free(s->bH[c]); free(s->cH[c]);
   }
   for (int q = 0; q < 4; ++q) free(s->N[q]);
+  free(s->rho);
   for (int p = 0; p < s->nprobe; ++p) free(s->plog[p]);
   for (int f = 0; f < s->nflux; ++f) {
     free(s->flux[f].f); free(s->flux[f].T); free(s->flux[f].acc);
@@ -265,7 +286,17 @@ int orc_set_material_map(orc_sim* s, const uint8_t* map) {
     /* initial populations from each cell's material; non-gain cells hold none */
     for (int64_t q = 0; q < s->ncell; ++q) {
       const orc_material* mt = &s->mat[map[q]];
-      for (int l = 0; l < 4; ++l) s->N[l][q] = mt->gain ? mt->n_init[l] : 0.0;
+      for (int l = 0; l < 4; ++l) s->N[l][q] = mt->gain == 1 ? mt->n_init[l] : 0.0;
+    }
+  }
+  if (s->has_bloch) {
+    /* rho = diag(n_init) in gain-2 cells, zero elsewhere */
+    for (int64_t q = 0; q < s->ncell; ++q) {
+      const orc_material* mt = &s->mat[map[q]];
+      orc_z* r = s->rho + 16 * q;
+      for (int a = 0; a < 16; ++a) r[a] = 0.0;
+      if (mt->gain == 2)
+        for (int l = 0; l < 4; ++l) r[5 * l] = mt->n_init[l];
     }
   }
   return 0;
@@ -407,10 +438,23 @@ static void update_E_and_matter(orc_sim* s, int64_t n) {
         const orc_material* mt = &s->mat[m];
         const double eps = mt->eps;
         const double cb = dt / (eps * dx);
-        double Eold[3], Pnew[3] = {0, 0, 0}, Pcur[3] = {0, 0, 0};
+        double Eold[3], Pnew[3] = {0, 0, 0}, Pcur[3] = {0, 0, 0}, A[3];
+        int pec[3] = {0, 0, 0};
         for (int c = 0; c < 3; ++c) Eold[c] = s->E[c][q];
+        /* density-matrix cells: noise current (dx J) on the E update */
+        orc_z(*r)[4] = mt->gain == 2 ? (orc_z(*)[4])(s->rho + 16 * q) : NULL;
+        double jn[3] = {0, 0, 0};
+        if (r && mt->noise != 0.0) {
+          const uint32_t ctr[4] = {(uint32_t)n, (uint32_t)q, 0u, 2u};
+          double gs[4];
+          orc_normals4(ctr, key, gs);
+          for (int c = 0; c < 3; ++c) {
+            const double pc = creal(r[c + 1][c + 1]) > 0.0 ? creal(r[c + 1][c + 1]) : 0.0;
+            jn[c] = dx * s->bc[m].noise * sqrt(pc) * gs[c];
+          }
+        }
         /* 2-3: noise and Lorentz polarization in gain cells */
-        if (mt->gain) {
+        if (mt->gain == 1) {
           double F[3] = {0, 0, 0};
           if (mt->noise != 0.0) {
             const uint32_t ctr[4] = {(uint32_t)n, (uint32_t)q, 0u, 2u};
@@ -431,7 +475,8 @@ static void update_E_and_matter(orc_sim* s, int64_t n) {
           const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
           /* tangential E on a PEC wall stays zero */
           if ((!s->g.periodic[a1] && p[a1] == 0) || (!s->g.periodic[a2] && p[a2] == 0)) {
-            s->E[c][q] = 0.0;
+            pec[c] = 1;
+            A[c] = 0.0;
             continue;
           }
           /* (curl H)_c = d_{a1} H_{a2} - d_{a2} H_{a1}, backward differences */
@@ -451,17 +496,39 @@ static void update_E_and_matter(orc_sim* s, int64_t n) {
             d2 = d2 * s->kE[a2][p[a2]] + *psi;
           }
           double curl = d1 - d2;
-          for (int r = 0; r < s->nsrc; ++r) {
-            const orc_source* src = &s->src[r];
+          for (int rr = 0; rr < s->nsrc; ++rr) {
+            const orc_source* src = &s->src[rr];
             if (src->comp != c) continue;
             if (src->kind == ORC_SRC_DIPOLE && (src->i != i || src->j != j || src->k != k)) continue;
             if (src->kind != ORC_SRC_DIPOLE && src->k != k) continue;
-            curl -= src->kind == ORC_SRC_BEAM ? dxJ[r] * beam_weight(s, src, c, i, j) : dxJ[r];
+            curl -= src->kind == ORC_SRC_BEAM ? dxJ[rr] * beam_weight(s, src, c, i, j) : dxJ[rr];
           }
-          s->E[c][q] = Eold[c] + cb * curl - (Pnew[c] - Pcur[c]) / eps;
+          curl -= jn[c];
+          A[c] = Eold[c] + cb * curl;
+        }
+        if (r) {
+          /* density matrix: predictor-corrector on the midpoint field */
+          const orc_bloch_c* bc = &s->bc[m];
+          double Pn[3], Em[3], Es[3];
+          orc_z t[4][4];
+          for (int c = 0; c < 3; ++c) {
+            Pn[c] = 2.0 * bc->kappa * creal(r[0][c + 1]);
+            Em[c] = 0.5 * (Eold[c] + A[c]);
+          }
+          orc_bloch_step(bc, dt, Em, r, t);
+          for (int c = 0; c < 3; ++c) {
+            Es[c] = pec[c] ? 0.0 : A[c] - (2.0 * bc->kappa * creal(t[0][c + 1]) - Pn[c]) / eps;
+            Em[c] = 0.5 * (Eold[c] + Es[c]);
+          }
+          orc_bloch_step(bc, dt, Em, r, t);
+          memcpy(r, t, sizeof(t));
+          for (int c = 0; c < 3; ++c)
+            s->E[c][q] = pec[c] ? 0.0 : A[c] - (2.0 * bc->kappa * creal(r[0][c + 1]) - Pn[c]) / eps;
+        } else {
+          for (int c = 0; c < 3; ++c) s->E[c][q] = pec[c] ? 0.0 : A[c] - (Pnew[c] - Pcur[c]) / eps;
         }
         /* 5: populations */
-        if (mt->gain) {
+        if (mt->gain == 1) {
           double u = 0.0;
           for (int c = 0; c < 3; ++c)
             u += 0.5 * (Eold[c] + s->E[c][q]) * (Pnew[c] - Pcur[c]) / dt;
@@ -591,14 +658,40 @@ int orc_set_field(orc_sim* s, int32_t comp, const double* in) {
 }
 
 int orc_get_populations(const orc_sim* s, double* out) {
-  if (!s->has_gain) return -1;
-  for (int l = 0; l < 4; ++l) memcpy(out + l * s->ncell, s->N[l], sizeof(double) * (size_t)s->ncell);
+  if (!s->has_gain && !s->has_bloch) return -1;
+  for (int64_t q = 0; q < s->ncell; ++q) {
+    const int g = s->mat[s->map[q]].gain;
+    for (int l = 0; l < 4; ++l)
+      out[l * s->ncell + q] = g == 1 ? s->N[l][q] : g == 2 ? creal(s->rho[16 * q + 5 * l]) : 0.0;
+  }
   return 0;
 }
 
 int orc_get_polarization(const orc_sim* s, double* out) {
-  if (!s->has_gain) return -1;
-  for (int c = 0; c < 3; ++c) memcpy(out + c * s->ncell, s->P[c], sizeof(double) * (size_t)s->ncell);
+  if (!s->has_gain && !s->has_bloch) return -1;
+  for (int64_t q = 0; q < s->ncell; ++q) {
+    const int m = s->map[q];
+    const int g = s->mat[m].gain;
+    for (int c = 0; c < 3; ++c)
+      out[c * s->ncell + q] = g == 1 ? s->P[c][q] : g == 2 ? 2.0 * s->bc[m].kappa * creal(s->rho[16 * q + 1 + c]) : 0.0;
+  }
+  return 0;
+}
+
+int orc_get_density(const orc_sim* s, double* out) {
+  if (!s->has_bloch) return -1;
+  const int64_t nc = s->ncell;
+  static const int pr[3][2] = {{1, 2}, {1, 3}, {2, 3}};
+  for (int64_t q = 0; q < nc; ++q) {
+    const orc_z* r = s->rho + 16 * q;
+    for (int k = 0; k < 3; ++k) {
+      out[k * nc + q] = creal(r[5 * (k + 1)]);
+      out[(3 + k) * nc + q] = creal(r[1 + k]);
+      out[(6 + k) * nc + q] = cimag(r[1 + k]);
+      out[(9 + k) * nc + q] = creal(r[4 * pr[k][0] + pr[k][1]]);
+      out[(12 + k) * nc + q] = cimag(r[4 * pr[k][0] + pr[k][1]]);
+    }
+  }
   return 0;
 }
 

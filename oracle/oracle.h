@@ -17,9 +17,10 @@
  *     source: same section and the lasing section.
  *   - Transmitted power T(t) = transversely integrated Poynting vector at the
  *     output face: section "Dynamical diffusion and localization".
- * The gain medium is modelled as a Lorentz polarization driven by four-level
- * population rate equations (not the paper's su(4) density matrix); every
- * reading of a point the paper leaves open is listed in the design doc.
+ * Two gain models: a Lorentz polarization driven by four-level population
+ * rate equations (gain = 1), and the paper's density-matrix model of a ground
+ * level coupled to three degenerate upper levels (gain = 2, bloch_ref.h);
+ * every reading of a point the paper leaves open is listed in the design doc.
  *
  * Units: c = eps0 = mu0 = 1; lengths in a, time in a/c, frequency in c/a.
  * Grid pitch dx = 1/res, time step dt = courant * dx.  Arrays are [nz][ny][nx],
@@ -57,13 +58,15 @@ typedef struct {
 
 typedef struct {
   double eps;                   /* relative permittivity (host permittivity for gain) */
-  int32_t gain;                 /* 1: four-level gain medium */
+  int32_t gain;                 /* 1: Lorentz + four-level rate equations; 2: density matrix */
   double n_total;               /* m^-3 */
-  double tau32, tau21, tau10;   /* s */
-  double pump;                  /* s^-1, level 0 -> 3 */
-  double f_a, df_a;             /* transition frequency and FWHM linewidth, c/a */
+  double tau32, tau21, tau10;   /* s (gain 1) */
+  double pump;                  /* s^-1: level 0 -> 3 (gain 1); 0 -> each upper level / 3 (gain 2) */
+  double f_a, df_a;             /* transition frequency and FWHM linewidth (gain 1), c/a */
   double noise;                 /* noise amplitude sigma_N */
   double n_init[4];             /* initial fractional populations n0..n3 */
+  double t1, t2;                /* s: population decay and dephasing times (gain 2) */
+  double dipole;                /* C m: transition dipole (gain 2); <= 0: radiative value from t1 */
 } orc_material;
 
 enum { ORC_SRC_DIPOLE = 0, ORC_SRC_PLANE = 1, ORC_SRC_BEAM = 2 };
@@ -124,6 +127,17 @@ int orc_get_field(const orc_sim* s, int32_t comp, double* out);   /* 0..5: Ex Ey
 int orc_set_field(orc_sim* s, int32_t comp, const double* in);
 int orc_get_populations(const orc_sim* s, double* out);          /* 4 x cells, n0..n3 */
 int orc_get_polarization(const orc_sim* s, double* out);         /* 3 x cells, P^n */
+/* Density matrix of gain-2 cells, 15 x cells: rho_11, rho_22, rho_33,
+   Re rho_01, Re rho_02, Re rho_03, Im rho_01, Im rho_02, Im rho_03,
+   Re rho_12, Re rho_13, Re rho_23, Im rho_12, Im rho_13, Im rho_23 (zero elsewhere). */
+int orc_get_density(const orc_sim* s, double* out);
+/* Matter alone (gain-2 material m, no Maxwell): nsteps steps of the splitting
+   of bloch_ref.h driven by emid (nsteps x 3); rho is 4x4 row-major (re, im)
+   pairs, in/out; hist (nsteps x 32) or NULL. */
+int orc_bloch_evolve(const orc_material* m, double dt, double dx, double a_meters, int64_t nsteps,
+                     const double* emid, double* rho, double* hist);
+/* w0, prewarped w', kappa, 1/T1, 1/T2, pump of a gain-2 material (normalised). */
+int orc_bloch_constants(const orc_material* m, double dt, double dx, double a_meters, double* out6);
 int64_t orc_get_probe(const orc_sim* s, int32_t id, double* out);
 int64_t orc_get_flux(const orc_sim* s, int32_t id, double* T, double* spec);
 int64_t orc_get_energy(const orc_sim* s, double* out);

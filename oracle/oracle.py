@@ -34,7 +34,8 @@ class Material(C.Structure):
     _fields_ = [("eps", C.c_double), ("gain", C.c_int32), ("n_total", C.c_double),
                 ("tau32", C.c_double), ("tau21", C.c_double), ("tau10", C.c_double),
                 ("pump", C.c_double), ("f_a", C.c_double), ("df_a", C.c_double),
-                ("noise", C.c_double), ("n_init", C.c_double * 4)]
+                ("noise", C.c_double), ("n_init", C.c_double * 4),
+                ("t1", C.c_double), ("t2", C.c_double), ("dipole", C.c_double)]
 
 
 class Source(C.Structure):
@@ -83,6 +84,10 @@ def lib():
         L.orc_set_field.argtypes = [C.c_void_p, C.c_int32, P(C.c_double)]
         L.orc_get_populations.argtypes = [C.c_void_p, P(C.c_double)]
         L.orc_get_polarization.argtypes = [C.c_void_p, P(C.c_double)]
+        L.orc_get_density.argtypes = [C.c_void_p, P(C.c_double)]
+        L.orc_bloch_evolve.argtypes = [P(Material), C.c_double, C.c_double, C.c_double, C.c_int64,
+                                       P(C.c_double), P(C.c_double), P(C.c_double)]
+        L.orc_bloch_constants.argtypes = [P(Material), C.c_double, C.c_double, C.c_double, P(C.c_double)]
         L.orc_get_probe.argtypes = [C.c_void_p, C.c_int32, P(C.c_double)]
         L.orc_get_probe.restype = C.c_int64
         L.orc_get_flux.argtypes = [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double)]
@@ -124,8 +129,8 @@ def make_grid(g):
 def make_material(m):
     s = Material()
     s.eps = m["eps"]
-    s.gain = 1 if m.get("gain") else 0
-    for f in ("n_total", "tau32", "tau21", "tau10", "pump", "f_a", "df_a", "noise"):
+    s.gain = int(m.get("gain") or 0)
+    for f in ("n_total", "tau32", "tau21", "tau10", "pump", "f_a", "df_a", "noise", "t1", "t2", "dipole"):
         setattr(s, f, float(m.get(f, 0.0)))
     if s.gain:
         s.n_init[:] = list(m.get("n_init", (1.0, 0.0, 0.0, 0.0)))
@@ -293,6 +298,14 @@ class OracleSim:
             raise ValueError("no gain material")
         return out
 
+    def density(self):
+        """Density matrix of the density-matrix gain cells, 15 planes (see
+        orc_get_density)."""
+        out = np.zeros((15,) + self.n[::-1], dtype=np.float64)
+        if lib().orc_get_density(self.h, _ptr(out, C.c_double)) != 0:
+            raise ValueError("no density-matrix gain material")
+        return out
+
     def probe(self, pid):
         out = np.zeros(max(self.max_steps, 1), dtype=np.float64)
         n = lib().orc_get_probe(self.h, int(pid), _ptr(out, C.c_double))
@@ -308,3 +321,33 @@ class OracleSim:
         out = np.zeros(self.max_steps + 1, dtype=np.float64)
         n = lib().orc_get_energy(self.h, _ptr(out, C.c_double))
         return out[:max(n, 0)]
+
+
+# ------------------------------------------------------------ matter alone
+
+def bloch_evolve(material, dt, dx, a_meters, emid, rho0, history=False):
+    """Density matrix of one gain-2 cell driven by the midpoint fields emid
+    (n x 3), from the 4x4 complex rho0.  Returns the final rho, and the n x 4 x 4
+    history when asked."""
+    m = make_material(material)
+    e = np.ascontiguousarray(emid, dtype=np.float64).reshape(-1, 3)
+    n = e.shape[0]
+    r = np.ascontiguousarray(np.asarray(rho0, dtype=np.complex128).reshape(4, 4)).view(np.float64).copy()
+    hist = np.zeros((max(n, 1), 32), dtype=np.float64) if history else None
+    rc = lib().orc_bloch_evolve(C.byref(m), float(dt), float(dx), float(a_meters), n, _ptr(e, C.c_double),
+                                _ptr(r, C.c_double), _ptr(hist, C.c_double) if history else None)
+    if rc != 0:
+        raise ValueError("invalid density-matrix material")
+    out = r.view(np.complex128).reshape(4, 4)
+    if history:
+        return out, hist[:n].view(np.complex128).reshape(n, 4, 4)
+    return out
+
+
+def bloch_constants(material, dt, dx, a_meters):
+    """(w0, prewarped w', kappa, 1/T1, 1/T2, pump) in normalised units."""
+    m = make_material(material)
+    out = np.zeros(6, dtype=np.float64)
+    if lib().orc_bloch_constants(C.byref(m), float(dt), float(dx), float(a_meters), _ptr(out, C.c_double)) != 0:
+        raise ValueError("invalid density-matrix material")
+    return tuple(out)
