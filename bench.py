@@ -243,10 +243,10 @@ def measure_batched(args, steps=300):
             "note": "10k-step runs extrapolated from %d timed steps per realization" % steps}
 
 
-def measure_lasing(args, steps=1000):
+def measure_lasing(args, steps=1000, model="lorentz"):
     from paper_0802_3775_amd import fdtd, tune
     from paper_0802_3775_amd import workloads as W
-    cfg = W.lasing(pump=1e10, steps=steps + 300)
+    cfg = W.lasing(pump=1e10, steps=steps + 300, model=model)
     tuning = tune.autotune(dict(cfg), budget_s=args.tune_seconds, quick=True)
     plan = fdtd.Plan(cfg, max_steps=steps + 300, tuning=tuning)
     plan.step(100)
@@ -254,8 +254,10 @@ def measure_lasing(args, steps=1000):
     kern = kernel_table(plan, 50)
     n = plan.ncell
     plan.close()
+    medium = ("Lorentz + four-level rate equations" if model == "lorentz" else
+              "density-matrix dye (ground + 3 upper levels, T1 1 ns, T2 10 fs, N 5e25 m^-3, inverted start)")
     return {"workload": "lasing box 6x6x6 cells at 24 cells/a + 12-cell CPML on all faces (168^3), "
-            "gain voids, pump 1e10 s^-1, noise", "cells": n, "steps_timed": steps,
+            "gain voids: %s, pump 1e10 s^-1, noise" % medium, "cells": n, "steps_timed": steps,
             "cell_updates_per_s": n * steps / wall, "tuning": tuning, "kernels": kern}
 
 
@@ -355,6 +357,8 @@ def main():
         out["paper_beam_200"] = measure_beam(args)
         log("lasing ...")
         out["lasing"] = measure_lasing(args)
+        log("lasing, density matrix ...")
+        out["lasing_density"] = measure_lasing(args, model="density")
         log("batched ...")
         out["batched"] = measure_batched(args)
         log("serving ...")

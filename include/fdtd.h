@@ -10,8 +10,9 @@
  *     source: same section and the lasing section ("3+1D simulation of lasing").
  *   - Transmitted power T(t), the transversely integrated Poynting vector at the
  *     output face: section "Dynamical diffusion and localization".
- * The gain medium is a Lorentz polarization driven by four-level rate equations
- * (not the paper's su(4) density-matrix form).
+ * Gain media: a Lorentz polarization driven by four-level rate equations, or
+ * the paper's density-matrix (su(4)) model of a ground level coupled to three
+ * degenerate upper levels (fdtd_material, gain = 2).
  *
  * Units: c = eps0 = mu0 = 1; lengths in a (cubic lattice constant), time in
  * a/c, frequency in c/a.  dx = 1/res, dt = courant * dx.  SI enters only through
@@ -87,12 +88,26 @@ typedef struct {
 /* Material.  eps: relative permittivity (host permittivity of a gain medium).
    gain = 1: four-level medium with total density n_total (m^-3), lifetimes
    tau32, tau21, tau10 (s), pump rate 0->3 (s^-1), Lorentz transition f_a and
-   FWHM linewidth df_a (c/a), noise amplitude, initial fractions n_init[0..3]. */
+   FWHM linewidth df_a (c/a), noise amplitude, initial fractions n_init[0..3].
+   gain = 2: the paper's density-matrix medium (section "Sample and numerical
+   approach": a ground level 0 and three degenerate upper levels 1..3 coupled to
+   Ex, Ey, Ez): density n_total, transition f_a (c/a), population decay time t1
+   and dephasing time t2 (s), pump rate (s^-1, 0 -> each upper level at pump/3),
+   transition dipole (C m; <= 0 selects the radiative value for which t1 is the
+   spontaneous lifetime in a host of index sqrt(eps)), noise amplitude (a
+   current sigma_N sqrt(rho_cc) g / sqrt(dt dx^3) on E_c), initial populations
+   n_init (no coherences).  Field unit hbar c / (dipole a); P_c = 2 kappa
+   Re rho_0c with kappa = n_total dipole^2 a / (eps0 hbar c).  Density-matrix
+   state per gain cell: 15 reals (three populations, the three ground-upper and
+   three upper-upper complex coherences), the trace fixed at 1.  The gain
+   materials of one plan, and of the gain members of one batch, must share one
+   model (FDTD_EUNSUPPORTED otherwise). */
 typedef struct {
   double eps;
   int32_t gain;
   double n_total, tau32, tau21, tau10, pump, f_a, df_a, noise;
   double n_init[4];
+  double t1, t2, dipole;
 } fdtd_material;
 
 /* Source: s(t) = amp sin(2 pi f0 (t - t0)) exp(-(t - t0)^2 / (2 sigma_t^2)),
@@ -205,6 +220,11 @@ int fdtd_read_flux(fdtd_plan* p, int32_t id, double* T, double* spec, int64_t* n
 int fdtd_read_populations(fdtd_plan* p, float* host, void* stream);
 /* Polarization P^n, 3 * cells floats. */
 int fdtd_read_polarization(fdtd_plan* p, float* host, void* stream);
+/* Density matrix of a gain = 2 plan, 15 * cells floats: rho_11, rho_22, rho_33,
+   Re rho_01, Re rho_02, Re rho_03, Im rho_01, Im rho_02, Im rho_03, Re rho_12,
+   Re rho_13, Re rho_23, Im rho_12, Im rho_13, Im rho_23 (zero outside gain
+   cells).  FDTD_ESTATE for plans without such a medium. */
+int fdtd_read_density(fdtd_plan* p, float* host, void* stream);
 /* Energy samples W^0, W^ke, ... (n returned). */
 int fdtd_read_energy(fdtd_plan* p, double* host, int64_t* n, void* stream);
 
@@ -229,7 +249,8 @@ int fdtd_class_cells(const fdtd_plan* p, int64_t* cells /* 7 */);
 /* Algorithmic bytes one launch of each class moves (7 entries): 49 per cell
    (E, H and the material index in, E and H out) + 32 per cell and CPML axis
    whose slab holds it (2 E-side psi read+write, 2 H-side psi read + write) + 84
-   per gain cell (P^n, P^{n-1}, populations in; P^{n+1}, populations out); the
+   per Lorentz gain cell (P^n, P^{n-1}, populations in; P^{n+1}, populations
+   out) or 144 per density-matrix gain cell (18 floats in and out); the
    DFT entry is the average bytes of one call: the plane sample (24 bytes read,
    16 written per point) and, once per 32 samples, the 4 complex FP64
    accumulators read + written per plane point and frequency plus the sample

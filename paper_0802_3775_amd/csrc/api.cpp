@@ -26,6 +26,8 @@ namespace {
 
 constexpr double kPi = 3.141592653589793238462643383279502884;
 constexpr double kC = 299792458.0;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kHbar = 1.054571817e-34;
 
 thread_local std::string g_err;
 
@@ -160,6 +162,7 @@ struct fdtd_plan {
   int maxnf = 0;
   int src_len[FD_MAXSRC] = {0, 0, 0, 0};
   bool has_gain = false;
+  int gm = 0;  // gain model of the plan's gain materials: 0 none, 1 Lorentz, 2 density matrix
   hipStream_t cap = nullptr;
   std::unique_ptr<Fork> fork;
   std::map<int64_t, GraphEntry> graphs;
@@ -176,6 +179,7 @@ struct fdtd_batch {
   fd_xcd part[FD_NCLASS] = {};
   int pgrid[FD_NCLASS] = {};
   int ntst = 0;
+  int gm = 1;  // gain model shared by the members with gain
   std::vector<fd_dft_tile> dft;
   int maxnf = 0;
   void* dmem = nullptr;  // tile tables + desc pointer list (setup-time allocation)
@@ -191,6 +195,42 @@ namespace {
 
 // ------------------------------------------------------------ coefficients
 
+// Density-matrix gain (ground level 0, upper levels 1..3 coupled to Ex, Ey, Ez),
+// normalised with hbar = 1 and the field unit hbar c / (mu a):
+//   H = w0 sum_k |k><k| - sum_k E_k (|0><k| + |k><0|),  P_k = 2 kappa Re rho_0k,
+//   kappa = N mu^2 a / (eps0 hbar c); T1 decay of each upper level to 0, T2
+//   dephasing of every coherence, pump 0 -> each upper level at pump / 3.
+// A step is R(dt/2) C(E) R(dt/2): R the exact relaxation flow, C the Cayley
+// map rho -> V rho V^+, V = (I + i dt/2 H')^{-1} (I - i dt/2 H') with the
+// prewarped w' = (2/dt) tan(w0 dt/2) (free precession exactly exp(i w0 dt)).
+int build_density_material(const fdtd_plan* p, const fdtd_material& m, fd_mat& out) {
+  const double dt = p->dt, a = p->g.a_meters, tu = a / kC;
+  const double w0 = 2.0 * kPi * m.f_a;
+  if (!(w0 * dt < kPi)) return fail(FDTD_EUNSTABLE, "transition too fast for dt (w0 dt = %g)", w0 * dt);
+  double mu = m.dipole;
+  if (!(mu > 0.0)) {  // radiative value: T1 is the spontaneous lifetime in a host of index sqrt(eps)
+    const double ws = w0 * kC / a;
+    mu = std::sqrt(3.0 * kPi * kEps0 * kHbar * kC * kC * kC / (ws * ws * ws * std::sqrt(m.eps) * m.t1));
+  }
+  const double kappa = m.n_total * mu * mu * a / (kEps0 * kHbar * kC);
+  const double th = std::tan(0.5 * w0 * dt);  // w' dt / 2
+  const double g1 = tu / m.t1, g2 = tu / m.t2, gp = m.pump * tu;
+  const double den = 1.0 + th * th;
+  out.bk2 = (float)(2.0 * kappa);
+  out.btau = (float)(0.5 * dt);
+  out.bwt = (float)th;
+  out.bc1r = (float)(1.0 / den);
+  out.bc1i = (float)(-th / den);
+  out.brr = (float)((1.0 - th * th) / den);
+  out.bri = (float)(-2.0 * th / den);
+  out.bf2 = (float)std::exp(-0.5 * g2 * dt);
+  out.beinf = (float)(gp + g1 > 0.0 ? gp / (gp + g1) : 0.0);
+  out.bg1m = (float)(-std::expm1(-0.5 * (gp + g1) * dt));
+  out.bh1m = (float)(-std::expm1(-0.5 * g1 * dt));
+  out.noise = (float)(m.noise * p->dx / std::sqrt(dt * p->dx * p->dx * p->dx));
+  return FDTD_OK;
+}
+
 int build_material(const fdtd_plan* p, const fdtd_material& m, fd_mat& out) {
   std::memset(&out, 0, sizeof out);
   const double dt = p->dt, dx = p->dx;
@@ -200,6 +240,7 @@ int build_material(const fdtd_plan* p, const fdtd_material& m, fd_mat& out) {
   out.inv_dt = (float)(1.0 / dt);
   if (!m.gain) return FDTD_OK;
   out.is_gain = 1;
+  if (m.gain == 2) return build_density_material(p, m, out);
   // Lorentz ADE by central differences:
   // (P+ - 2P + P-)/dt^2 + dw (P+ - P-)/(2dt) + w^2 P = kappa' dn E + F
   const double w = 2.0 * kPi * m.f_a, dw = 2.0 * kPi * m.df_a;
@@ -305,6 +346,17 @@ size_t psi_elems(const fdtd_plan* p, int w) {
   return nz * t * nx;
 }
 
+int gain_model_of(const std::vector<fdtd_material>& mats) {
+  for (const fdtd_material& m : mats)
+    if (m.gain) return m.gain;
+  return 0;
+}
+
+// Algorithmic bytes of one gain cell per step beyond the linear 49: Lorentz
+// P^n, P^{n-1}, populations in and P^{n+1}, populations out (84); density
+// matrix 18 floats in and out (144).
+double gain_cell_bytes(int gm) { return gm == 2 ? 144.0 : 84.0; }
+
 // Bytes a step streams through: both field buffers, the material map, the psi
 // slabs and the gain arrays.  Above four times the Infinity Cache (256 MB on
 // MI355X) the field stores go out non-temporal; between one and four times it
@@ -314,7 +366,7 @@ constexpr size_t kNonTemporalBytes = 4 * kInfinityCacheBytes;
 size_t step_state_bytes(const fdtd_plan* p) {
   size_t b = (size_t)p->ncell * 49;
   for (int w = 0; w < 3; ++w) b += 6 * 4 * psi_elems(p, w);
-  if (p->has_gain) b += (size_t)p->ncell * 48;
+  if (p->has_gain) b += (size_t)p->ncell * (p->gm == 2 ? 144 : 48);
   return b;
 }
 
@@ -356,7 +408,7 @@ int compute_layout(fdtd_plan* p, int64_t max_steps, Layout& L) {
     return at;
   };
   const size_t nc = (size_t)p->ncell;
-  const bool gain = std::any_of(p->mats.begin(), p->mats.end(), [](const fdtd_material& m) { return m.gain != 0; });
+  const int gm = gain_model_of(p->mats);
   L.desc = take(sizeof(fd_desc));
   L.mats = take(sizeof(fd_mat) * FD_MAXMAT);
   L.ninit = take(sizeof(float) * 4 * FD_MAXMAT);
@@ -366,8 +418,8 @@ int compute_layout(fdtd_plan* p, int64_t max_steps, Layout& L) {
     for (int c = 0; c < 3; ++c) L.H[b][c] = take(nc * 4);
   L.map = take(nc);
   for (int b = 0; b < 2; ++b)
-    for (int c = 0; c < 3; ++c) L.P[b][c] = gain ? take(nc * 4) : 0;
-  L.pop = gain ? take(nc * 4 * 6) : 0;
+    for (int c = 0; c < 3; ++c) L.P[b][c] = gm == 1 ? take(nc * 4) : 0;
+  L.pop = gm ? take(nc * 4 * (gm == 2 ? 18 : 6)) : 0;
   for (int w = 0; w < 3; ++w) {
     const bool on = pml_t(p, w) > 0;
     L.prof[w] = on ? take(sizeof(float) * 6 * axis_n(p, w)) : 0;
@@ -433,12 +485,11 @@ T* at(fdtd_plan* p, size_t off) {
   return reinterpret_cast<T*>(p->arena + off);
 }
 
-// Enqueue one step (batch-relative index s) of the given tile sets.
 // Enqueue one step (batch-relative index s) of the given tile sets.  With a
 // Fork (graph capture) the non-empty classes become parallel graph branches.
 int enqueue_step(fd_tile* const dtiles[FD_NCLASS], const std::vector<fd_tile>* tiles, const fd_xcd* part,
                  const int* pgrid, int tile_x, int block, int max_blocks, const fd_dft_tile* ddft, int ndft,
-                 int maxnf, bool dft_due, int s, int ntst, hipStream_t st, Fork* fk) {
+                 int maxnf, bool dft_due, int s, int ntst, int gm, hipStream_t st, Fork* fk) {
   int used[FD_NCLASS], nused = 0;
   for (int c = 0; c < FD_NCLASS; ++c)
     if (!tiles[c].empty()) used[nused++] = c;
@@ -454,7 +505,7 @@ int enqueue_step(fd_tile* const dtiles[FD_NCLASS], const std::vector<fd_tile>* t
       on = fk->side[c];
       HIPCHK(hipStreamWaitEvent(on, fk->fork, 0));
     }
-    HIPCHK(fd_launch_step(c, dtiles[c], nt, tile_x, block, grid, s, pc, ntst, on));
+    HIPCHK(fd_launch_step(c, dtiles[c], nt, tile_x, block, grid, s, pc, ntst, gm, on));
     if (par && u > 0) HIPCHK(hipEventRecord(fk->join[c], on));
   }
   if (par)
@@ -481,7 +532,7 @@ int plan_enqueue(fdtd_plan* p, int64_t n, hipStream_t st, Fork* fk) {
   for (int64_t s = 0; s < n; ++s) {
     const int r = enqueue_step(p->dtiles, p->tiles, p->part, p->pgrid, p->tune.tile_x, p->tune.block,
                                p->tune.max_blocks, p->ddft, (int)p->dft.size(), p->maxnf,
-                               plan_dft_due(p, p->step + s), (int)s, p->ntst, st, fk);
+                               plan_dft_due(p, p->step + s), (int)s, p->ntst, p->gm ? p->gm : 1, st, fk);
     if (r) return r;
   }
   HIPCHK(fd_launch_advance_one(p->ddesc, n, st));
@@ -548,11 +599,20 @@ int fdtd_set_materials(fdtd_plan* p, const fdtd_material* tab, int32_t n) {
   for (int q = 0; q < n; ++q) {
     const fdtd_material& m = tab[q];
     if (!(m.eps > 0.0)) return fail(FDTD_EINVAL, "material %d: eps must be > 0", q);
-    if (m.gain) {
+    if (m.gain < 0 || m.gain > 2) return fail(FDTD_EINVAL, "material %d: gain must be 0, 1 or 2", q);
+    if (m.gain == 1) {
       if (!(m.n_total >= 0.0) || !(m.tau32 > 0.0) || !(m.tau21 > 0.0) || !(m.tau10 > 0.0) || !(m.pump >= 0.0) ||
           !(m.f_a > 0.0) || !(m.df_a >= 0.0))
         return fail(FDTD_EINVAL, "material %d: bad gain parameters", q);
+    } else if (m.gain == 2) {
+      if (!(m.n_total >= 0.0) || !(m.t1 > 0.0) || !(m.t2 > 0.0) || !(m.pump >= 0.0) || !(m.f_a > 0.0))
+        return fail(FDTD_EINVAL, "material %d: bad density-matrix parameters", q);
+    }
+    if (m.gain) {
       if (!(p->g.a_meters > 0.0)) return fail(FDTD_EINVAL, "gain needs a_meters > 0");
+      for (int r = 0; r < q; ++r)
+        if (tab[r].gain && tab[r].gain != m.gain)
+          return fail(FDTD_EUNSUPPORTED, "materials %d and %d use different gain models", r, q);
     }
   }
   p->mats.assign(tab, tab + n);
@@ -736,6 +796,7 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
   std::vector<fd_mat> mt(FD_MAXMAT);
   std::vector<float> ninit(4 * FD_MAXMAT, 0.0f);
   p->has_gain = false;
+  p->gm = gain_model_of(p->mats);
   for (size_t q = 0; q < p->mats.size(); ++q) {
     r = build_material(p, p->mats[q], mt[q]);
     if (r) return r;
@@ -757,6 +818,7 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
   d.ch = (float)(p->dt / p->dx);
   d.nmat = (int)p->mats.size();
   d.has_gain = p->has_gain ? 1 : 0;
+  d.gain_model = p->gm;
   d.gainmask = 0u;
   for (size_t m = 0; m < p->mats.size(); ++m)
     if (p->mats[m].gain) d.gainmask |= 1u << m;
@@ -769,7 +831,7 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
     for (int c = 0; c < 3; ++c) {
       d.E[b][c] = at<float>(p, L.E[b][c]);
       d.H[b][c] = at<float>(p, L.H[b][c]);
-      d.P[b][c] = p->has_gain ? at<float>(p, L.P[b][c]) : nullptr;
+      d.P[b][c] = p->gm == 1 ? at<float>(p, L.P[b][c]) : nullptr;
     }
   d.pop = p->has_gain ? at<float>(p, L.pop) : nullptr;
   d.key0 = p->g.seed;
@@ -1001,7 +1063,7 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
                                   (double)nxt_ * slab_count(1, t.j0, jend) * nzt_ +
                                   (double)nxt_ * nyt_ * slab_count(2, t.k0, t.k1);
         // algorithmic bytes of the tile, plus the plane below it that it also stages
-        tcost.push_back(49.0 * nxt_ * nyt_ * (nzt_ + 1) + 32.0 * slab_cells + 84.0 * (double)ngain);
+        tcost.push_back(49.0 * nxt_ * nyt_ * (nzt_ + 1) + 32.0 * slab_cells + gain_cell_bytes(p->gm) * (double)ngain);
         tcls.push_back({pml, gain ? 1 : 0});
         all.push_back(t);
       }
@@ -1228,11 +1290,42 @@ int fdtd_read_polarization(fdtd_plan* p, float* host, void* stream) {
   if (!p->bound) return fail(FDTD_ESTATE, "plan not bound");
   if (!p->has_gain) return fail(FDTD_ESTATE, "no gain material");
   hipStream_t st = (hipStream_t)stream;
+  const size_t nc = (size_t)p->ncell;
+  if (p->gm == 2) {  // P_c = 2 kappa Re rho_0c of each gain cell's material
+    std::vector<float> re(3 * nc);
+    HIPCHK(hipMemcpyAsync(re.data(), p->arena + p->L.pop + sizeof(float) * 6 * nc, sizeof(float) * re.size(),
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<float> k2(p->mats.size(), 0.0f);
+    for (size_t m = 0; m < p->mats.size(); ++m) {
+      fd_mat mt;
+      if (p->mats[m].gain && build_material(p, p->mats[m], mt) == FDTD_OK) k2[m] = mt.bk2;
+    }
+    for (int c = 0; c < 3; ++c)
+      for (size_t o = 0; o < nc; ++o) host[c * nc + o] = k2[p->host_map[o]] * re[c * nc + o];
+    return FDTD_OK;
+  }
   const int par = (int)(p->step & 1);
   for (int c = 0; c < 3; ++c)
-    HIPCHK(hipMemcpyAsync(host + (size_t)c * p->ncell, p->arena + p->L.P[par][c], sizeof(float) * (size_t)p->ncell,
+    HIPCHK(hipMemcpyAsync(host + (size_t)c * nc, p->arena + p->L.P[par][c], sizeof(float) * nc,
                           hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  return FDTD_OK;
+}
+
+int fdtd_read_density(fdtd_plan* p, float* host, void* stream) {
+  if (!p || !host) return fail(FDTD_EINVAL, "null argument");
+  if (!p->bound) return fail(FDTD_ESTATE, "plan not bound");
+  if (p->gm != 2) return fail(FDTD_ESTATE, "no density-matrix gain material");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nc = (size_t)p->ncell;
+  std::vector<float> pop(6 * nc);
+  HIPCHK(hipMemcpyAsync(pop.data(), p->arena + p->L.pop, sizeof(float) * pop.size(), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(host + 3 * nc, p->arena + p->L.pop + sizeof(float) * 6 * nc, sizeof(float) * 12 * nc,
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int l = 0; l < 3; ++l)
+    for (size_t o = 0; o < nc; ++o) host[l * nc + o] = (float)((double)pop[l * nc + o] + (double)pop[(3 + l) * nc + o]);
   return FDTD_OK;
 }
 
@@ -1317,7 +1410,7 @@ int fdtd_class_bytes(const fdtd_plan* p, double* bytes) {
             double b = 49.0;
             b += 32.0 * ((in_slab(0, i) ? 1 : 0) + (in_slab(1, j) ? 1 : 0) + (in_slab(2, k) ? 1 : 0));
             const uint8_t m = p->host_map[((size_t)k * ny + j) * nx + i];
-            if (p->mats[m].gain) b += 84.0;
+            if (p->mats[m].gain) b += gain_cell_bytes(p->gm);
             acc += b;
           }
     bytes[c] = acc;
@@ -1364,7 +1457,8 @@ int fdtd_time_kernels(fdtd_plan* p, int64_t n, void* stream, double* ms, int64_t
       const int grid = p->tune.max_blocks > 0 ? std::min(nt, p->tune.max_blocks) : p->pgrid[c];
       const fd_xcd* pc = p->tune.max_blocks > 0 ? nullptr : &p->part[c];
       const int r = record(c, [&](hipEvent_t a, hipEvent_t b) {
-        return fd_launch_step(c, p->dtiles[c], nt, p->tune.tile_x, p->tune.block, grid, (int)s, pc, p->ntst, st, a, b);
+        return fd_launch_step(c, p->dtiles[c], nt, p->tune.tile_x, p->tune.block, grid, (int)s, pc, p->ntst,
+                              p->gm ? p->gm : 1, st, a, b);
       });
       if (r) { cleanup(); return r; }
     }
@@ -1410,10 +1504,17 @@ int fdtd_batch_create(fdtd_plan* const* plans, int32_t n, fdtd_batch** out) {
     for (int r = 0; r < q; ++r)
       if (plans[r] == plans[q]) return fail(FDTD_EINVAL, "plan listed twice");
   }
+  int gm = 0;
+  for (int q = 0; q < n; ++q) {
+    if (plans[q]->gm && gm && plans[q]->gm != gm)
+      return fail(FDTD_EUNSUPPORTED, "batch members with gain must share the gain model");
+    if (plans[q]->gm) gm = plans[q]->gm;
+  }
   fdtd_batch* b = new (std::nothrow) fdtd_batch();
   if (!b) return fail(FDTD_ENOMEM, "host allocation");
   b->plans.assign(plans, plans + n);
   b->block = block;
+  b->gm = gm ? gm : 1;
   b->tile_x = plans[0]->tune.tile_x;
   b->parallel = plans[0]->tune.parallel;
   b->max_blocks = plans[0]->tune.max_blocks;
@@ -1490,7 +1591,7 @@ static bool batch_dft_due(const fdtd_batch* b, int64_t s) {
 static int batch_enqueue(fdtd_batch* b, int64_t n, hipStream_t st, Fork* fk) {
   for (int64_t s = 0; s < n; ++s) {
     const int r = enqueue_step(b->dtiles, b->tiles, b->part, b->pgrid, b->tile_x, b->block, b->max_blocks, b->ddft,
-                               (int)b->dft.size(), b->maxnf, batch_dft_due(b, s), (int)s, b->ntst, st, fk);
+                               (int)b->dft.size(), b->maxnf, batch_dft_due(b, s), (int)s, b->ntst, b->gm, st, fk);
     if (r) return r;
   }
   HIPCHK(fd_launch_advance(b->ddescs, (int)b->plans.size(), n, st));

@@ -27,6 +27,17 @@ struct fd_mat {
   float MI[3][4];  // rows 1..3 of (M - I), M the Crank-Nicolson propagator
   float Bu[3];     // rows 1..3 of (B e2 - B e1): response to the stimulated transfer u
   float pad[3];
+  // density-matrix gain (ground level + three degenerate upper levels)
+  float bk2;       // 2 kappa: P_c = 2 kappa Re rho_0c
+  float btau;      // dt / 2
+  float bwt;       // w' dt / 2 = tan(w0 dt / 2), w' the prewarped transition frequency
+  float bc1r, bc1i;  // 1 / (1 + i w' dt/2)
+  float brr, bri;  // (1 - i w' dt/2) / (1 + i w' dt/2)
+  float bf2;       // exp(-dt / (2 T2)): coherence decay per half step
+  float beinf;     // pumped equilibrium of the upper-level total
+  float bg1m;      // 1 - exp(-(pump + 1/T1) dt/2)
+  float bh1m;      // 1 - exp(-dt / (2 T1))
+  float bpad;
 };
 
 // One realization on the device (lives in its plan's arena).
@@ -37,6 +48,7 @@ struct fd_desc {
   float ch;                    // dt / dx
   int nmat;
   int has_gain;
+  int gain_model;     // 1: Lorentz + rate equations, 2: density matrix (one model per plan)
   unsigned gainmask;  // bit m: material m is a gain medium
   int block;                   // threads per workgroup used for this plan's tiles
   long long step;              // absolute step at batch step 0 (advanced on the device)
@@ -46,7 +58,10 @@ struct fd_desc {
   float* E[2][3];              // ping-pong by step parity
   float* H[2][3];
   float* P[2][3];              // polarization ping-pong (P^n in [n&1], P^{n-1} in the other)
-  float* pop;                  // 6 planes of ncell floats: n1,n2,n3 high parts, then low parts
+  // Lorentz model: 6 planes of ncell floats, n1,n2,n3 high parts, then low parts.
+  // Density matrix: 18 planes, rho_11, rho_22, rho_33 high parts, low parts, then
+  // Re rho_01..03, Im rho_01..03, Re rho_12, rho_13, rho_23, Im rho_12, rho_13, rho_23.
+  float* pop;
   uint32_t key0, key1;
   // CPML
   int pml_lo[3], pml_hi[3], pml_t[3];
@@ -121,8 +136,9 @@ struct fd_xcd {
 // part == nullptr: grid-stride loop over the tiles with the plain XCD renumbering
 // start / stop (optional): events that take the kernel's own begin and end timestamps
 // nt: non-temporal field stores (the launch's working set exceeds the Infinity Cache)
+// gm: gain model of the gain classes (1 Lorentz, 2 density matrix)
 hipError_t fd_launch_step(int cls, const fd_tile* tiles, int ntiles, int tile_x, int block, int grid,
-                          int s, const fd_xcd* part, int nt, hipStream_t st, hipEvent_t start = nullptr,
+                          int s, const fd_xcd* part, int nt, int gm, hipStream_t st, hipEvent_t start = nullptr,
                           hipEvent_t stop = nullptr);
 hipError_t fd_launch_dft(const fd_dft_tile* tiles, int ntiles, int s, hipStream_t st, hipEvent_t start = nullptr,
                          hipEvent_t stop = nullptr);

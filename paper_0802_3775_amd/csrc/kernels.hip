@@ -279,6 +279,95 @@ __device__ __forceinline__ void two_sum(float& hi, float& lo, float inc) {
   hi = h2;
 }
 
+// ------------------------------------------------- density-matrix gain cells
+// State of one cell in registers: upper-level populations rho_kk as (hi, lo)
+// pairs, the ground-upper coherences rho_0k = cr + i ci and the upper-upper
+// coherences rho_12, rho_13, rho_23 = xr + i xi.  The trace is fixed at 1, so
+// rho_00 = 1 - sum rho_kk (the real su(4) coordinates of the paper's model,
+// with the diagonal held as level populations).
+struct Cz {
+  float r, i;
+};
+__device__ __forceinline__ Cz zm(Cz a, Cz b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ __forceinline__ Cz zc(Cz a) { return {a.r, -a.i}; }
+__device__ __forceinline__ Cz za(Cz a, Cz b) { return {a.r + b.r, a.i + b.i}; }
+__device__ __forceinline__ Cz zs(Cz a, float s) { return {a.r * s, a.i * s}; }
+
+// Half-step relaxation R(dt/2): exact flow of T1 decay, pump and T2 dephasing.
+// p: populations (updated), inc: their accumulated increments.
+__device__ __forceinline__ void dm_relax(const fd_mat& mt, float p[3], float inc[3], Cz c[3], Cz x[3]) {
+  const float e = (p[0] + p[1]) + p[2];
+  const float de3 = (mt.beinf - e) * mt.bg1m * (1.0f / 3.0f);
+  const float e3 = e * (1.0f / 3.0f);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float d = de3 - (p[k] - e3) * mt.bh1m;
+    inc[k] += d;
+    p[k] += d;
+    c[k] = zs(c[k], mt.bf2);
+    x[k] = zs(x[k], mt.bf2);
+  }
+}
+
+// Cayley step C(E): rho -> V rho V^+, V = (I + i tau H')^{-1}(I - i tau H'),
+// tau = dt/2.  In closed form (D = 1 + tau^2 |E|^2 + i w' tau):
+//   V_00 = (1 + i w' tau - tau^2 |E|^2) / D,  V_0k = V_k0 = 2 i tau E_k / D,
+//   V_kl = r delta_kl + g E_k E_l,  r = (1 - i w' tau)/(1 + i w' tau),
+//   g = -2 tau^2 / (D (1 + i w' tau)).
+// With w_k = rho_k0, y = X^T E (X the upper block), s = E.w, q = E.X.E:
+//   T_k0 = E_k (b p00 + g s) + r w_k,  z_k = E_k (b s* + g q) + r y_k*,
+//   rho'_k0 = a* T_k0 + b* z_k,
+//   rho'_kl = X_kl + r* E_k (b w_l* + g y_l) + E_l (b* T_k0 + g* z_k)
+// (a = V_00, b = V_0k / E_k).  FULL = false stops after rho'_k0 (the predictor).
+template <bool FULL>
+__device__ __forceinline__ void dm_cayley(const fd_mat& mt, const float E[3], float p[3], float inc[3], Cz c[3],
+                                          Cz x[3]) {
+  const float tau = mt.btau;
+  const float t2e = tau * tau * fmaf(E[0], E[0], fmaf(E[1], E[1], E[2] * E[2]));
+  const float dr = 1.0f + t2e, di = mt.bwt;
+  const float inv = 1.0f / fmaf(dr, dr, di * di);
+  const Cz iD = {dr * inv, -di * inv};
+  const Cz al = zm({1.0f - t2e, di}, iD);
+  const Cz be = {-2.0f * tau * iD.i, 2.0f * tau * iD.r};
+  const Cz ga = zs(zm(iD, {mt.bc1r, mt.bc1i}), -2.0f * tau * tau);
+  const Cz rr = {mt.brr, mt.bri};
+  const float p00 = 1.0f - ((p[0] + p[1]) + p[2]);
+  Cz w[3], y[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) w[k] = zc(c[k]);
+  // upper block: X_kk = p_k, X_01 = x0, X_02 = x1, X_12 = x2, X_lk = X_kl*
+  y[0] = za(za({E[0] * p[0], 0.0f}, zs(zc(x[0]), E[1])), zs(zc(x[1]), E[2]));
+  y[1] = za(za(zs(x[0], E[0]), {E[1] * p[1], 0.0f}), zs(zc(x[2]), E[2]));
+  y[2] = za(za(zs(x[1], E[0]), zs(x[2], E[1])), {E[2] * p[2], 0.0f});
+  const Cz sv = za(za(zs(w[0], E[0]), zs(w[1], E[1])), zs(w[2], E[2]));
+  const float qv = fmaf(E[0], y[0].r, fmaf(E[1], y[1].r, E[2] * y[2].r));
+  const Cz u0 = za(zs(be, p00), zm(ga, sv));
+  const Cz u1 = za(zm(be, zc(sv)), zs(ga, qv));
+  Cz T[3], z[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    T[k] = za(zs(u0, E[k]), zm(rr, w[k]));
+    z[k] = za(zs(u1, E[k]), zm(rr, zc(y[k])));
+    c[k] = zc(za(zm(zc(al), T[k]), zm(zc(be), z[k])));  // rho'_0k = (rho'_k0)*
+  }
+  if (!FULL) return;
+  Cz a[3], b[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    a[k] = zm(zc(rr), za(zm(be, zc(w[k])), zm(ga, y[k])));  // r* (b w_k* + g y_k)
+    b[k] = za(zm(zc(be), T[k]), zm(zc(ga), z[k]));
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float d = E[k] * (a[k].r + b[k].r);
+    inc[k] += d;
+    p[k] += d;
+  }
+  x[0] = za(x[0], za(zs(a[1], E[0]), zs(b[0], E[1])));
+  x[1] = za(x[1], za(zs(a[2], E[0]), zs(b[0], E[2])));
+  x[2] = za(x[2], za(zs(a[2], E[1]), zs(b[1], E[2])));
+}
+
 template <int TX>
 struct Lds {
   static constexpr int TYM = FD_MAXBLOCK / TX;
@@ -299,7 +388,7 @@ struct Lds {
 // every z-CPML test (PMM), so interior tiles of a CPML launch run the same
 // code as tiles of a plain launch; the plane below the range still takes the
 // general path.
-template <int TX, int PM, bool GAIN, bool ZT, bool NT>
+template <int TX, int PM, int GAIN, bool ZT, bool NT>
 __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   const cdesc* d = (const cdesc*)tl.d;
   constexpr int W = Lds<TX>::W;
@@ -562,9 +651,10 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         }
       }
     }
-    // gain-cell inputs of plane k (populations, P^n, P^{n-1}), consumed in the E
-    // update; other lanes read element 0
+    // gain-cell inputs of plane k (Lorentz: populations, P^n, P^{n-1}; density
+    // matrix: its 18 floats), consumed in the E update; other lanes read element 0
     float gnh[3], gnl[3], gPn[3], gPm[3];
+    float gq[12];
     bool gk = false;
     if (GAIN) {
       gk = act && ((gmask >> S.m) & 1u);
@@ -574,8 +664,16 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       for (int q = 0; q < 3; ++q) {
         gnh[q] = pop[(size_t)q * ncs + ig];
         gnl[q] = pop[(size_t)(3 + q) * ncs + ig];
-        gPn[q] = G((const float*)d->P[par][q])[ig];
-        gPm[q] = G((const float*)d->P[par ^ 1][q])[ig];
+      }
+      if (GAIN == 1) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          gPn[q] = G((const float*)d->P[par][q])[ig];
+          gPm[q] = G((const float*)d->P[par ^ 1][q])[ig];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 12; ++q) gq[q] = pop[(size_t)(6 + q) * ncs + ig];
       }
     }
     // the loads two planes ahead go out after this plane's psi and gain inputs:
@@ -698,6 +796,19 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
           nh[q] = gnh[q];
           nl[q] = gnl[q];
         }
+      }
+      // density matrix of the cell (populations p, their increments, coherences)
+      float dmp[3] = {0.0f, 0.0f, 0.0f}, dminc[3] = {0.0f, 0.0f, 0.0f};
+      Cz dmc[3], dmx[3];
+      if (GAIN == 2) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          dmp[q] = nh[q] + nl[q];
+          dmc[q] = {gq[q], gq[3 + q]};
+          dmx[q] = {gq[6 + q], gq[9 + q]};
+        }
+      }
+      if (GAIN == 1 && g) {
         const float n1 = nh[0] + nl[0], n2 = nh[1] + nl[1];
         float F[3] = {0.0f, 0.0f, 0.0f};
         if (mt.noise != 0.0f) {
@@ -728,6 +839,16 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         else if (sc == 1) cy += v;
         else cz += v;
       }
+      if (GAIN == 2 && g && mt.noise != 0.0f) {  // spontaneous-emission current on E
+        float gg[3];
+        normals3((uint32_t)n, (uint32_t)o, d->key0, d->key1, gg);
+        cx += mt.noise * sqrtf(fmaxf(dmp[0], 0.0f)) * gg[0];
+        cy += mt.noise * sqrtf(fmaxf(dmp[1], 0.0f)) * gg[1];
+        cz += mt.noise * sqrtf(fmaxf(dmp[2], 0.0f)) * gg[2];
+      }
+      // av: E^{n+1} without the polarization current; on: not a PEC-held component
+      float av[3] = {0.0f, 0.0f, 0.0f};
+      bool on[3] = {false, false, false};
       if (!((!x.py && j == 0) || (!x.pz && k == 0))) {  // Ex: d/dy Hz - d/dz Hy
         float d1 = hz - hz_jm, d2 = hy - hym;
         if (AX) {
@@ -737,7 +858,8 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
           d1 = stretch<false, PMM>(x, 0, 1, j, i, j, k, d1, true);
           d2 = ZP ? stretch_z<false>(x, 0, S.ge, sz, c, d2, true, S.pe[0]) : stretch<false, PMM>(x, 0, 2, k, i, j, k, d2, true);
         }
-        ex_n = fmaf(mt.cb, (d1 - d2) - cx, eo[0]) - dP[0] * mt.inv_eps;
+        av[0] = fmaf(mt.cb, (d1 - d2) - cx, eo[0]);
+        on[0] = true;
       }
       if (!((!x.pz && k == 0) || (!x.px && i == 0))) {  // Ey: d/dz Hx - d/dx Hz
         float d1 = hx - hxm, d2 = hz - hz_im;
@@ -748,7 +870,8 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
           d1 = ZP ? stretch_z<false>(x, 1, S.ge, sz, c, d1, true, S.pe[1]) : stretch<false, PMM>(x, 1, 2, k, i, j, k, d1, true);
           d2 = stretch<false, PMM>(x, 1, 0, i, i, j, k, d2, true);
         }
-        ey_n = fmaf(mt.cb, (d1 - d2) - cy, eo[1]) - dP[1] * mt.inv_eps;
+        av[1] = fmaf(mt.cb, (d1 - d2) - cy, eo[1]);
+        on[1] = true;
       }
       if (!((!x.px && i == 0) || (!x.py && j == 0))) {  // Ez: d/dx Hy - d/dy Hx
         float d1 = hy - hy_im, d2 = hx - hx_jm;
@@ -759,12 +882,54 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
           d1 = stretch<false, PMM>(x, 2, 0, i, i, j, k, d1, true);
           d2 = stretch<false, PMM>(x, 2, 1, j, i, j, k, d2, true);
         }
-        ez_n = fmaf(mt.cb, (d1 - d2) - cz, eo[2]) - dP[2] * mt.inv_eps;
+        av[2] = fmaf(mt.cb, (d1 - d2) - cz, eo[2]);
+        on[2] = true;
       }
+      if (GAIN == 2 && g) {
+        // one predictor-corrector pass of the implicit midpoint coupling:
+        // rho^{n+1} = R C(E_mid) R rho^n with E_mid = (E^n + E^{n+1}) / 2
+        const float Pn[3] = {mt.bk2 * dmc[0].r, mt.bk2 * dmc[1].r, mt.bk2 * dmc[2].r};
+        dm_relax(mt, dmp, dminc, dmc, dmx);
+        float em[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) em[q] = 0.5f * (eo[q] + av[q]);
+        {
+          Cz cp[3] = {dmc[0], dmc[1], dmc[2]};
+          Cz xp[3] = {dmx[0], dmx[1], dmx[2]};
+          float pp[3] = {dmp[0], dmp[1], dmp[2]}, ip[3] = {0.0f, 0.0f, 0.0f};
+          dm_cayley<false>(mt, em, pp, ip, cp, xp);
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            const float es = on[q] ? av[q] - (mt.bk2 * (cp[q].r * mt.bf2) - Pn[q]) * mt.inv_eps : 0.0f;
+            em[q] = 0.5f * (eo[q] + es);
+          }
+        }
+        dm_cayley<true>(mt, em, dmp, dminc, dmc, dmx);
+        dm_relax(mt, dmp, dminc, dmc, dmx);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) dP[q] = mt.bk2 * dmc[q].r - Pn[q];
+      }
+      if (on[0]) ex_n = av[0] - dP[0] * mt.inv_eps;
+      if (on[1]) ey_n = av[1] - dP[1] * mt.inv_eps;
+      if (on[2]) ez_n = av[2] - dP[2] * mt.inv_eps;
       put(x.Eout[0], o, ex_n);
       put(x.Eout[1], o, ey_n);
       put(x.Eout[2], o, ez_n);
-      if (g) {
+      if (GAIN == 2 && g) {
+        const int nc = d->ncell;
+        gf* pop = G(d->pop);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          two_sum(nh[r], nl[r], dminc[r]);
+          pop[(size_t)r * nc + o] = nh[r];
+          pop[(size_t)(3 + r) * nc + o] = nl[r];
+          pop[(size_t)(6 + r) * nc + o] = dmc[r].r;
+          pop[(size_t)(9 + r) * nc + o] = dmc[r].i;
+          pop[(size_t)(12 + r) * nc + o] = dmx[r].r;
+          pop[(size_t)(15 + r) * nc + o] = dmx[r].i;
+        }
+      }
+      if (GAIN == 1 && g) {
         const float en[3] = {ex_n, ey_n, ez_n};
         float u = 0.0f;
 #pragma unroll
@@ -851,7 +1016,7 @@ __device__ __forceinline__ int xcd_tile(int w, int n) {
 // With a cost-balanced partition (use_part), workgroup w takes tile
 // part.start[x] + w/8 of XCD x = w mod 8, or nothing if that part is shorter;
 // otherwise the workgroups loop over the renumbered tile list.
-template <int TX, int PM, bool GAIN, bool NT>
+template <int TX, int PM, int GAIN, bool NT>
 __global__ __launch_bounds__(FD_MAXBLOCK) void step_kernel(const fd_tile* __restrict__ tiles, int ntiles, int s,
                                                            fd_xcd part, int use_part) {
   __shared__ Lds<TX> lds;
@@ -1162,34 +1327,48 @@ __global__ void init_pop_kernel(const uint8_t* __restrict__ map, const float* __
 }  // namespace
 
 // start/stop (optional) take the kernel's own begin and end timestamps
-template <int TX, int PM, bool GAIN>
+template <int TX, int PM, int GAIN>
 static void launch_one(const fd_tile* tiles, int ntiles, int block, int grid, int s, const fd_xcd& part, int use,
                        int nt, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
-  if (nt)
-    hipExtLaunchKernelGGL(step_kernel<TX, PM, GAIN, true>, dim3(grid), dim3(block), 0, st, start, stop, 0, tiles,
-                          ntiles, s, part, use);
-  else
+  if constexpr (GAIN != 2) {  // density-matrix kernels keep ordinary stores
+    if (nt) {
+      hipExtLaunchKernelGGL(step_kernel<TX, PM, GAIN, true>, dim3(grid), dim3(block), 0, st, start, stop, 0, tiles,
+                            ntiles, s, part, use);
+      return;
+    }
+  }
     hipExtLaunchKernelGGL(step_kernel<TX, PM, GAIN, false>, dim3(grid), dim3(block), 0, st, start, stop, 0, tiles,
                           ntiles, s, part, use);
 }
 
 template <int TX>
 static hipError_t launch_tx(int cls, const fd_tile* tiles, int ntiles, int block, int grid, int s,
-                            const fd_xcd& part, int use, int nt, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
+                            const fd_xcd& part, int use, int nt, int gm, hipStream_t st, hipEvent_t start,
+                            hipEvent_t stop) {
+  const bool dm = gm == 2;
   switch (cls) {
-    case FD_CLASS_PLAIN: launch_one<TX, 0, false>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
-    case FD_CLASS_PMLZ: launch_one<TX, 4, false>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
-    case FD_CLASS_PML: launch_one<TX, 7, false>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
-    case FD_CLASS_GAIN: launch_one<TX, 0, true>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
-    case FD_CLASS_PMLZ_GAIN: launch_one<TX, 4, true>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
-    case FD_CLASS_PML_GAIN: launch_one<TX, 7, true>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
+    case FD_CLASS_PLAIN: launch_one<TX, 0, 0>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
+    case FD_CLASS_PMLZ: launch_one<TX, 4, 0>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
+    case FD_CLASS_PML: launch_one<TX, 7, 0>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
+    case FD_CLASS_GAIN:
+      if (dm) launch_one<TX, 0, 2>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop);
+      else launch_one<TX, 0, 1>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop);
+      break;
+    case FD_CLASS_PMLZ_GAIN:
+      if (dm) launch_one<TX, 4, 2>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop);
+      else launch_one<TX, 4, 1>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop);
+      break;
+    case FD_CLASS_PML_GAIN:
+      if (dm) launch_one<TX, 7, 2>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop);
+      else launch_one<TX, 7, 1>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t fd_launch_step(int cls, const fd_tile* tiles, int ntiles, int tile_x, int block, int grid, int s,
-                          const fd_xcd* part, int nt, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
+                          const fd_xcd* part, int nt, int gm, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
   if (ntiles <= 0) return hipSuccess;
   if (block < 64 || block > FD_MAXBLOCK || (block & 63) != 0 || grid <= 0 || block % tile_x != 0 ||
       2 * (tile_x + 2) + 2 * (block / tile_x) > block)
@@ -1209,9 +1388,9 @@ hipError_t fd_launch_step(int cls, const fd_tile* tiles, int ntiles, int tile_x,
     use = 1;
   }
   switch (tile_x) {
-    case 16: return launch_tx<16>(cls, tiles, ntiles, block, grid, s, pz, use, nt, st, start, stop);
-    case 32: return launch_tx<32>(cls, tiles, ntiles, block, grid, s, pz, use, nt, st, start, stop);
-    case 64: return launch_tx<64>(cls, tiles, ntiles, block, grid, s, pz, use, nt, st, start, stop);
+    case 16: return launch_tx<16>(cls, tiles, ntiles, block, grid, s, pz, use, nt, gm, st, start, stop);
+    case 32: return launch_tx<32>(cls, tiles, ntiles, block, grid, s, pz, use, nt, gm, st, start, stop);
+    case 64: return launch_tx<64>(cls, tiles, ntiles, block, grid, s, pz, use, nt, gm, st, start, stop);
     default: return hipErrorInvalidValue;
   }
 }

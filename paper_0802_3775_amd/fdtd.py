@@ -39,7 +39,8 @@ class Material(C.Structure):
     _fields_ = [("eps", C.c_double), ("gain", C.c_int32), ("n_total", C.c_double),
                 ("tau32", C.c_double), ("tau21", C.c_double), ("tau10", C.c_double),
                 ("pump", C.c_double), ("f_a", C.c_double), ("df_a", C.c_double),
-                ("noise", C.c_double), ("n_init", C.c_double * 4)]
+                ("noise", C.c_double), ("n_init", C.c_double * 4),
+                ("t1", C.c_double), ("t2", C.c_double), ("dipole", C.c_double)]
 
 
 class SourceDesc(C.Structure):
@@ -92,6 +93,7 @@ SIGNATURES = {
     "fdtd_read_flux": ([VP, C.c_int32, P(C.c_double), P(C.c_double), P(C.c_int64), VP], C.c_int),
     "fdtd_read_populations": ([VP, P(C.c_float), VP], C.c_int),
     "fdtd_read_polarization": ([VP, P(C.c_float), VP], C.c_int),
+    "fdtd_read_density": ([VP, P(C.c_float), VP], C.c_int),
     "fdtd_read_energy": ([VP, P(C.c_double), P(C.c_int64), VP], C.c_int),
     "fdtd_batch_create": ([P(VP), C.c_int32, P(VP)], C.c_int),
     "fdtd_batch_step": ([VP, C.c_int64, VP], C.c_int),
@@ -160,8 +162,8 @@ def _grid(g):
 def _material(m):
     d = Material()
     d.eps = m["eps"]
-    d.gain = 1 if m.get("gain") else 0
-    for f in ("n_total", "tau32", "tau21", "tau10", "pump", "f_a", "df_a", "noise"):
+    d.gain = int(m.get("gain") or 0)
+    for f in ("n_total", "tau32", "tau21", "tau10", "pump", "f_a", "df_a", "noise", "t1", "t2", "dipole"):
         setattr(d, f, float(m.get(f, 0.0)))
     if d.gain:
         d.n_init[:] = list(m.get("n_init", (1.0, 0.0, 0.0, 0.0)))
@@ -343,6 +345,13 @@ class Plan:
     def populations(self, stream=None):
         out = np.zeros((4,) + self.n[::-1], dtype=np.float32)
         _check(lib().fdtd_read_populations(self.h, _ptr(out, C.c_float), _stream(stream)))
+        return out
+
+    def density(self, stream=None):
+        """Density matrix of the density-matrix gain cells, 15 planes: rho_11..33,
+        Re rho_01..03, Im rho_01..03, Re rho_12, 13, 23, Im rho_12, 13, 23."""
+        out = np.zeros((15,) + self.n[::-1], dtype=np.float32)
+        _check(lib().fdtd_read_density(self.h, _ptr(out, C.c_float), _stream(stream)))
         return out
 
     def polarization(self, stream=None):

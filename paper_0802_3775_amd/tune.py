@@ -27,9 +27,9 @@ def _cache_path():
 
 
 def shape_key(cfg):
-    """Shape bin: grid extents, boundary/CPML layout, gain and flux presence."""
+    """Shape bin: grid extents, boundary/CPML layout, gain model and flux presence."""
     g = cfg["grid"]
-    gain = any(m.get("gain") for m in cfg["materials"])
+    gain = max(int(m.get("gain") or 0) for m in cfg["materials"])  # gain model (0 none)
     nflux = sum(1 for f in cfg.get("flux", []) if len(f.get("freqs", ())) > 0)
     return "v%d|n=%s|per=%s|pml=%s,%s|gain=%d|flux=%d" % (
         CACHE_VERSION, tuple(g["n"]), tuple(g.get("periodic", (1, 1, 1))), tuple(g.get("pml_lo", (0, 0, 0))),

@@ -47,6 +47,16 @@ def gain_material(pump=1e10, noise=1e-6, n_total=1e24, n_init=(1.0, 0.0, 0.0, 0.
             "n_init": tuple(n_init)}
 
 
+def density_material(pump=0.0, noise=1e-6, n_total=5e25, n_init=(0.0, 1 / 3, 1 / 3, 1 / 3), t1=1e-9,
+                     t2=10e-15, f_a=0.7749, dipole=0.0, eps=EPS_DYE):
+    """The paper's density-matrix dye (section "Sample and numerical approach"):
+    484 THz (0.7749 c/a at a = 480 nm), T1 = 1 ns, T2 = 10 fs, n = 1.3 host, and
+    the lasing section's N_a = 5e25 m^-3 of molecules, inverted at the start and
+    spread evenly over the three upper levels (the reading of "inversion N_a")."""
+    return {"eps": eps, "gain": 2, "n_total": n_total, "f_a": f_a, "t1": t1, "t2": t2, "pump": pump,
+            "dipole": dipole, "noise": noise, "n_init": tuple(n_init)}
+
+
 def _grid(n, periodic, res, pml=(0, 0, 0), seed=0, realization=0, courant=0.5):
     lo = tuple(p if not per else 0 for p, per in zip(pml, periodic))
     return {"n": tuple(int(v) for v in n), "periodic": tuple(int(v) for v in periodic),
@@ -188,19 +198,24 @@ def ensemble(count=64, seed0=1000, steps=10000, max_cells=1_400_000, n_range=(4,
 
 
 def lasing(pump=1e10, delta=0.05, seed=7, res=24, cells=(6, 6, 6), steps=100000, noise=1e-6,
-           n_init=(1.0, 0.0, 0.0, 0.0), energy_interval=100, pml=PML, tau21=1e-9):
+           n_init=None, energy_interval=100, pml=PML, tau21=1e-9, model="lorentz", **gain_kw):
     """Maxwell-Bloch lasing box: the crystal flush with a CPML on all six faces, gain
-    medium in the voids, vacuum in the PML, seeded polarization noise, Ez probe at a
-    seeded cell inside the crystal, energy every energy_interval steps."""
+    medium in the voids, vacuum in the PML, seeded noise, Ez probe at a seeded cell
+    inside the crystal, energy every energy_interval steps.  model: "lorentz"
+    (Lorentz polarization + rate equations; n_init defaults to the ground state) or
+    "density" (the density-matrix medium of density_material; n_init defaults to
+    its inverted start)."""
     n = [c * res + 2 * pml for c in cells]
     rng = np.random.default_rng(seed + 104729)
     p = [int(pml + rng.integers(0, c * res)) for c in cells]
+    if model == "density":
+        gm = density_material(pump=pump, noise=noise, **gain_kw, **({"n_init": n_init} if n_init else {}))
+    else:
+        gm = gain_material(pump=pump, noise=noise, n_init=n_init or (1.0, 0.0, 0.0, 0.0), tau21=tau21, **gain_kw)
     return {
-        "name": "lasing_%dx%dx%d_R%d_P%.0e" % (tuple(cells) + (res, pump)),
+        "name": "lasing%s_%dx%dx%d_R%d_P%.0e" % ((("_dm" if model == "density" else ""),) + tuple(cells) + (res, pump)),
         "grid": _grid(n, (0, 0, 0), res, pml=(pml, pml, pml), seed=seed),
-        "materials": [{"eps": EPS_BG},
-                      gain_material(pump=pump, noise=noise, n_init=n_init, tau21=tau21),
-                      {"eps": 1.0}],
+        "materials": [{"eps": EPS_BG}, gm, {"eps": 1.0}],
         "opal": {"cells": tuple(cells), "origin": (pml, pml, pml), "r0": 0.35,
                  "disorder": "gauss" if delta > 0 else "none", "strength": float(delta),
                  "mat_bg": 0, "mat_void": 1, "mat_out": 2},

@@ -104,3 +104,44 @@ def test_sphere_list_matches_oracle_bit_for_bit(maker):
     F.lib().fdtd_plan_destroy(h)
     want = O.opal_spheres(cfg["grid"], cfg["opal"])
     assert np.array_equal(got, want)
+
+
+def test_density_matrix_materials_validated():
+    """gain = 2 materials: parameters checked at fdtd_set_materials, one gain model
+    per plan, transitions too fast for dt rejected, 18 state floats per cell."""
+    g = W.periodic_cell(res=8)["grid"]
+    L = F.lib()
+
+    def set_mats(mats):
+        code, h = _plan(g)
+        assert code == 0
+        arr = (F.Material * len(mats))(*[F._material(m) for m in mats])
+        r = L.fdtd_set_materials(h, arr, len(mats))
+        return r, h
+
+    dm = W.density_material()
+    r, h = set_mats([{"eps": 11.9}, dm])
+    assert r == 0
+    t = F.Tuning(128, 4, 0, 0, 16, 1, 0)
+    assert L.fdtd_set_tuning(h, C.byref(t)) == 0
+    with_dm = C.c_size_t()
+    assert L.fdtd_required_bytes(h, 10, C.byref(with_dm)) == 0
+    L.fdtd_plan_destroy(h)
+    r, h = set_mats([{"eps": 11.9}, W.gain_material()])
+    assert L.fdtd_set_tuning(h, C.byref(t)) == 0
+    with_lorentz = C.c_size_t()
+    assert L.fdtd_required_bytes(h, 10, C.byref(with_lorentz)) == 0
+    L.fdtd_plan_destroy(h)
+    # 18 floats per cell instead of 6 populations and two P buffers (12)
+    ncell = 8 * 8 * 8
+    assert with_dm.value - with_lorentz.value >= 4 * ncell * (18 - 12) - 4096
+    for bad in (dict(dm, t1=0.0), dict(dm, t2=-1.0), dict(dm, f_a=0.0), dict(dm, pump=-1.0)):
+        r, h = set_mats([{"eps": 11.9}, bad])
+        assert r == -1, bad
+        L.fdtd_plan_destroy(h)
+    r, h = set_mats([{"eps": 11.9}, dm, W.gain_material()])
+    assert r == -6 and b"gain models" in L.fdtd_last_error()
+    L.fdtd_plan_destroy(h)
+    r, h = set_mats([{"eps": 11.9}, dict(dm, f_a=20.0)])  # w0 dt >= pi at 8 cells/a
+    assert r == -5
+    L.fdtd_plan_destroy(h)
