@@ -1017,13 +1017,13 @@ __device__ __forceinline__ int xcd_tile(int w, int n) {
 // part.start[x] + w/8 of XCD x = w mod 8, or nothing if that part is shorter;
 // otherwise the workgroups loop over the renumbered tile list.
 template <int TX, int PM, int GAIN, bool NT>
-__global__ __launch_bounds__(FD_MAXBLOCK) void step_kernel(const fd_tile* __restrict__ tiles, int ntiles, int s,
-                                                           fd_xcd part, int use_part) {
-  __shared__ Lds<TX> lds;
+__device__ __forceinline__ void step_body(const fd_tile* __restrict__ tiles, int ntiles, int s, const fd_xcd& part,
+                                          int use_part, Lds<TX>& lds) {
   // z-only CPML launches specialise their interior tiles; the all-axes kernel
-  // keeps one general march (two would not fit its register budget)
+  // and the density-matrix kernels keep one general march (two would not fit
+  // their register budget)
   auto run = [&](const fd_tile& tl) {
-    if (PM == 4 && !(tl.flags & FD_TILE_ZSLAB)) run_tile<TX, PM, GAIN, false, NT>(tl, s, lds);
+    if (PM == 4 && GAIN != 2 && !(tl.flags & FD_TILE_ZSLAB)) run_tile<TX, PM, GAIN, false, NT>(tl, s, lds);
     else run_tile<TX, PM, GAIN, (PM & 4) != 0, NT>(tl, s, lds);
   };
   if (use_part) {
@@ -1038,6 +1038,23 @@ __global__ __launch_bounds__(FD_MAXBLOCK) void step_kernel(const fd_tile* __rest
     const fd_tile tl = tiles[xcd_tile(w, ntiles)];
     run(tl);
   }
+}
+
+template <int TX, int PM, int GAIN, bool NT>
+__global__ __launch_bounds__(FD_MAXBLOCK) void step_kernel(const fd_tile* __restrict__ tiles, int ntiles, int s,
+                                                           fd_xcd part, int use_part) {
+  __shared__ Lds<TX> lds;
+  step_body<TX, PM, GAIN, NT>(tiles, ntiles, s, part, use_part, lds);
+}
+
+// Density-matrix gain: the register budget is capped at three waves per SIMD
+// (168 VGPRs); left alone the compiler takes a few more and drops to two waves,
+// which measured 20% slower on the lasing box.
+template <int TX, int PM>
+__global__ __launch_bounds__(FD_MAXBLOCK) __attribute__((amdgpu_waves_per_eu(3))) void step_kernel_dm(
+    const fd_tile* __restrict__ tiles, int ntiles, int s, fd_xcd part, int use_part) {
+  __shared__ Lds<TX> lds;
+  step_body<TX, PM, 2, false>(tiles, ntiles, s, part, use_part, lds);
 }
 
 // ------------------------------------------------------------- flux DFT
@@ -1330,15 +1347,17 @@ __global__ void init_pop_kernel(const uint8_t* __restrict__ map, const float* __
 template <int TX, int PM, int GAIN>
 static void launch_one(const fd_tile* tiles, int ntiles, int block, int grid, int s, const fd_xcd& part, int use,
                        int nt, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
-  if constexpr (GAIN != 2) {  // density-matrix kernels keep ordinary stores
-    if (nt) {
-      hipExtLaunchKernelGGL(step_kernel<TX, PM, GAIN, true>, dim3(grid), dim3(block), 0, st, start, stop, 0, tiles,
-                            ntiles, s, part, use);
-      return;
-    }
-  }
+  if constexpr (GAIN == 2) {  // density-matrix kernels keep ordinary stores
+    (void)nt;
+    hipExtLaunchKernelGGL(step_kernel_dm<TX, PM>, dim3(grid), dim3(block), 0, st, start, stop, 0, tiles, ntiles, s,
+                          part, use);
+  } else if (nt) {
+    hipExtLaunchKernelGGL(step_kernel<TX, PM, GAIN, true>, dim3(grid), dim3(block), 0, st, start, stop, 0, tiles,
+                          ntiles, s, part, use);
+  } else {
     hipExtLaunchKernelGGL(step_kernel<TX, PM, GAIN, false>, dim3(grid), dim3(block), 0, st, start, stop, 0, tiles,
                           ntiles, s, part, use);
+  }
 }
 
 template <int TX>
