@@ -261,6 +261,24 @@ def measure_lasing(args, steps=1000, model="lorentz"):
             "cell_updates_per_s": n * steps / wall, "tuning": tuning, "kernels": kern}
 
 
+def measure_paper_lasing(args, steps=300):
+    """The paper's lasing run: the 200^3 box with the density-matrix dye in the
+    spheres (gamma 0.1), noise-seeded, autotuned."""
+    from paper_0802_3775_amd import fdtd, tune
+    from paper_0802_3775_amd import workloads as W
+    cfg = W.paper_lasing(0.1, steps=steps + 300)
+    tuning = tune.autotune(dict(cfg), budget_s=args.tune_seconds, quick=True)
+    plan = fdtd.Plan(cfg, max_steps=steps + 300, tuning=tuning)
+    plan.step(100)
+    wall = timed_run(plan, steps)
+    kern = kernel_table(plan, 50)
+    n = plan.ncell
+    plan.close()
+    return {"workload": "paper's lasing box 200^3 at 16 cells/a (8^3 cells of eps-12 inverted opal, gamma 0.1, "
+            "density-matrix dye in the spheres, CPML on all faces, noise-seeded)", "cells": n,
+            "steps_timed": steps, "cell_updates_per_s": n * steps / wall, "tuning": tuning, "kernels": kern}
+
+
 def measure_serving(args, plain_rate):
     """A reduced Poisson trace of mixed requests (70% linear slabs, 30% lasing
     boxes, 27k-512k-cell crystals, 2000 steps each), offered at 0.9 of the
@@ -359,6 +377,8 @@ def main():
         out["lasing"] = measure_lasing(args)
         log("lasing, density matrix ...")
         out["lasing_density"] = measure_lasing(args, model="density")
+        log("paper lasing box ...")
+        out["paper_lasing_200"] = measure_paper_lasing(args)
         log("batched ...")
         out["batched"] = measure_batched(args)
         log("serving ...")

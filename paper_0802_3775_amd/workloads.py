@@ -175,6 +175,27 @@ def paper_beam(gamma=0.0, seed=31, res=16, cells=8, margin=None, pml=PML, steps=
     }
 
 
+def paper_lasing(gamma=0.0, seed=37, res=16, cells=8, pml=PML, steps=59960, realization=0, pump=1e10,
+                 noise=1e-6, energy_interval=100, box_um=6.0, **dye):
+    """The paper's lasing run (lasing section): the box of paper_beam (6 um,
+    200^3 at 16 cells/a, 8 cubic cells of eps-12 inverted opal with uniform-radius
+    disorder gamma, CPML on all faces) with the spheres filled by the
+    density-matrix dye of density_material (N_a = 5e25 m^-3 inverted at the
+    start, pumped), no launched pulse: the emission starts from the noise.  An Ez
+    probe at a seeded cell inside the crystal records the oscillation; the
+    energy every energy_interval steps.  3 ps is 59,960 steps at Courant 0.5."""
+    cfg = paper_beam(gamma, seed=seed, res=res, cells=cells, pml=pml, steps=steps, realization=realization,
+                     box_um=box_um)
+    cfg["name"] = cfg["name"].replace("beam", "lasing")
+    cfg["materials"] = [cfg["materials"][0], density_material(pump=pump, noise=noise, **dye), {"eps": 1.0}]
+    cfg["opal"] = dict(cfg["opal"], mat_out=2)  # margins and CPML stay vacuum, the dye fills the spheres
+    cfg["sources"] = []
+    cfg["probes"] = [(2,) + tuple(cfg["probes"][0][1:])]
+    cfg["flux"] = []
+    cfg["energy_interval"] = energy_interval
+    return cfg
+
+
 def ensemble(count=64, seed0=1000, steps=10000, max_cells=1_400_000, n_range=(4, 6),
              res_range=(16, 24)):
     """Uneven disorder realizations: delta ~ U[0, 0.12] a, n^3 cubic cells with

@@ -154,3 +154,41 @@ def test_density_batch_matches_plain_runs():
     b.close()
     for p in plans:
         p.close()
+
+
+def test_paper_lasing_box_reduced_parity():
+    """The paper's lasing run at reduced size (4^3 cells at 8 cells/a, eps-12 opal
+    with uniform-radius disorder, dye spheres, CPML on all faces, noise-seeded)."""
+    steps = 800
+    cfg = W.paper_lasing(0.1, seed=5, res=8, cells=4, pml=6, box_um=2.4, steps=steps, noise=1e-3,
+                         energy_interval=20)
+    _say("paper lasing reduced", cfg["grid"]["n"])
+    orc, plan, out = _both(cfg, steps, [400, 400], tuning={"block": 256, "tile_x": 32, "zchunk": 4,
+                                                          "graph_steps": 50, "merge": 2})
+    gain = orc.map == 1
+    assert gain.any()
+    for done, ferr, dg, do in out:
+        derr = rel_l2(dg[:, gain], do[:, gain])
+        _say("step", done, "fields", ferr, "density", derr)
+        assert ferr <= 1e-3 and derr <= 1e-3
+    assert rel_l2(plan.probe(0), orc.probe(0)) <= 1e-3
+    assert rel_l2(plan.energy(), orc.energy()) <= 1e-3
+    plan.close()
+
+
+def test_paper_lasing_box_full_size():
+    """The full 200^3 box (8 cells at 16 cells/a, gamma 0.1) in the benchmark's
+    launch shape: the dye map bit-exact and 20 noise-driven steps against the
+    oracle."""
+    steps = 20
+    cfg = W.paper_lasing(0.1, seed=5, steps=steps, noise=1e-3, energy_interval=10)
+    _say("paper lasing 200^3", cfg["grid"]["n"])
+    orc, plan, out = _both(cfg, steps, [steps], tuning={"block": 256, "tile_x": 32, "zchunk": 8,
+                                                       "graph_steps": 0, "merge": 2})
+    assert np.array_equal(plan.material_map(), orc.map)
+    gain = orc.map == 1
+    done, ferr, dg, do = out[-1]
+    derr = rel_l2(dg[:, gain], do[:, gain])
+    _say("step", done, "fields", ferr, "density", derr)
+    assert ferr <= 1e-4 and derr <= 1e-4
+    plan.close()
