@@ -54,7 +54,7 @@ extern "C" {
 #define FDTD_EHIP (-3)         /* a HIP runtime call failed */
 #define FDTD_ESTATE (-4)       /* call not allowed in the plan's current state */
 #define FDTD_EUNSTABLE (-5)    /* courant >= 1/sqrt(3) or an unstable oscillator */
-#define FDTD_EUNSUPPORTED (-6) /* valid request outside what this build implements */
+#define FDTD_EUNSUPPORTED (-6) /* valid request outside what the library implements */
 
 #define FDTD_MAX_MATERIALS 16
 #define FDTD_MAX_SOURCES 4
