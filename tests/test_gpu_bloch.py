@@ -192,3 +192,32 @@ def test_paper_lasing_box_full_size():
     _say("step", done, "fields", ferr, "density", derr)
     assert ferr <= 1e-4 and derr <= 1e-4
     plan.close()
+
+
+def test_density_pec_walls_and_ragged_shape():
+    """Gain cells on PEC walls (tangential E held at zero inside the coupled
+    update), a ragged 19 x 13 x 11 box, x and y PEC, z periodic."""
+    n = (19, 13, 11)
+    dm = W.density_material(noise=1e-3, pump=1e12, t1=50e-15, t2=10e-15, dipole=8e-29,
+                            n_init=(0.2, 0.3, 0.3, 0.2))
+    rng = np.random.default_rng(9)
+    mp = (rng.random(n[::-1]) < 0.6).astype(np.uint8)  # scattered gain cells, walls included
+    cfg = {"name": "dm_pec", "grid": W._grid(n, (0, 0, 1), 12, seed=3), "materials": [{"eps": 4.0}, dm],
+           "map": mp, "sources": [], "probes": [(1, 0, 5, 5), (2, 7, 0, 3), (0, 9, 6, 4)], "flux": [],
+           "energy_interval": 10,
+           "steps": 400}
+    _say("density pec", n)
+    orc, plan, out = _both(cfg, 400, [200, 200], tuning={"block": 64, "tile_x": 16, "zchunk": 3, "graph_steps": 0},
+                           init=[a * 0.3 for a in _smooth_field(n, 4)])
+    gain = orc.map == 1
+    for done, ferr, dg, do in out:
+        derr = rel_l2(dg[:, gain], do[:, gain])
+        _say("step", done, "fields", ferr, "density", derr)
+        assert ferr <= 1e-4 and derr <= 1e-4
+    E = plan.fields()
+    assert np.all(E[1][:, :, 0] == 0) and np.all(E[2][:, :, 0] == 0)  # Ey, Ez on the x = 0 wall
+    assert np.all(E[0][:, 0, :] == 0) and np.all(E[2][:, 0, :] == 0)  # Ex, Ez on the y = 0 wall
+    for p in range(2):  # on the walls: exactly zero on both sides
+        assert not np.any(orc.probe(p)) and not np.any(plan.probe(p))
+    assert rel_l2(plan.probe(2), orc.probe(2)) <= 1e-4
+    plan.close()
