@@ -59,7 +59,7 @@ struct Layout {
   size_t desc, mats, ninit;
   size_t E[2][3], H[2][3];
   size_t map;
-  size_t P[2][3], pop;
+  size_t P[2][3], pop, gidx;
   size_t prof[3], psiE[3][2], psiH[2][3][2];
   size_t src[FD_MAXSRC], srcprof[FD_MAXSRC];
   size_t probe;
@@ -135,6 +135,7 @@ struct fdtd_plan {
   fdtd_opal_desc opal{};
   std::vector<int64_t> spheres;  // rows of 5
   std::vector<uint8_t> host_map; // given map, or read back after bind
+  std::vector<uint32_t> gidx;     // density-matrix gain ordinal of each cell (0 elsewhere)
   bool map_given = false;
   std::vector<fdtd_source_desc> sources;
   std::vector<std::array<int, 4>> probes;
@@ -420,6 +421,7 @@ int compute_layout(fdtd_plan* p, int64_t max_steps, Layout& L) {
   for (int b = 0; b < 2; ++b)
     for (int c = 0; c < 3; ++c) L.P[b][c] = gm == 1 ? take(nc * 4) : 0;
   L.pop = gm ? take(nc * 4 * (gm == 2 ? 18 : 6)) : 0;
+  L.gidx = gm == 2 ? take(nc * 4) : 0;
   for (int w = 0; w < 3; ++w) {
     const bool on = pml_t(p, w) > 0;
     L.prof[w] = on ? take(sizeof(float) * 6 * axis_n(p, w)) : 0;
@@ -834,6 +836,7 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
       d.P[b][c] = p->gm == 1 ? at<float>(p, L.P[b][c]) : nullptr;
     }
   d.pop = p->has_gain ? at<float>(p, L.pop) : nullptr;
+  d.gidx = p->gm == 2 ? at<uint32_t>(p, L.gidx) : nullptr;
   d.key0 = p->g.seed;
   d.key1 = p->g.realization;
   std::vector<float> prof;
@@ -981,7 +984,26 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
     HIPCHK(hipMemcpyAsync(p->arena + L.map, p->host_map.data(), (size_t)p->ncell, hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
   }
-  if (p->has_gain) HIPCHK(fd_launch_init_pop(p->ddesc, at<uint8_t>(p, L.map), at<float>(p, L.ninit), d.pop, d.ncell, st));
+  if (p->gm == 2) {
+    // gain ordinals and the initial populations at them (the rest of the state
+    // starts at zero with the arena)
+    const size_t nc = (size_t)p->ncell;
+    p->gidx.assign(nc, 0u);
+    std::vector<float> init(3 * nc, 0.0f);
+    uint32_t g = 0;
+    for (size_t o = 0; o < nc; ++o) {
+      const fdtd_material& m = p->mats[p->host_map[o]];
+      if (!m.gain) continue;
+      p->gidx[o] = g;
+      for (int l = 0; l < 3; ++l) init[l * nc + g] = (float)m.n_init[1 + l];
+      ++g;
+    }
+    HIPCHK(hipMemcpyAsync(p->arena + L.gidx, p->gidx.data(), sizeof(uint32_t) * nc, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(p->arena + L.pop, init.data(), sizeof(float) * init.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  } else if (p->has_gain) {
+    HIPCHK(fd_launch_init_pop(p->ddesc, at<uint8_t>(p, L.map), at<float>(p, L.ninit), d.pop, d.ncell, st));
+  }
 
   // tiles, classified by CPML and gain presence
   const int plane = d.plane;
@@ -1277,8 +1299,9 @@ int fdtd_read_populations(fdtd_plan* p, float* host, void* stream) {
       for (int l = 0; l < 4; ++l) host[l * nc + o] = 0.0f;
       continue;
     }
+    const size_t q = p->gm == 2 ? (size_t)p->gidx[o] : o;  // state index of the cell
     double lv[3];
-    for (int l = 0; l < 3; ++l) lv[l] = (double)pop[l * nc + o] + (double)pop[(3 + l) * nc + o];
+    for (int l = 0; l < 3; ++l) lv[l] = (double)pop[l * nc + q] + (double)pop[(3 + l) * nc + q];
     host[0 * nc + o] = (float)(1.0 - (lv[0] + lv[1] + lv[2]));
     for (int l = 0; l < 3; ++l) host[(1 + l) * nc + o] = (float)lv[l];
   }
@@ -1302,7 +1325,7 @@ int fdtd_read_polarization(fdtd_plan* p, float* host, void* stream) {
       if (p->mats[m].gain && build_material(p, p->mats[m], mt) == FDTD_OK) k2[m] = mt.bk2;
     }
     for (int c = 0; c < 3; ++c)
-      for (size_t o = 0; o < nc; ++o) host[c * nc + o] = k2[p->host_map[o]] * re[c * nc + o];
+      for (size_t o = 0; o < nc; ++o) host[c * nc + o] = k2[p->host_map[o]] * re[c * nc + p->gidx[o]];
     return FDTD_OK;
   }
   const int par = (int)(p->step & 1);
@@ -1319,13 +1342,16 @@ int fdtd_read_density(fdtd_plan* p, float* host, void* stream) {
   if (p->gm != 2) return fail(FDTD_ESTATE, "no density-matrix gain material");
   hipStream_t st = (hipStream_t)stream;
   const size_t nc = (size_t)p->ncell;
-  std::vector<float> pop(6 * nc);
-  HIPCHK(hipMemcpyAsync(pop.data(), p->arena + p->L.pop, sizeof(float) * pop.size(), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(host + 3 * nc, p->arena + p->L.pop + sizeof(float) * 6 * nc, sizeof(float) * 12 * nc,
-                        hipMemcpyDeviceToHost, st));
+  std::vector<float> st18(18 * nc);
+  HIPCHK(hipMemcpyAsync(st18.data(), p->arena + p->L.pop, sizeof(float) * st18.size(), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  for (int l = 0; l < 3; ++l)
-    for (size_t o = 0; o < nc; ++o) host[l * nc + o] = (float)((double)pop[l * nc + o] + (double)pop[(3 + l) * nc + o]);
+  for (size_t o = 0; o < nc; ++o) {
+    const bool g = p->mats[p->host_map[o]].gain != 0;
+    const size_t q = p->gidx[o];
+    for (int l = 0; l < 3; ++l)
+      host[l * nc + o] = g ? (float)((double)st18[l * nc + q] + (double)st18[(3 + l) * nc + q]) : 0.0f;
+    for (int l = 3; l < 15; ++l) host[l * nc + o] = g ? st18[(3 + l) * nc + q] : 0.0f;
+  }
   return FDTD_OK;
 }
 
@@ -1411,6 +1437,7 @@ int fdtd_class_bytes(const fdtd_plan* p, double* bytes) {
             b += 32.0 * ((in_slab(0, i) ? 1 : 0) + (in_slab(1, j) ? 1 : 0) + (in_slab(2, k) ? 1 : 0));
             const uint8_t m = p->host_map[((size_t)k * ny + j) * nx + i];
             if (p->mats[m].gain) b += gain_cell_bytes(p->gm);
+            if (p->gm == 2 && c >= FD_CLASS_GAIN) b += 4.0;  // the cell's gain ordinal
             acc += b;
           }
     bytes[c] = acc;

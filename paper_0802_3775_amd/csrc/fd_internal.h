@@ -58,10 +58,14 @@ struct fd_desc {
   float* E[2][3];              // ping-pong by step parity
   float* H[2][3];
   float* P[2][3];              // polarization ping-pong (P^n in [n&1], P^{n-1} in the other)
-  // Lorentz model: 6 planes of ncell floats, n1,n2,n3 high parts, then low parts.
-  // Density matrix: 18 planes, rho_11, rho_22, rho_33 high parts, low parts, then
-  // Re rho_01..03, Im rho_01..03, Re rho_12, rho_13, rho_23, Im rho_12, rho_13, rho_23.
+  // Lorentz model: 6 planes of ncell floats, n1,n2,n3 high parts, then low parts,
+  // indexed by cell.  Density matrix: 18 planes of ncell floats, rho_11, rho_22,
+  // rho_33 high parts, low parts, then Re rho_01..03, Im rho_01..03, Re rho_12,
+  // rho_13, rho_23, Im rho_12, rho_13, rho_23, indexed by the cell's gain ordinal
+  // gidx[cell] (gain cells numbered in cell order, so a wavefront's gain cells
+  // read and write contiguous runs; 0 for other cells, which never use it).
   float* pop;
+  const uint32_t* gidx;
   uint32_t key0, key1;
   // CPML
   int pml_lo[3], pml_hi[3], pml_t[3];

@@ -484,6 +484,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
     float pe[2];  // z-slab planes: old psi_E of Ex, Ey (own)
     float gh[3];  // z-slab planes: H-side grading 1/kappa, b, c (uniform)
     float ge[3];  // z-slab planes: E-side grading (uniform)
+    uint32_t gi;  // density-matrix gain: the cell's gain ordinal (state index)
   };
   // Every global load of the z march is issued unconditionally (a lane with
   // nothing to load reads element 0 and discards it), and the march stores to
@@ -512,6 +513,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
     }
   };
   const R32<const uint8_t> matp{(const gu8*)d->mat};
+  const R32<const uint32_t> gidxp{(const __attribute__((address_space(1))) uint32_t*)d->gidx};
   constexpr int PMM = ZT ? PM : (PM & 3);  // CPML axes the march handles
   constexpr bool ZP = ZT && PM == 4;       // z-slab psi prefetched with the plane (z-only CPML tiles)
   constexpr bool AX = PMM == 7;            // all-axes CPML tiles: psi of the plane issued up front
@@ -522,6 +524,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
 #pragma unroll
     for (int q = 0; q < 3; ++q) S.ho[q] = x.Hin[q][io];
     S.m = matp[io];  // lanes outside the grid read cell 0: a valid material
+    if (GAIN == 2) S.gi = gidxp[io];
     // the column i0-1 needs Hy, Hz; the row j0-1 needs Hx, Hz
 #pragma unroll
     for (int q = 0; q < 3; ++q) S.hh[q] = x.Hin[q][ih];
@@ -658,7 +661,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
     bool gk = false;
     if (GAIN) {
       gk = act && ((gmask >> S.m) & 1u);
-      const uint32_t ig = gk ? (uint32_t)o : 0u;
+      const uint32_t ig = gk ? (GAIN == 2 ? S.gi : (uint32_t)o) : 0u;
       const gf* pop = G(d->pop);
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
@@ -917,16 +920,17 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       put(x.Eout[2], o, ez_n);
       if (GAIN == 2 && g) {
         const int nc = d->ncell;
+        const uint32_t q = S.gi;
         gf* pop = G(d->pop);
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
           two_sum(nh[r], nl[r], dminc[r]);
-          pop[(size_t)r * nc + o] = nh[r];
-          pop[(size_t)(3 + r) * nc + o] = nl[r];
-          pop[(size_t)(6 + r) * nc + o] = dmc[r].r;
-          pop[(size_t)(9 + r) * nc + o] = dmc[r].i;
-          pop[(size_t)(12 + r) * nc + o] = dmx[r].r;
-          pop[(size_t)(15 + r) * nc + o] = dmx[r].i;
+          pop[(size_t)r * nc + q] = nh[r];
+          pop[(size_t)(3 + r) * nc + q] = nl[r];
+          pop[(size_t)(6 + r) * nc + q] = dmc[r].r;
+          pop[(size_t)(9 + r) * nc + q] = dmc[r].i;
+          pop[(size_t)(12 + r) * nc + q] = dmx[r].r;
+          pop[(size_t)(15 + r) * nc + q] = dmx[r].i;
         }
       }
       if (GAIN == 1 && g) {
