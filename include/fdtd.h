@@ -251,8 +251,7 @@ int fdtd_class_cells(const fdtd_plan* p, int64_t* cells /* 7 */);
    whose slab holds it (2 E-side psi read+write, 2 H-side psi read + write) + 84
    per Lorentz gain cell (P^n, P^{n-1}, populations in; P^{n+1}, populations
    out) or 144 per density-matrix gain cell (18 floats in and out) + 4 per cell
-   of a density-matrix gain tile (the cell's gain ordinal, which addresses the
-   compact state); the
+   of a gain tile (the cell's gain ordinal, which addresses the gain state); the
    DFT entry is the average bytes of one call: the plane sample (24 bytes read,
    16 written per point) and, once per 32 samples, the 4 complex FP64
    accumulators read + written per plane point and frequency plus the sample

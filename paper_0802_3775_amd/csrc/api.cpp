@@ -135,7 +135,7 @@ struct fdtd_plan {
   fdtd_opal_desc opal{};
   std::vector<int64_t> spheres;  // rows of 5
   std::vector<uint8_t> host_map; // given map, or read back after bind
-  std::vector<uint32_t> gidx;     // density-matrix gain ordinal of each cell (0 elsewhere)
+  std::vector<uint32_t> gidx;     // gain ordinal of each cell (0 elsewhere)
   bool map_given = false;
   std::vector<fdtd_source_desc> sources;
   std::vector<std::array<int, 4>> probes;
@@ -421,7 +421,7 @@ int compute_layout(fdtd_plan* p, int64_t max_steps, Layout& L) {
   for (int b = 0; b < 2; ++b)
     for (int c = 0; c < 3; ++c) L.P[b][c] = gm == 1 ? take(nc * 4) : 0;
   L.pop = gm ? take(nc * 4 * (gm == 2 ? 18 : 6)) : 0;
-  L.gidx = gm == 2 ? take(nc * 4) : 0;
+  L.gidx = gm ? take(nc * 4) : 0;
   for (int w = 0; w < 3; ++w) {
     const bool on = pml_t(p, w) > 0;
     L.prof[w] = on ? take(sizeof(float) * 6 * axis_n(p, w)) : 0;
@@ -836,7 +836,7 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
       d.P[b][c] = p->gm == 1 ? at<float>(p, L.P[b][c]) : nullptr;
     }
   d.pop = p->has_gain ? at<float>(p, L.pop) : nullptr;
-  d.gidx = p->gm == 2 ? at<uint32_t>(p, L.gidx) : nullptr;
+  d.gidx = p->has_gain ? at<uint32_t>(p, L.gidx) : nullptr;
   d.key0 = p->g.seed;
   d.key1 = p->g.realization;
   std::vector<float> prof;
@@ -984,25 +984,18 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
     HIPCHK(hipMemcpyAsync(p->arena + L.map, p->host_map.data(), (size_t)p->ncell, hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
   }
-  if (p->gm == 2) {
-    // gain ordinals and the initial populations at them (the rest of the state
-    // starts at zero with the arena)
+  if (p->has_gain) {
+    // gain ordinals (gain cells numbered in cell order) and the initial
+    // populations at them; the rest of the state starts at zero with the arena
     const size_t nc = (size_t)p->ncell;
     p->gidx.assign(nc, 0u);
-    std::vector<float> init(3 * nc, 0.0f);
     uint32_t g = 0;
-    for (size_t o = 0; o < nc; ++o) {
-      const fdtd_material& m = p->mats[p->host_map[o]];
-      if (!m.gain) continue;
-      p->gidx[o] = g;
-      for (int l = 0; l < 3; ++l) init[l * nc + g] = (float)m.n_init[1 + l];
-      ++g;
-    }
+    for (size_t o = 0; o < nc; ++o)
+      if (p->mats[p->host_map[o]].gain) p->gidx[o] = g++;
     HIPCHK(hipMemcpyAsync(p->arena + L.gidx, p->gidx.data(), sizeof(uint32_t) * nc, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(p->arena + L.pop, init.data(), sizeof(float) * init.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(fd_launch_init_pop(at<uint8_t>(p, L.map), at<float>(p, L.ninit), at<uint32_t>(p, L.gidx), d.gainmask,
+                              d.pop, d.ncell, st));
     HIPCHK(hipStreamSynchronize(st));
-  } else if (p->has_gain) {
-    HIPCHK(fd_launch_init_pop(p->ddesc, at<uint8_t>(p, L.map), at<float>(p, L.ninit), d.pop, d.ncell, st));
   }
 
   // tiles, classified by CPML and gain presence
@@ -1299,7 +1292,7 @@ int fdtd_read_populations(fdtd_plan* p, float* host, void* stream) {
       for (int l = 0; l < 4; ++l) host[l * nc + o] = 0.0f;
       continue;
     }
-    const size_t q = p->gm == 2 ? (size_t)p->gidx[o] : o;  // state index of the cell
+    const size_t q = p->gidx[o];  // state index of the cell
     double lv[3];
     for (int l = 0; l < 3; ++l) lv[l] = (double)pop[l * nc + q] + (double)pop[(3 + l) * nc + q];
     host[0 * nc + o] = (float)(1.0 - (lv[0] + lv[1] + lv[2]));
@@ -1329,10 +1322,13 @@ int fdtd_read_polarization(fdtd_plan* p, float* host, void* stream) {
     return FDTD_OK;
   }
   const int par = (int)(p->step & 1);
+  std::vector<float> pb(3 * nc);
   for (int c = 0; c < 3; ++c)
-    HIPCHK(hipMemcpyAsync(host + (size_t)c * nc, p->arena + p->L.P[par][c], sizeof(float) * nc,
+    HIPCHK(hipMemcpyAsync(pb.data() + (size_t)c * nc, p->arena + p->L.P[par][c], sizeof(float) * nc,
                           hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  for (int c = 0; c < 3; ++c)
+    for (size_t o = 0; o < nc; ++o) host[c * nc + o] = p->mats[p->host_map[o]].gain ? pb[c * nc + p->gidx[o]] : 0.0f;
   return FDTD_OK;
 }
 
@@ -1437,7 +1433,7 @@ int fdtd_class_bytes(const fdtd_plan* p, double* bytes) {
             b += 32.0 * ((in_slab(0, i) ? 1 : 0) + (in_slab(1, j) ? 1 : 0) + (in_slab(2, k) ? 1 : 0));
             const uint8_t m = p->host_map[((size_t)k * ny + j) * nx + i];
             if (p->mats[m].gain) b += gain_cell_bytes(p->gm);
-            if (p->gm == 2 && c >= FD_CLASS_GAIN) b += 4.0;  // the cell's gain ordinal
+            if (c >= FD_CLASS_GAIN) b += 4.0;  // the cell's gain ordinal
             acc += b;
           }
     bytes[c] = acc;

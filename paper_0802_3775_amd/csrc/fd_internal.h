@@ -57,13 +57,13 @@ struct fd_desc {
   const uint8_t* mat;
   float* E[2][3];              // ping-pong by step parity
   float* H[2][3];
-  float* P[2][3];              // polarization ping-pong (P^n in [n&1], P^{n-1} in the other)
-  // Lorentz model: 6 planes of ncell floats, n1,n2,n3 high parts, then low parts,
-  // indexed by cell.  Density matrix: 18 planes of ncell floats, rho_11, rho_22,
-  // rho_33 high parts, low parts, then Re rho_01..03, Im rho_01..03, Re rho_12,
-  // rho_13, rho_23, Im rho_12, rho_13, rho_23, indexed by the cell's gain ordinal
-  // gidx[cell] (gain cells numbered in cell order, so a wavefront's gain cells
-  // read and write contiguous runs; 0 for other cells, which never use it).
+  float* P[2][3];              // polarization ping-pong (P^n in [n&1], P^{n-1} in the other), by gain ordinal
+  // Gain state, indexed by the cell's gain ordinal gidx[cell] (gain cells
+  // numbered in cell order, so a wavefront's gain cells read and write one
+  // contiguous run; 0 for other cells, which never use it).  Lorentz model:
+  // P[2][3] and 6 planes, n1,n2,n3 high parts, then low parts.  Density matrix:
+  // 18 planes, rho_11, rho_22, rho_33 high parts, low parts, then Re rho_01..03,
+  // Im rho_01..03, Re rho_12, rho_13, rho_23, Im rho_12, rho_13, rho_23.
   float* pop;
   const uint32_t* gidx;
   uint32_t key0, key1;
@@ -155,5 +155,5 @@ hipError_t fd_launch_voxelize(const int64_t* sites, int ex, int ey, int ez, cons
                               const int* ncr, const int* origin, const int64_t* reach,
                               int res, int mat_bg, int mat_void, int mat_out,
                               int nx, int ny, int nz, uint8_t* map, hipStream_t st);
-hipError_t fd_launch_init_pop(fd_desc* d_dev, const uint8_t* map, const float* n_init_by_mat,
+hipError_t fd_launch_init_pop(const uint8_t* map, const float* n_init_by_mat, const uint32_t* gidx, unsigned gainmask,
                               float* pop, int ncell, hipStream_t st);

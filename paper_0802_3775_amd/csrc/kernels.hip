@@ -484,7 +484,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
     float pe[2];  // z-slab planes: old psi_E of Ex, Ey (own)
     float gh[3];  // z-slab planes: H-side grading 1/kappa, b, c (uniform)
     float ge[3];  // z-slab planes: E-side grading (uniform)
-    uint32_t gi;  // density-matrix gain: the cell's gain ordinal (state index)
+    uint32_t gi;  // gain cells: the cell's gain ordinal (index of its gain state)
   };
   // Every global load of the z march is issued unconditionally (a lane with
   // nothing to load reads element 0 and discards it), and the march stores to
@@ -524,7 +524,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
 #pragma unroll
     for (int q = 0; q < 3; ++q) S.ho[q] = x.Hin[q][io];
     S.m = matp[io];  // lanes outside the grid read cell 0: a valid material
-    if (GAIN == 2) S.gi = gidxp[io];
+    if (GAIN) S.gi = gidxp[io];
     // the column i0-1 needs Hy, Hz; the row j0-1 needs Hx, Hz
 #pragma unroll
     for (int q = 0; q < 3; ++q) S.hh[q] = x.Hin[q][ih];
@@ -661,7 +661,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
     bool gk = false;
     if (GAIN) {
       gk = act && ((gmask >> S.m) & 1u);
-      const uint32_t ig = gk ? (GAIN == 2 ? S.gi : (uint32_t)o) : 0u;
+      const uint32_t ig = gk ? S.gi : 0u;
       const gf* pop = G(d->pop);
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
@@ -948,11 +948,11 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) inc = fmaf(mt.MI[r][q], nn[q], inc);
           two_sum(nh[r], nl[r], inc);
-          pop[(size_t)r * nc + o] = nh[r];
-          pop[(size_t)(3 + r) * nc + o] = nl[r];
+          pop[(size_t)r * nc + S.gi] = nh[r];
+          pop[(size_t)(3 + r) * nc + S.gi] = nl[r];
         }
 #pragma unroll
-        for (int q = 0; q < 3; ++q) G(d->P[par ^ 1][q])[o] = Pnew[q];
+        for (int q = 0; q < 3; ++q) G(d->P[par ^ 1][q])[S.gi] = Pnew[q];
       }
       for (unsigned mm = pmask; mm; mm &= mm - 1u) {  // uniform
         const int p = __builtin_ctz(mm);
@@ -1341,16 +1341,17 @@ __global__ void voxelize_kernel(const int64_t* __restrict__ sites, int ex, int e
   }
 }
 
-__global__ void init_pop_kernel(const uint8_t* __restrict__ map, const float* __restrict__ ninit, float* pop,
-                                int ncell) {
+// Initial upper-level populations of the gain cells at their gain ordinals (the
+// low parts and every other state variable start at zero with the arena).
+__global__ void init_pop_kernel(const uint8_t* __restrict__ map, const float* __restrict__ ninit,
+                                const uint32_t* __restrict__ gidx, unsigned gainmask, float* pop, int ncell) {
   const int stride = gridDim.x * blockDim.x;
   for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < ncell; o += stride) {
     const int m = map[o];
+    if (!((gainmask >> m) & 1u)) continue;
+    const uint32_t g = gidx[o];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      pop[q * ncell + o] = ninit[4 * m + 1 + q];
-      pop[(3 + q) * ncell + o] = 0.0f;
-    }
+    for (int q = 0; q < 3; ++q) pop[(size_t)q * ncell + g] = ninit[4 * m + 1 + q];
   }
 }
 
@@ -1485,11 +1486,10 @@ hipError_t fd_launch_voxelize(const int64_t* sites, int ex, int ey, int ez, cons
   return hipGetLastError();
 }
 
-hipError_t fd_launch_init_pop(fd_desc* d_dev, const uint8_t* map, const float* n_init_by_mat, float* pop, int ncell,
-                              hipStream_t st) {
-  (void)d_dev;
+hipError_t fd_launch_init_pop(const uint8_t* map, const float* n_init_by_mat, const uint32_t* gidx, unsigned gainmask,
+                              float* pop, int ncell, hipStream_t st) {
   int blocks = (ncell + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  init_pop_kernel<<<blocks, 256, 0, st>>>(map, n_init_by_mat, pop, ncell);
+  init_pop_kernel<<<blocks, 256, 0, st>>>(map, n_init_by_mat, gidx, gainmask, pop, ncell);
   return hipGetLastError();
 }
