@@ -69,3 +69,17 @@ def test_dye_parameters_and_their_normalised_rates():
     assert g2 / t_unit == pytest.approx(p["gain_bandwidth_hz_printed"], rel=1e-12)
     assert g1 / t_unit == pytest.approx(1.0 / p["t1_s"], rel=1e-12)
     assert w0 == pytest.approx(2 * math.pi * m["f_a"], rel=1e-15)
+
+
+def test_diffusion_run_pulse_and_window():
+    """The dynamic-diffusion run: a 100 fs pulse (intensity FWHM) in the paper's
+    box and beam, T(t) at the back margin, 2.5 ps at Courant 0.5."""
+    p = _load("paper_parameters.json")
+    cfg = W.paper_diffusion(0.1)
+    src = cfg["sources"][0]
+    t_unit = p["a_m"] / C0
+    assert src["width_kind"] == "fwhm_intensity"
+    assert src["width"] * t_unit == pytest.approx(100e-15, rel=1e-12)
+    assert cfg["steps"] * 0.5 / cfg["grid"]["res"] * t_unit == pytest.approx(2.5e-12, rel=1e-4)
+    assert cfg["flux"][0]["k"] > cfg["layout"]["z0"] + cfg["opal"]["cells"][2] * cfg["grid"]["res"]
+    assert cfg["grid"]["n"] == (p["grid_cells_per_axis"],) * 3
