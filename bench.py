@@ -123,10 +123,12 @@ def copy_bandwidth(reps=10):
 
 def kernel_table(plan, nsteps):
     """Per kernel class: average launch duration (a hipEvent pair bound to each
-    launch on the launch stream: the kernel's own begin and end timestamps) and the algorithmic bytes of one launch (libfdtd counts
-    them per cell: 49 B, +32 B per CPML slab axis, +84 B per gain cell; a DFT
-    launch stores a 40 B/point plane sample and, once per 32-sample ring, moves
-    128 B per plane point and frequency: averaged per launch)."""
+    launch on the launch stream: the kernel's own begin and end timestamps) and
+    the algorithmic bytes of one launch (libfdtd counts them per cell: 49 B, +32 B
+    per CPML slab axis, +84 B per Lorentz or +144 B per density-matrix gain cell,
+    +4 B per cell of a gain tile for its gain ordinal; a DFT launch stores a
+    40 B/point plane sample and, once per 32-sample ring, moves 128 B per plane
+    point and frequency: averaged per launch)."""
     from paper_0802_3775_amd import fdtd
     ms, cnt = plan.time_kernels(nsteps)
     cells = plan.class_cells()

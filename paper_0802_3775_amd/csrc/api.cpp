@@ -2,7 +2,8 @@
 // tables, graph capture, batches and read-back.  The C ABI is include/fdtd.h.
 //
 // Method: C. Conti and A. Fratalocchi, arXiv:0802.3775 (Yee FDTD in a
-// disordered inverted opal with a pumped gain medium; sections "Sample and
+// disordered inverted opal with a pumped gain medium -- a Lorentz oscillator with
+// four-level rate equations, or the paper's density matrix; sections "Sample and
 // numerical approach", "Dynamical diffusion and localization", lasing section).
 #include <hip/hip_runtime.h>
 

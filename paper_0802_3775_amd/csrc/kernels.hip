@@ -1,15 +1,18 @@
-// gfx950 kernels of libfdtd: one fused Yee step (H then E, CPML, Lorentz ADE,
-// four-level populations, noise, soft sources, probes, transmitted power,
-// energy), the running-DFT flux update, the integer voxelizer and small helpers.
+// gfx950 kernels of libfdtd: one fused Yee step (H then E, CPML, the gain media
+// -- Lorentz ADE with four-level populations, or the density matrix of a ground
+// level and three degenerate upper levels -- noise, soft sources, probes,
+// transmitted power, energy), the running-DFT flux update, the integer
+// voxelizer and small helpers.
 //
 // Method: C. Conti and A. Fratalocchi, arXiv:0802.3775 — Yee FDTD with absorbing
 // walls in a disordered inverted opal, pumped gain medium seeded by a stochastic
 // source, transmitted power T(t) (sections "Sample and numerical approach" and
 // "Dynamical diffusion and localization").
 //
-// Stepping scheme.  E, H, the H-side CPML memory and the polarization are
-// double-buffered by step parity, so one step reads only buffer n&1 and writes
-// only the other one.  Every tile is therefore independent within a step, and a
+// Stepping scheme.  E, H, the H-side CPML memory and the Lorentz polarization
+// are double-buffered by step parity, so one step reads only buffer n&1 and
+// writes only the other one (the E-side CPML memory, the populations and the
+// density matrix are read and written only by their own cell's thread).  Every tile is therefore independent within a step, and a
 // workgroup can recompute the H^{n+1/2} values its E update needs at x-1, y-1 and
 // z-1 from the read-only inputs instead of waiting for the owner: one pass over
 // HBM per step (E, H, material index in; E, H out).
