@@ -24,20 +24,24 @@ from . import workloads as W
 def request_config(req):
     """Workload dict of a request: linear slab (crystal n^3 cubic cells at `res`,
     vacuum margins, z-CPML, pulse, transmission flux) or lasing box (n^3 cells,
-    CPML on all faces, gain voids at pump 1e10 s^-1)."""
+    CPML on all faces, gain voids at pump 1e10 s^-1; req["model"] = "density"
+    fills them with the density-matrix dye instead of the Lorentz medium)."""
     n, res = int(req["n"]), int(req["res"])
     if req["kind"] == "linear":
         cfg = W.slab(delta=req["delta"], seed=req["seed"], res=res, cells=(n, n, n), steps=req["steps"],
                      nf=req.get("nf", 100), decim=8, energy_interval=req.get("energy_interval", 100))
     else:
         cfg = W.lasing(pump=req.get("pump", 1e10), delta=req["delta"], seed=req["seed"], res=res,
-                       cells=(n, n, n), steps=req["steps"], energy_interval=req.get("energy_interval", 100))
+                       cells=(n, n, n), steps=req["steps"], energy_interval=req.get("energy_interval", 100),
+                       model=req.get("model", "lorentz"))
     cfg["name"] = "req%d_%s" % (req["id"], cfg["name"])
     return cfg
 
 
 class GpuBackend:
-    """libfdtd plans and batches; one torch uint8 arena per request."""
+    """libfdtd plans and batches; one torch uint8 arena per request.  Requests
+    with the density-matrix medium step in a batch of their own (members of one
+    batch share a gain model); linear and Lorentz requests share the other."""
 
     def __init__(self, tuning=None):
         import torch
@@ -45,13 +49,14 @@ class GpuBackend:
         self.fdtd = fdtd
         self.torch = torch
         self.tuning = tuning or fdtd.default_tuning()
-        self._batch = None
-        self._members = None
+        self._batch = {}
+        self._members = {}
 
     def prepare(self, req):
         cfg = request_config(req)
         plan = self.fdtd.Plan(cfg, max_steps=req["steps"], tuning=self.tuning, bind=False)
-        return {"plan": plan, "cfg": cfg, "bytes": plan.required_bytes() + 256}
+        dm = any(int(m.get("gain") or 0) == 2 for m in cfg["materials"])
+        return {"plan": plan, "cfg": cfg, "bytes": plan.required_bytes() + 256, "group": int(dm)}
 
     def footprint(self, h):
         return h["bytes"]
@@ -60,16 +65,20 @@ class GpuBackend:
         h["plan"].bind()
 
     def step(self, hs, n):
-        if len(hs) == 1:
-            hs[0]["plan"].step(n)   # a lone request runs on the plain stepper
-            return
-        members = tuple(id(h["plan"]) for h in hs)
-        if members != self._members:
-            if self._batch is not None:
-                self._batch.close()
-            self._batch = self.fdtd.Batch([h["plan"] for h in hs])
-            self._members = members
-        self._batch.step(n)
+        groups = {}
+        for h in hs:
+            groups.setdefault(h["group"], []).append(h)
+        for key, g in groups.items():
+            if len(g) == 1:
+                g[0]["plan"].step(n)   # a lone request runs on the plain stepper
+                continue
+            members = tuple(id(h["plan"]) for h in g)
+            if members != self._members.get(key):
+                if self._batch.get(key) is not None:
+                    self._batch[key].close()
+                self._batch[key] = self.fdtd.Batch([h["plan"] for h in g])
+                self._members[key] = members
+            self._batch[key].step(n)
 
     def sync(self):
         self.torch.cuda.synchronize()
@@ -96,10 +105,12 @@ class GpuBackend:
         return out
 
     def release(self, h):
-        if self._members is not None and id(h["plan"]) in self._members:
-            if self._batch is not None:
-                self._batch.close()
-            self._batch, self._members = None, None
+        for key in list(self._members):
+            if id(h["plan"]) in self._members[key]:
+                if self._batch.get(key) is not None:
+                    self._batch[key].close()
+                self._batch.pop(key, None)
+                self._members.pop(key, None)
         h["plan"].close()
 
 

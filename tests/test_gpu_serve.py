@@ -1,5 +1,6 @@
 """Continuous-batching server on the GPU: requests that join while others run
-produce exactly the results they produce when run alone."""
+(linear, Lorentz lasing and density-matrix lasing, the last in a batch of their
+own) produce exactly the results they produce when run alone."""
 import numpy as np
 import pytest
 
@@ -14,6 +15,11 @@ def _trace():
         {"id": 2, "arrival": 0.02, "kind": "linear", "n": 2, "res": 8, "delta": 0.00, "seed": 503, "steps": 400, "nf": 8},
         {"id": 3, "arrival": 0.05, "kind": "linear", "n": 1, "res": 12, "delta": 0.10, "seed": 504, "steps": 800, "nf": 10},
         {"id": 4, "arrival": 0.08, "kind": "lasing", "n": 1, "res": 10, "delta": 0.03, "seed": 505, "steps": 400},
+        # density-matrix dye: a batch of their own beside the others
+        {"id": 5, "arrival": 0.00, "kind": "lasing", "model": "density", "n": 1, "res": 8, "delta": 0.05,
+         "seed": 506, "steps": 600},
+        {"id": 6, "arrival": 0.03, "kind": "lasing", "model": "density", "n": 1, "res": 10, "delta": 0.02,
+         "seed": 507, "steps": 400},
     ]
 
 
