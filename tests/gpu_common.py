@@ -46,3 +46,14 @@ def pec_clean(fields, periodic):
                 sl[2 - a] = 0
                 fields[c][tuple(sl)] = 0.0
     return fields
+
+
+def emission_peak_bin(probe, dt, start):
+    """Bin index (and frequency) of the emission peak: |FFT|^2 of the Hann-windowed
+    probe record from `start` to its end, argmax on 0.6-0.9 c/a."""
+    from paper_0802_3775_amd import analysis as A
+    x = np.asarray(probe[start:], dtype=np.float64)
+    f, P = A.field_spectrum(x * np.hanning(len(x)), dt)
+    band = np.nonzero((f >= 0.6) & (f <= 0.9))[0]
+    q = int(band[np.argmax(P[band])])
+    return q, float(f[q])

@@ -10,7 +10,7 @@ Every tile class with gain (plain, z-CPML, all-axes CPML) is exercised."""
 import numpy as np
 import pytest
 
-from gpu_common import field_rel_l2, rel_l2
+from gpu_common import emission_peak_bin, field_rel_l2, rel_l2
 from oracle import oracle as O
 from paper_0802_3775_amd import workloads as W
 
@@ -107,6 +107,11 @@ def test_density_lasing_box_parity(merge):
         # together past the onset as well; the bound is the one stated up to it
         assert ferr <= 1e-3 and derr <= 1e-3
     assert onset < steps  # the run reaches the onset
+    # emission peak of the probe from the onset on: the same bin within one
+    qg, fg = emission_peak_bin(plan.probe(0), plan.dt, onset)
+    qo, fo = emission_peak_bin(orc.probe(0), orc.dt, onset)
+    _say("emission peak", fg, fo)
+    assert abs(qg - qo) <= 1
     pops = plan.populations().astype(np.float64)
     assert np.max(np.abs(pops[:, gain].sum(axis=0) - 1.0)) <= 1e-6
     assert np.all(pops[:, gain] >= -1e-4)

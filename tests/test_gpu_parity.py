@@ -9,7 +9,7 @@ Tolerances (stated for the method's FP32 fields):
 import numpy as np
 import pytest
 
-from gpu_common import field_rel_l2, pec_clean, rel_l2, run_gpu, run_oracle
+from gpu_common import emission_peak_bin, field_rel_l2, pec_clean, rel_l2, run_gpu, run_oracle
 from oracle import oracle as O
 from paper_0802_3775_amd import workloads as W
 
@@ -280,3 +280,9 @@ def test_lasing_reduced_populations_and_fields():
     assert err <= 1e-3
     assert rel_l2(gpu.probe(0), orc.probe(0)) <= 1e-3
     assert rel_l2(gpu.polarization()[:, gain], orc.polarization()[:, gain]) <= 1e-3
+    # emission peak of the probe from the onset on: the same bin within one
+    start = int(onset) * cfg["energy_interval"]
+    qg, fg = emission_peak_bin(gpu.probe(0), gpu.dt, start)
+    qo, fo = emission_peak_bin(orc.probe(0), orc.dt, start)
+    _say("emission peak", fg, fo)
+    assert abs(qg - qo) <= 1
