@@ -422,6 +422,9 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   const int i = i0 + tx, j = j0 + ty;
   const bool act = i < x.nx && j < x.ny;
   const int c = j * x.nx + i;
+  // the cell's column / row lies on the PEC wall x = 0 / y = 0 (its tangential
+  // E components are held at zero there)
+  const bool pec_i = !x.px && i == 0, pec_j = !x.py && j == 0;
 
   // ---- per-tile gather offsets (plane-relative), outside the z loop
   int own_off;
@@ -447,12 +450,14 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   };
   int r_slot = -1, r_off = -1;
   if (t < nring) ring_cell(t, r_slot, r_off);
-  // halo duty: threads [0, TY) own the column i0-1, threads [TY, TY+TX) the row j0-1
-  const bool lh = t < TY;
-  const bool bh = !lh && t < TY + TX;
-  const int hgi = wrap(lh ? i0 - 1 : i0 + (t - TY), x.nx, x.px);
-  const int hgj = wrap(lh ? j0 + t : j0 - 1, x.ny, x.py);
-  const bool hact = (lh || bh) && hgi >= 0 && hgj >= 0 && (lh ? (j0 + t < x.ny) : (i0 + (t - TY) < x.nx));
+  // halo duty: threads [0, TX) own the row j0-1, threads [TX, TX+TY) the column
+  // i0-1; hr: column of the row cell / row of the column cell
+  const bool bh = t < TX;
+  const bool lh = !bh && t < TX + TY;
+  const int hr = lh ? t - TX : t;
+  const int hgi = wrap(lh ? i0 - 1 : i0 + hr, x.nx, x.px);
+  const int hgj = wrap(lh ? j0 + hr : j0 - 1, x.ny, x.py);
+  const bool hact = (lh || bh) && hgi >= 0 && hgj >= 0 && (lh ? (j0 + hr < x.ny) : (i0 + hr < x.nx));
   const int h_off = hact ? hgj * x.nx + hgi : 0;
 
   // ---- sources, probes and flux planes that touch the tile (set on the host);
@@ -520,6 +525,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   constexpr int PMM = ZT ? PM : (PM & 3);  // CPML axes the march handles
   constexpr bool ZP = ZT && PM == 4;       // z-slab psi prefetched with the plane (z-only CPML tiles)
   constexpr bool AX = PMM == 7;            // all-axes CPML tiles: psi of the plane issued up front
+  static_assert(PMM == 0 || PMM == 4 || PMM == 7, "tile classes: no CPML, z slabs, all axes");
   auto load_h = [&](int kk, Stage& S, bool live) {
     kk = live ? kk : 0;
     const int zo = kk * x.plane;
@@ -722,6 +728,20 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         put(x.Hout[0], o, hx);
         put(x.Hout[1], o, hy);
         put(x.Hout[2], o, hz);
+      } else if (PMM == 0) {
+        // no CPML memory: every lane computes (lanes outside the grid read
+        // in-bounds LDS slots and element 0 of H) and only the stores are masked
+        hx = h_from<0>(x, 0, 1, j, 2, k, i, j, k, Ez[a + W], Ez[a], Ey1[a], Ey[a], S.ho[0], true);
+        hy = h_from<0>(x, 1, 2, k, 0, i, i, j, k, Ex1[a], Ex[a], Ez[a + 1], Ez[a], S.ho[1], true);
+        hz = h_from<0>(x, 2, 0, i, 1, j, i, j, k, Ey[a + 1], Ey[a], Ex[a + W], Ex[a], S.ho[2], true);
+        hx = act ? hx : 0.0f;
+        hy = act ? hy : 0.0f;
+        hz = act ? hz : 0.0f;
+        if (act) {
+          put(x.Hout[0], o, hx);
+          put(x.Hout[1], o, hy);
+          put(x.Hout[2], o, hz);
+        }
       } else if (act) {
         hx = h_from<PMM, ZP>(x, 0, 1, j, 2, k, i, j, k, Ez[a + W], Ez[a], Ey1[a], Ey[a], S.ho[0], true, sz, c, S.ph[0], S.gh);
         hy = h_from<PMM, ZP>(x, 1, 2, k, 0, i, i, j, k, Ex1[a], Ex[a], Ez[a + 1], Ez[a], S.ho[1], true, sz, c, S.ph[1], S.gh);
@@ -734,54 +754,54 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       s.H[0][hs] = hx;
       s.H[1][hs] = hy;
       s.H[2][hs] = hz;
-      if (hact) {
+      if (hact && AX) {
         if (lh) {
-          // cell (i0-1, j0+t): LDS column 0, row t+1
-          const int e = (t + 1) * W;
-          float hyv, hzv;
-          if (AX) {
-            const int yj = t + 1;  // hgj = j0 + t; the column i0-1 is x-table entry 0
-            float d1 = Ex1[e] - Ex[e], d2 = Ez[e + 1] - Ez[e];
-            d1 = stretch_v(d1, sz, gzH[0], gzH[1], gzH[2], aHh[0], false, x.psiHout[2][1], 0u);
-            d2 = stretch_v(d2, sxh, s.gx[3][0], s.gx[4][0], s.gx[5][0], aHh[1], false, x.psiHout[0][0], 0u);
-            hyv = fmaf(-x.ch, d1 - d2, S.hh[1]);
-            d1 = Ey[e + 1] - Ey[e];
-            d2 = Ex[e + W] - Ex[e];
-            d1 = stretch_v(d1, sxh, s.gx[3][0], s.gx[4][0], s.gx[5][0], aHh[2], false, x.psiHout[0][1], 0u);
-            d2 = stretch_v(d2, syh, s.gy[3][yj], s.gy[4][yj], s.gy[5][yj], aHh[3], false, x.psiHout[1][0], 0u);
-            hzv = fmaf(-x.ch, d1 - d2, S.hh[2]);
-          } else {
-            hyv = h_from<PMM, ZP>(x, 1, 2, k, 0, hgi, hgi, hgj, k, Ex1[e], Ex[e], Ez[e + 1], Ez[e], S.hh[1],
-                                  false, sz, h_off, S.phh[1], S.gh);
-            hzv = h_from<PMM, ZP>(x, 2, 0, hgi, 1, hgj, hgi, hgj, k, Ey[e + 1], Ey[e], Ex[e + W], Ex[e],
-                                  S.hh[2], false, sz, h_off, 0.0f, S.gh);
-          }
-          s.H[1][(t + 1) * (TX + 1)] = hyv;
-          s.H[2][(t + 1) * (TX + 1)] = hzv;
+          // cell (i0-1, j0+hr): LDS column 0, row hr+1; y-table entry hr+1, x-table entry 0
+          const int e = (hr + 1) * W;
+          const int yj = hr + 1;
+          float d1 = Ex1[e] - Ex[e], d2 = Ez[e + 1] - Ez[e];
+          d1 = stretch_v(d1, sz, gzH[0], gzH[1], gzH[2], aHh[0], false, x.psiHout[2][1], 0u);
+          d2 = stretch_v(d2, sxh, s.gx[3][0], s.gx[4][0], s.gx[5][0], aHh[1], false, x.psiHout[0][0], 0u);
+          const float hyv = fmaf(-x.ch, d1 - d2, S.hh[1]);
+          d1 = Ey[e + 1] - Ey[e];
+          d2 = Ex[e + W] - Ex[e];
+          d1 = stretch_v(d1, sxh, s.gx[3][0], s.gx[4][0], s.gx[5][0], aHh[2], false, x.psiHout[0][1], 0u);
+          d2 = stretch_v(d2, syh, s.gy[3][yj], s.gy[4][yj], s.gy[5][yj], aHh[3], false, x.psiHout[1][0], 0u);
+          const float hzv = fmaf(-x.ch, d1 - d2, S.hh[2]);
+          s.H[1][(hr + 1) * (TX + 1)] = hyv;
+          s.H[2][(hr + 1) * (TX + 1)] = hzv;
         } else {
-          // cell (i0+q-1, j0-1): LDS row 0, column q
-          const int q = t - TY + 1;
-          float hxv, hzv;
-          if (AX) {
-            // hgi = i0 + q - 1: x-table entry q; the row j0-1 is y-table entry 0
-            float d1 = Ez[W + q] - Ez[q], d2 = Ey1[q] - Ey[q];
-            d1 = stretch_v(d1, syh, s.gy[3][0], s.gy[4][0], s.gy[5][0], aHh[1], false, x.psiHout[1][1], 0u);
-            d2 = stretch_v(d2, sz, gzH[0], gzH[1], gzH[2], aHh[0], false, x.psiHout[2][0], 0u);
-            hxv = fmaf(-x.ch, d1 - d2, S.hh[0]);
-            d1 = Ey[q + 1] - Ey[q];
-            d2 = Ex[W + q] - Ex[q];
-            d1 = stretch_v(d1, sxh, s.gx[3][q], s.gx[4][q], s.gx[5][q], aHh[2], false, x.psiHout[0][1], 0u);
-            d2 = stretch_v(d2, syh, s.gy[3][0], s.gy[4][0], s.gy[5][0], aHh[3], false, x.psiHout[1][0], 0u);
-            hzv = fmaf(-x.ch, d1 - d2, S.hh[2]);
-          } else {
-            hxv = h_from<PMM, ZP>(x, 0, 1, hgj, 2, k, hgi, hgj, k, Ez[W + q], Ez[q], Ey1[q], Ey[q], S.hh[0],
-                                  false, sz, h_off, S.phh[0], S.gh);
-            hzv = h_from<PMM, ZP>(x, 2, 0, hgi, 1, hgj, hgi, hgj, k, Ey[q + 1], Ey[q], Ex[W + q], Ex[q],
-                                  S.hh[2], false, sz, h_off, 0.0f, S.gh);
-          }
+          // cell (i0+q-1, j0-1): LDS row 0, column q; x-table entry q, y-table entry 0
+          const int q = hr + 1;
+          float d1 = Ez[W + q] - Ez[q], d2 = Ey1[q] - Ey[q];
+          d1 = stretch_v(d1, syh, s.gy[3][0], s.gy[4][0], s.gy[5][0], aHh[1], false, x.psiHout[1][1], 0u);
+          d2 = stretch_v(d2, sz, gzH[0], gzH[1], gzH[2], aHh[0], false, x.psiHout[2][0], 0u);
+          const float hxv = fmaf(-x.ch, d1 - d2, S.hh[0]);
+          d1 = Ey[q + 1] - Ey[q];
+          d2 = Ex[W + q] - Ex[q];
+          d1 = stretch_v(d1, sxh, s.gx[3][q], s.gx[4][q], s.gx[5][q], aHh[2], false, x.psiHout[0][1], 0u);
+          d2 = stretch_v(d2, syh, s.gy[3][0], s.gy[4][0], s.gy[5][0], aHh[3], false, x.psiHout[1][0], 0u);
+          const float hzv = fmaf(-x.ch, d1 - d2, S.hh[2]);
           s.H[0][q] = hxv;
           s.H[2][q] = hzv;
         }
+      } else if (hact) {
+        // the column cell (i0-1, j0+hr) takes Hy and Hz, the row cell (i0+hr, j0-1)
+        // Hx and Hz: one path for both, operands selected per lane.  The first
+        // component is -(dt/dx)(z difference - transverse difference of Ez) for
+        // the column and -(dt/dx)(y difference of Ez - z difference) for the row;
+        // bit-identical to the two h_from calls it replaces
+        const int b = lh ? (hr + 1) * W : hr + 1;  // E slot of the halo cell
+        const float* z1 = lh ? Ex1 : Ey1;
+        const float* z0 = lh ? Ex : Ey;
+        float zd = z1[b] - z0[b];
+        if (ZP) zd = stretch_z<true>(x, 0, S.gh, sz, h_off, zd, false, lh ? S.phh[1] : S.phh[0]);
+        const float td = Ez[b + (lh ? 1 : W)] - Ez[b];
+        const float v1 = fmaf(-x.ch, lh ? zd - td : td - zd, lh ? S.hh[1] : S.hh[0]);
+        const float hzv = fmaf(-x.ch, (Ey[b + 1] - Ey[b]) - (Ex[b + W] - Ex[b]), S.hh[2]);
+        const int hb = lh ? (hr + 1) * (TX + 1) : hr + 1;  // H slot of the halo cell
+        (lh ? s.H[1] : s.H[0])[hb] = v1;
+        s.H[2][hb] = hzv;
       }
     }
     lds_barrier();
@@ -855,7 +875,20 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       // av: E^{n+1} without the polarization current; on: not a PEC-held component
       float av[3] = {0.0f, 0.0f, 0.0f};
       bool on[3] = {false, false, false};
-      if (!((!x.py && j == 0) || (!x.pz && k == 0))) {  // Ex: d/dy Hz - d/dz Hy
+      if (PMM == 0) {
+        // no CPML memory: plain selects for the components held by a PEC wall
+        const bool pec_k = !x.pz && k == 0;  // uniform over the plane
+        on[0] = !(pec_j | pec_k);
+        on[1] = !(pec_k | pec_i);
+        on[2] = !(pec_i | pec_j);
+        const float v0 = fmaf(mt.cb, ((hz - hz_jm) - (hy - hym)) - cx, eo[0]);
+        const float v1 = fmaf(mt.cb, ((hx - hxm) - (hz - hz_im)) - cy, eo[1]);
+        const float v2 = fmaf(mt.cb, ((hy - hy_im) - (hx - hx_jm)) - cz, eo[2]);
+        av[0] = on[0] ? v0 : 0.0f;
+        av[1] = on[1] ? v1 : 0.0f;
+        av[2] = on[2] ? v2 : 0.0f;
+      } else {
+      if (!(pec_j || (!x.pz && k == 0))) {  // Ex: d/dy Hz - d/dz Hy
         float d1 = hz - hz_jm, d2 = hy - hym;
         if (AX) {
           d1 = stretch_v(d1, syo, s.gy[0][ty + 1], s.gy[1][ty + 1], s.gy[2][ty + 1], aE[0], true, x.psiE[1][1], oy);
@@ -867,7 +900,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         av[0] = fmaf(mt.cb, (d1 - d2) - cx, eo[0]);
         on[0] = true;
       }
-      if (!((!x.pz && k == 0) || (!x.px && i == 0))) {  // Ey: d/dz Hx - d/dx Hz
+      if (!((!x.pz && k == 0) || pec_i)) {  // Ey: d/dz Hx - d/dx Hz
         float d1 = hx - hxm, d2 = hz - hz_im;
         if (AX) {
           d1 = stretch_v(d1, sz, gzE[0], gzE[1], gzE[2], aE[2], true, x.psiE[2][1], oz);
@@ -879,7 +912,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         av[1] = fmaf(mt.cb, (d1 - d2) - cy, eo[1]);
         on[1] = true;
       }
-      if (!((!x.px && i == 0) || (!x.py && j == 0))) {  // Ez: d/dx Hy - d/dy Hx
+      if (!(pec_i || pec_j)) {  // Ez: d/dx Hy - d/dy Hx
         float d1 = hy - hy_im, d2 = hx - hx_jm;
         if (AX) {
           d1 = stretch_v(d1, sxo, s.gx[0][tx + 1], s.gx[1][tx + 1], s.gx[2][tx + 1], aE[4], true, x.psiE[0][1], ox);
@@ -890,6 +923,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         }
         av[2] = fmaf(mt.cb, (d1 - d2) - cz, eo[2]);
         on[2] = true;
+      }
       }
       if (GAIN == 2 && g) {
         // one predictor-corrector pass of the implicit midpoint coupling:
@@ -915,9 +949,17 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
 #pragma unroll
         for (int q = 0; q < 3; ++q) dP[q] = mt.bk2 * dmc[q].r - Pn[q];
       }
-      if (on[0]) ex_n = av[0] - dP[0] * mt.inv_eps;
-      if (on[1]) ey_n = av[1] - dP[1] * mt.inv_eps;
-      if (on[2]) ez_n = av[2] - dP[2] * mt.inv_eps;
+      if (GAIN == 0) {
+        // no polarization current: av is E^{n+1} (0 where a PEC wall holds it),
+        // bit for bit what av - 0 / eps gives
+        ex_n = av[0];
+        ey_n = av[1];
+        ez_n = av[2];
+      } else {
+        if (on[0]) ex_n = av[0] - dP[0] * mt.inv_eps;
+        if (on[1]) ey_n = av[1] - dP[1] * mt.inv_eps;
+        if (on[2]) ez_n = av[2] - dP[2] * mt.inv_eps;
+      }
       put(x.Eout[0], o, ex_n);
       put(x.Eout[1], o, ey_n);
       put(x.Eout[2], o, ez_n);
@@ -1030,8 +1072,13 @@ __device__ __forceinline__ void step_body(const fd_tile* __restrict__ tiles, int
   // and the density-matrix kernels keep one general march (two would not fit
   // their register budget)
   auto run = [&](const fd_tile& tl) {
-    if (PM == 4 && GAIN != 2 && !(tl.flags & FD_TILE_ZSLAB)) run_tile<TX, PM, GAIN, false, NT>(tl, s, lds);
-    else run_tile<TX, PM, GAIN, (PM & 4) != 0, NT>(tl, s, lds);
+    if constexpr (PM == 4 && GAIN != 2) {
+      if (!(tl.flags & FD_TILE_ZSLAB)) {
+        run_tile<TX, PM, GAIN, false, NT>(tl, s, lds);
+        return;
+      }
+    }
+    run_tile<TX, PM, GAIN, (PM & 4) != 0, NT>(tl, s, lds);
   };
   if (use_part) {
     const int x = (int)blockIdx.x % 8, q = (int)blockIdx.x / 8;
