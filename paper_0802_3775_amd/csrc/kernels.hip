@@ -485,10 +485,11 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
     float ring[3];
     bool zok;     // plane inside the grid (or its periodic image)
     float ho[3];  // H^{n-1/2} of the own cell
-    float hh[3];  // Hx, Hy, Hz at the halo-duty cell
+    float hsel;   // halo-duty cell: Hy (column cell) or Hx (row cell)
+    float hh2;    // halo-duty cell: Hz
     int m;
     float ph[2];  // z-slab planes: old psi_H of Hx, Hy (own)
-    float phh[2]; // z-slab planes: old psi_H of Hx, Hy at the halo-duty cell
+    float phz;    // z-slab planes: old psi_H of hsel's z difference at the halo-duty cell
     float pe[2];  // z-slab planes: old psi_E of Ex, Ey (own)
     float gh[3];  // z-slab planes: H-side grading 1/kappa, b, c (uniform)
     float ge[3];  // z-slab planes: E-side grading (uniform)
@@ -534,9 +535,12 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
     for (int q = 0; q < 3; ++q) S.ho[q] = x.Hin[q][io];
     S.m = matp[io];  // lanes outside the grid read cell 0: a valid material
     if (GAIN) S.gi = gidxp[io];
-    // the column i0-1 needs Hy, Hz; the row j0-1 needs Hx, Hz
-#pragma unroll
-    for (int q = 0; q < 3; ++q) S.hh[q] = x.Hin[q][ih];
+    // the column i0-1 needs Hy, Hz; the row j0-1 needs Hx, Hz.  The lane picks
+    // the array (a choice between two loaded values would wait for both loads
+    // at once, and a choice between two Stage fields becomes an indexed, spilled
+    // access)
+    S.hsel = R32<const float>{lh ? x.Hin[1].p : x.Hin[0].p}[ih];
+    S.hh2 = x.Hin[2][ih];
     if (ZP) {
       // the z differences of Hx, Hy, Ex, Ey in a z slab carry psi: load the
       // old values with the plane's other inputs (psi_E is touched only by the
@@ -554,8 +558,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       S.ph[1] = x.psiHin[2][fam(1, 2)][jo];
       S.pe[0] = x.psiE[2][fam(0, 2)][jo];
       S.pe[1] = x.psiE[2][fam(1, 2)][jo];
-      S.phh[0] = x.psiHin[2][fam(0, 2)][jh];
-      S.phh[1] = x.psiHin[2][fam(1, 2)][jh];
+      S.phz = R32<const float>{lh ? x.psiHin[2][fam(1, 2)].p : x.psiHin[2][fam(0, 2)].p}[jh];
     }
   };
 
@@ -755,36 +758,29 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       s.H[1][hs] = hy;
       s.H[2][hs] = hz;
       if (hact && AX) {
-        if (lh) {
-          // cell (i0-1, j0+hr): LDS column 0, row hr+1; y-table entry hr+1, x-table entry 0
-          const int e = (hr + 1) * W;
-          const int yj = hr + 1;
-          float d1 = Ex1[e] - Ex[e], d2 = Ez[e + 1] - Ez[e];
-          d1 = stretch_v(d1, sz, gzH[0], gzH[1], gzH[2], aHh[0], false, x.psiHout[2][1], 0u);
-          d2 = stretch_v(d2, sxh, s.gx[3][0], s.gx[4][0], s.gx[5][0], aHh[1], false, x.psiHout[0][0], 0u);
-          const float hyv = fmaf(-x.ch, d1 - d2, S.hh[1]);
-          d1 = Ey[e + 1] - Ey[e];
-          d2 = Ex[e + W] - Ex[e];
-          d1 = stretch_v(d1, sxh, s.gx[3][0], s.gx[4][0], s.gx[5][0], aHh[2], false, x.psiHout[0][1], 0u);
-          d2 = stretch_v(d2, syh, s.gy[3][yj], s.gy[4][yj], s.gy[5][yj], aHh[3], false, x.psiHout[1][0], 0u);
-          const float hzv = fmaf(-x.ch, d1 - d2, S.hh[2]);
-          s.H[1][(hr + 1) * (TX + 1)] = hyv;
-          s.H[2][(hr + 1) * (TX + 1)] = hzv;
-        } else {
-          // cell (i0+q-1, j0-1): LDS row 0, column q; x-table entry q, y-table entry 0
-          const int q = hr + 1;
-          float d1 = Ez[W + q] - Ez[q], d2 = Ey1[q] - Ey[q];
-          d1 = stretch_v(d1, syh, s.gy[3][0], s.gy[4][0], s.gy[5][0], aHh[1], false, x.psiHout[1][1], 0u);
-          d2 = stretch_v(d2, sz, gzH[0], gzH[1], gzH[2], aHh[0], false, x.psiHout[2][0], 0u);
-          const float hxv = fmaf(-x.ch, d1 - d2, S.hh[0]);
-          d1 = Ey[q + 1] - Ey[q];
-          d2 = Ex[W + q] - Ex[q];
-          d1 = stretch_v(d1, sxh, s.gx[3][q], s.gx[4][q], s.gx[5][q], aHh[2], false, x.psiHout[0][1], 0u);
-          d2 = stretch_v(d2, syh, s.gy[3][0], s.gy[4][0], s.gy[5][0], aHh[3], false, x.psiHout[1][0], 0u);
-          const float hzv = fmaf(-x.ch, d1 - d2, S.hh[2]);
-          s.H[0][q] = hxv;
-          s.H[2][q] = hzv;
-        }
+        // column cell (i0-1, j0+hr): Hy(z, x) and Hz(x, y); row cell (i0+hr, j0-1):
+        // Hx(y, z) and Hz(x, y).  One path, operands selected per lane (the
+        // column's x-table entry is 0 and its y-table entry hr+1, the row's the
+        // reverse); bit-identical to separate column and row paths
+        const int b = lh ? (hr + 1) * W : hr + 1;  // E slot of the halo cell
+        const int xe = lh ? 0 : hr + 1, ye = lh ? hr + 1 : 0;
+        const float* z1 = lh ? Ex1 : Ey1;
+        const float* z0 = lh ? Ex : Ey;
+        float zd = z1[b] - z0[b];
+        zd = stretch_v(zd, sz, gzH[0], gzH[1], gzH[2], aHh[0], false, x.psiHout[2][0], 0u);
+        // the transverse difference of Ez: along x for the column, along y for the row
+        float td = Ez[b + (lh ? 1 : W)] - Ez[b];
+        td = stretch_v(td, lh ? sxh : syh, lh ? s.gx[3][0] : s.gy[3][0], lh ? s.gx[4][0] : s.gy[4][0],
+                       lh ? s.gx[5][0] : s.gy[5][0], aHh[1], false, x.psiHout[0][0], 0u);
+        const float v1 = fmaf(-x.ch, lh ? zd - td : td - zd, S.hsel);
+        float d1 = Ey[b + 1] - Ey[b];
+        float d2 = Ex[b + W] - Ex[b];
+        d1 = stretch_v(d1, sxh, s.gx[3][xe], s.gx[4][xe], s.gx[5][xe], aHh[2], false, x.psiHout[0][1], 0u);
+        d2 = stretch_v(d2, syh, s.gy[3][ye], s.gy[4][ye], s.gy[5][ye], aHh[3], false, x.psiHout[1][0], 0u);
+        const float hzv = fmaf(-x.ch, d1 - d2, S.hh2);
+        const int hb = lh ? (hr + 1) * (TX + 1) : hr + 1;  // H slot of the halo cell
+        (lh ? s.H[1] : s.H[0])[hb] = v1;
+        s.H[2][hb] = hzv;
       } else if (hact) {
         // the column cell (i0-1, j0+hr) takes Hy and Hz, the row cell (i0+hr, j0-1)
         // Hx and Hz: one path for both, operands selected per lane.  The first
@@ -795,10 +791,10 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         const float* z1 = lh ? Ex1 : Ey1;
         const float* z0 = lh ? Ex : Ey;
         float zd = z1[b] - z0[b];
-        if (ZP) zd = stretch_z<true>(x, 0, S.gh, sz, h_off, zd, false, lh ? S.phh[1] : S.phh[0]);
+        if (ZP) zd = stretch_z<true>(x, 0, S.gh, sz, h_off, zd, false, S.phz);
         const float td = Ez[b + (lh ? 1 : W)] - Ez[b];
-        const float v1 = fmaf(-x.ch, lh ? zd - td : td - zd, lh ? S.hh[1] : S.hh[0]);
-        const float hzv = fmaf(-x.ch, (Ey[b + 1] - Ey[b]) - (Ex[b + W] - Ex[b]), S.hh[2]);
+        const float v1 = fmaf(-x.ch, lh ? zd - td : td - zd, S.hsel);
+        const float hzv = fmaf(-x.ch, (Ey[b + 1] - Ey[b]) - (Ex[b + W] - Ex[b]), S.hh2);
         const int hb = lh ? (hr + 1) * (TX + 1) : hr + 1;  // H slot of the halo cell
         (lh ? s.H[1] : s.H[0])[hb] = v1;
         s.H[2][hb] = hzv;
