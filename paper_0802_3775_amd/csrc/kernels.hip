@@ -502,20 +502,36 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   // exactly the Stage it consumes and leaves the other one in flight.
   // live = false: the plane is past the tile; the loads are still issued (at
   // element 0) so that every path through the march issues the same loads.
+  // Linear tiles without x / y CPML (EREG) keep the own cell's E^n of planes k
+  // and k+1 in registers and form each load address with one select: in-plane
+  // offsets are clamped to cell 0 once where the lane has nothing to load (its
+  // values are discarded at use).  The other classes, near their register caps,
+  // read those E values from LDS and select per load.  Either way a plane the
+  // march does not need (past the tile, or outside the CPML slabs for psi) is
+  // read at element 0 by every lane: one cache line, not a row of another plane.
+  constexpr bool EREG = GAIN == 0 && !(ZT && PM == 7);
+  const uint32_t own_l = own_off >= 0 ? own_off : 0, ring_l = r_off >= 0 ? r_off : 0;
+  const uint32_t c_l = act ? c : 0;  // h_off is already 0 without halo duty
   auto load_e = [&](int kk, Stage& S, bool live) {
     const int kz = kk < x.nz ? kk : (x.pz ? kk - x.nz : -1);
     S.zok = kz >= 0;
-    const int zo = S.zok ? kz * x.plane : 0;
-    const uint32_t io = (live && own_off >= 0) ? zo + own_off : 0, ir = (live && r_off >= 0) ? zo + r_off : 0;
+    const uint32_t zo = S.zok ? kz * x.plane : 0;
+    const uint32_t io = EREG ? (live ? zo + own_l : 0u) : ((live && own_off >= 0) ? zo + own_off : 0u);
+    const uint32_t ir = EREG ? (live ? zo + ring_l : 0u) : ((live && r_off >= 0) ? zo + r_off : 0u);
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) S.own[cc] = x.Ein[cc][io];
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) S.ring[cc] = x.Ein[cc][ir];
   };
-  auto store_e = [&](int b, const Stage& S) {
+  // stages E^n of the Stage's plane into LDS buffer b; eown receives the own
+  // cell's values (0 beyond a PEC wall), which the march keeps in registers
+  auto store_e = [&](int b, const Stage& S, float eown[3]) {
     const bool oko = S.zok && own_off >= 0, okr = S.zok && r_off >= 0;
 #pragma unroll
-    for (int cc = 0; cc < 3; ++cc) s.E[b][cc][own_slot] = oko ? S.own[cc] : 0.0f;
+    for (int cc = 0; cc < 3; ++cc) {
+      eown[cc] = oko ? S.own[cc] : 0.0f;
+      s.E[b][cc][own_slot] = eown[cc];
+    }
     if (r_slot >= 0) {
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) s.E[b][cc][r_slot] = okr ? S.ring[cc] : 0.0f;
@@ -529,8 +545,9 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   static_assert(PMM == 0 || PMM == 4 || PMM == 7, "tile classes: no CPML, z slabs, all axes");
   auto load_h = [&](int kk, Stage& S, bool live) {
     kk = live ? kk : 0;
-    const int zo = kk * x.plane;
-    const uint32_t io = (live && act) ? zo + c : 0, ih = (live && hact) ? zo + h_off : 0;
+    const uint32_t zo = kk * x.plane;
+    const uint32_t io = EREG ? (live ? zo + c_l : 0u) : ((live && act) ? zo + c : 0u);
+    const uint32_t ih = EREG ? (live ? zo + h_off : 0u) : ((live && hact) ? zo + h_off : 0u);
 #pragma unroll
     for (int q = 0; q < 3; ++q) S.ho[q] = x.Hin[q][io];
     S.m = matp[io];  // lanes outside the grid read cell 0: a valid material
@@ -552,8 +569,10 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         S.ge[q] = x.prof[2][q * nz + kk];
         S.gh[q] = x.prof[2][(3 + q) * nz + kk];
       }
-      const int base = (sz >= 0 ? sz : 0) * x.plane;
-      const uint32_t jo = (live && sz >= 0 && act) ? base + c : 0, jh = (live && sz >= 0 && hact) ? base + h_off : 0;
+      const bool in = live && sz >= 0;
+      const uint32_t base = in ? sz * x.plane : 0;
+      const uint32_t jo = EREG ? (in ? base + c_l : 0u) : ((in && act) ? base + c : 0u);
+      const uint32_t jh = EREG ? (in ? base + h_off : 0u) : ((in && hact) ? base + h_off : 0u);
       S.ph[0] = x.psiHin[2][fam(0, 2)][jo];
       S.ph[1] = x.psiHin[2][fam(1, 2)][jo];
       S.pe[0] = x.psiE[2][fam(0, 2)][jo];
@@ -584,7 +603,8 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
     pHx = x.Hin[0][om];
     pHy = x.Hin[1][om];
   }
-  store_e(0, SA);
+  float ecur[3];  // E^n of the own cell at the plane being marched
+  store_e(0, SA, ecur);
   load_e(k0 + 1, SA, true);
   load_h(k0, SA, true);
   load_e(k0 + 2, SB, k0 + 1 < k1);
@@ -592,7 +612,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   // H^{n+1/2} at (i, j, k0-1); E^n at (i, j, k0) is already in LDS buffer 0
   float hxm = 0.0f, hym = 0.0f;
   if (pro) {
-    const float ey1 = s.E[0][1][own_slot], ex1 = s.E[0][0][own_slot];
+    const float ey1 = ecur[1], ex1 = ecur[0];
     const float ezj = jp >= 0 ? pEzj : 0.0f, ezi = ip >= 0 ? pEzi : 0.0f;
     hxm = h_from<PM>(x, 0, 1, j, 2, km, i, j, km, ezj, pEz, ey1, pEy, pHx, false);
     hym = h_from<PM>(x, 1, 2, km, 0, i, i, j, km, ex1, pEx, ezi, pEz, pHy, false);
@@ -629,7 +649,8 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
     constexpr int cb = decltype(cbc)::value;
     constexpr int nb = cb ^ 1;
     // plane k+1 into LDS; the loads two planes ahead reuse the same Stage
-    store_e(nb, S);
+    float enx[3];  // E^n of the own cell at plane k+1
+    store_e(nb, S, enx);
     const int zo = k * x.plane;
     const int o = zo + c;
     const int sz = (ZP || AX) ? slab(x, 2, k) : -1;
@@ -695,11 +716,12 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
     // the memory counter retires in order, so waiting for those does not wait
     // for them
     load_e(k + 3, S, k + 2 < k1);
-    // E^n of the own cell (plane k), read before the second barrier: after it a
-    // faster wave may already be staging plane k+2 into this buffer
+    // E^n of the own cell at plane k, from registers or read from LDS before the
+    // second barrier (after it a faster wave may already be staging plane k+2
+    // into this buffer)
     float eo[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) eo[q] = s.E[cb][q][own_slot];
+    for (int q = 0; q < 3; ++q) eo[q] = EREG ? ecur[q] : s.E[cb][q][own_slot];
     lds_barrier();
     // ---- H^{n+1/2} of plane k: own cell and halo duty
     float hx = 0.0f, hy = 0.0f, hz = 0.0f;
@@ -710,21 +732,26 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       const float* Ex1 = s.E[nb][0];
       const float* Ey1 = s.E[nb][1];
       const int a = own_slot;
+      // own-cell E^n at planes k and k+1: registers in the classes that carry
+      // them, else the LDS copies (equal values; the capped classes are short
+      // of registers)
+      const float e0x = EREG ? eo[0] : Ex[a], e0y = EREG ? eo[1] : Ey[a], e0z = EREG ? eo[2] : Ez[a];
+      const float e1x = EREG ? enx[0] : Ex1[a], e1y = EREG ? enx[1] : Ey1[a];
       if (act && AX) {
         const int xi = tx + 1, yj = ty + 1;
         const float* gxh[3] = {s.gx[3], s.gx[4], s.gx[5]};
         const float* gyh[3] = {s.gy[3], s.gy[4], s.gy[5]};
-        float d1 = Ez[a + W] - Ez[a], d2 = Ey1[a] - Ey[a];
+        float d1 = Ez[a + W] - e0z, d2 = e1y - e0y;
         d1 = stretch_v(d1, syo, gyh[0][yj], gyh[1][yj], gyh[2][yj], aH[0], true, x.psiHout[1][1], oy);
         d2 = stretch_v(d2, sz, gzH[0], gzH[1], gzH[2], aH[1], true, x.psiHout[2][0], oz);
         hx = fmaf(-x.ch, d1 - d2, S.ho[0]);
-        d1 = Ex1[a] - Ex[a];
-        d2 = Ez[a + 1] - Ez[a];
+        d1 = e1x - e0x;
+        d2 = Ez[a + 1] - e0z;
         d1 = stretch_v(d1, sz, gzH[0], gzH[1], gzH[2], aH[2], true, x.psiHout[2][1], oz);
         d2 = stretch_v(d2, sxo, gxh[0][xi], gxh[1][xi], gxh[2][xi], aH[3], true, x.psiHout[0][0], ox);
         hy = fmaf(-x.ch, d1 - d2, S.ho[1]);
-        d1 = Ey[a + 1] - Ey[a];
-        d2 = Ex[a + W] - Ex[a];
+        d1 = Ey[a + 1] - e0y;
+        d2 = Ex[a + W] - e0x;
         d1 = stretch_v(d1, sxo, gxh[0][xi], gxh[1][xi], gxh[2][xi], aH[4], true, x.psiHout[0][1], ox);
         d2 = stretch_v(d2, syo, gyh[0][yj], gyh[1][yj], gyh[2][yj], aH[5], true, x.psiHout[1][0], oy);
         hz = fmaf(-x.ch, d1 - d2, S.ho[2]);
@@ -734,9 +761,9 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       } else if (PMM == 0) {
         // no CPML memory: every lane computes (lanes outside the grid read
         // in-bounds LDS slots and element 0 of H) and only the stores are masked
-        hx = h_from<0>(x, 0, 1, j, 2, k, i, j, k, Ez[a + W], Ez[a], Ey1[a], Ey[a], S.ho[0], true);
-        hy = h_from<0>(x, 1, 2, k, 0, i, i, j, k, Ex1[a], Ex[a], Ez[a + 1], Ez[a], S.ho[1], true);
-        hz = h_from<0>(x, 2, 0, i, 1, j, i, j, k, Ey[a + 1], Ey[a], Ex[a + W], Ex[a], S.ho[2], true);
+        hx = h_from<0>(x, 0, 1, j, 2, k, i, j, k, Ez[a + W], e0z, e1y, e0y, S.ho[0], true);
+        hy = h_from<0>(x, 1, 2, k, 0, i, i, j, k, e1x, e0x, Ez[a + 1], e0z, S.ho[1], true);
+        hz = h_from<0>(x, 2, 0, i, 1, j, i, j, k, Ey[a + 1], e0y, Ex[a + W], e0x, S.ho[2], true);
         hx = act ? hx : 0.0f;
         hy = act ? hy : 0.0f;
         hz = act ? hz : 0.0f;
@@ -746,9 +773,9 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
           put(x.Hout[2], o, hz);
         }
       } else if (act) {
-        hx = h_from<PMM, ZP>(x, 0, 1, j, 2, k, i, j, k, Ez[a + W], Ez[a], Ey1[a], Ey[a], S.ho[0], true, sz, c, S.ph[0], S.gh);
-        hy = h_from<PMM, ZP>(x, 1, 2, k, 0, i, i, j, k, Ex1[a], Ex[a], Ez[a + 1], Ez[a], S.ho[1], true, sz, c, S.ph[1], S.gh);
-        hz = h_from<PMM, ZP>(x, 2, 0, i, 1, j, i, j, k, Ey[a + 1], Ey[a], Ex[a + W], Ex[a], S.ho[2], true, sz, c, 0.0f, S.gh);
+        hx = h_from<PMM, ZP>(x, 0, 1, j, 2, k, i, j, k, Ez[a + W], e0z, e1y, e0y, S.ho[0], true, sz, c, S.ph[0], S.gh);
+        hy = h_from<PMM, ZP>(x, 1, 2, k, 0, i, i, j, k, e1x, e0x, Ez[a + 1], e0z, S.ho[1], true, sz, c, S.ph[1], S.gh);
+        hz = h_from<PMM, ZP>(x, 2, 0, i, 1, j, i, j, k, Ey[a + 1], e0y, Ex[a + W], e0x, S.ho[2], true, sz, c, 0.0f, S.gh);
         put(x.Hout[0], o, hx);
         put(x.Hout[1], o, hy);
         put(x.Hout[2], o, hz);
@@ -1024,6 +1051,8 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       }
     }
     hxm = hx;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) ecur[q] = enx[q];
     hym = hy;
   };
 
