@@ -1070,7 +1070,6 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
         if (d.pml_t[0] && (t.i0 - 1 < d.pml_lo[0] || iend > p->g.nx - d.pml_hi[0])) axes |= 1;
         if (d.pml_t[1] && (t.j0 - 1 < d.pml_lo[1] || jend > p->g.ny - d.pml_hi[1])) axes |= 2;
         int pml = axes == 0 ? 0 : (axes == 4 ? 1 : 2);
-        if (axes & 3) t.flags |= FD_TILE_XY;
         long long ngain = 0;
         if (p->has_gain)
           for (int k = t.k0; k < t.k1; ++k) ngain += blk_gain[(size_t)k * p->nblk + t.blk];

@@ -109,10 +109,9 @@ struct fd_tile {
   int tidx, blk;
   // sources, probes and flux planes that touch the tile (bit q = entry q)
   unsigned srcmask, pmask, fmask;
-  int flags;  // FD_TILE_ZSLAB: some plane of [k0, k1) lies in a z CPML slab; FD_TILE_XY below
+  int flags;  // FD_TILE_ZSLAB: some plane of [k0, k1) lies in a z CPML slab
 };
 #define FD_TILE_ZSLAB 1
-#define FD_TILE_XY 2  // some H or E value the tile evaluates lies in an x or y CPML slab
 
 // DFT work unit: FD_DFT_PTS plane points x 4 components x FD_DFT_QB frequencies.
 struct fd_dft_tile {

@@ -1094,22 +1094,12 @@ template <int TX, int PM, int GAIN, bool NT>
 __device__ __forceinline__ void step_body(const fd_tile* __restrict__ tiles, int ntiles, int s, const fd_xcd& part,
                                           int use_part, Lds<TX>& lds) {
   // z-only CPML launches specialise their interior tiles; the all-axes kernel
-  // without gain sends tiles that touch no x / y slab (about half of a box
-  // with CPML on every face, all in one launch when classes are merged) to the
-  // z-only or plain march, the code those tiles run in separate launches.
-  // The gain kernels keep one general march (more would not fit their
-  // register budget).
+  // and the density-matrix kernels keep one general march (two would not fit
+  // their register budget)
   auto run = [&](const fd_tile& tl) {
     if constexpr (PM == 4 && GAIN != 2) {
       if (!(tl.flags & FD_TILE_ZSLAB)) {
         run_tile<TX, PM, GAIN, false, NT>(tl, s, lds);
-        return;
-      }
-    }
-    if constexpr (PM == 7 && GAIN == 0) {
-      if (!(tl.flags & FD_TILE_XY)) {
-        if (tl.flags & FD_TILE_ZSLAB) run_tile<TX, 4, GAIN, true, NT>(tl, s, lds);
-        else run_tile<TX, 4, GAIN, false, NT>(tl, s, lds);
         return;
       }
     }

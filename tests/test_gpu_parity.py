@@ -135,9 +135,8 @@ def test_flux_spectra_between_dft_flushes():
 def test_beam_reduced_parity():
     """The paper's linear workload at reduced size (TEM00 beam sheet, uniform-radius
     disorder, CPML on all six faces): fields, probe and T(t) against the oracle, with
-    a launch per tile class and with every class in the all-axes launch (whose tiles
-    that touch no x / y slab take the z-only and plain marches); the two agree bit
-    for bit."""
+    a launch per tile class and with every class in the all-axes launch; the two
+    agree bit for bit."""
     steps = 500
     cfg = W.paper_beam(gamma=0.1, seed=5, res=8, cells=2, margin=6, pml=6, steps=steps)
     _say("beam reduced", cfg["grid"]["n"], steps)
