@@ -66,10 +66,14 @@ enum { FDTD_SRC_DIPOLE = 0, FDTD_SRC_PLANE = 1, FDTD_SRC_BEAM = 2 };
 enum { FDTD_WIDTH_FWHM_POWER = 0, FDTD_WIDTH_FWHM_INTENSITY = 1, FDTD_WIDTH_SIGMA_T = 2 };
 enum { FDTD_DISORDER_NONE = 0, FDTD_DISORDER_UNIFORM_RADIUS = 1, FDTD_DISORDER_GAUSS_JITTER = 2 };
 
+enum { FDTD_STORES_AUTO = 0, FDTD_STORES_ORDINARY = 1, FDTD_STORES_NONTEMPORAL = 2 };
+
 typedef struct fdtd_plan fdtd_plan;
 typedef struct fdtd_batch fdtd_batch;
 
-/* Grid.  bc[d]: FDTD_BC_PERIODIC or FDTD_BC_PEC (PEC walls at both ends of axis
+/* Grid (paper, "Sample and numerical approach": the Yee grid of the FDTD code,
+   a 6 um box of 200^3 cells with absorbing walls).  bc[d]: FDTD_BC_PERIODIC or
+   FDTD_BC_PEC (PEC walls at both ends of axis
    d, optionally lined with pml_lo[d] / pml_hi[d] CPML layers).  CPML grading:
    sigma = sigma_max (rho/d)^m, kappa = 1 + (kappa_max - 1)(rho/d)^m,
    alpha = alpha_max (1 - rho/d); sigma_max <= 0 selects 0.8 (m + 1) / dx.
@@ -85,7 +89,10 @@ typedef struct {
   uint32_t seed, realization;
 } fdtd_grid_desc;
 
-/* Material.  eps: relative permittivity (host permittivity of a gain medium).
+/* Material (paper, "Sample and numerical approach": the opal's eps_r = 12, the
+   dye of index 1.3 in the spheres, its four-level Maxwell-Bloch model with T1,
+   T2 and the noise source; "3+1D simulation of lasing": the pumped medium).
+   eps: relative permittivity (host permittivity of a gain medium).
    gain = 1: four-level medium with total density n_total (m^-3), lifetimes
    tau32, tau21, tau10 (s), pump rate 0->3 (s^-1), Lorentz transition f_a and
    FWHM linewidth df_a (c/a), noise amplitude, initial fractions n_init[0..3].
@@ -110,7 +117,10 @@ typedef struct {
   double t1, t2, dipole;
 } fdtd_material;
 
-/* Source: s(t) = amp sin(2 pi f0 (t - t0)) exp(-(t - t0)^2 / (2 sigma_t^2)),
+/* Source (paper, "Wide-band excitation and gap filling": the single-cycle
+   linearly polarised TEM00 pulse of 2 um waist launched along [100];
+   "Dynamical diffusion and localization": the 100 fs Gaussian pulse).
+   s(t) = amp sin(2 pi f0 (t - t0)) exp(-(t - t0)^2 / (2 sigma_t^2)),
    t0 = delay * sigma_t.  Width: FWHM of the power spectrum (c/a), FWHM of the
    intensity envelope (a/c), or sigma_t (a/c).  DIPOLE: current s/dx^3 on E_comp
    of cell (i,j,k).  PLANE: sheet current s on E_comp over the whole z = k plane.
@@ -127,7 +137,10 @@ typedef struct {
   double x0, y0, waist;
 } fdtd_source_desc;
 
-/* Inverted opal: cells[3] cubic fcc cells starting at grid index origin[3];
+/* Inverted opal (paper, "Sample and numerical approach": air spheres of radius
+   r0 = a/(2 sqrt 2) at the fcc sites of the cubic lattice, disorder r = r0 (1 +
+   gamma xi) with xi uniform in [-1/2, 1/2]).  cells[3] cubic fcc cells starting
+   at grid index origin[3];
    air-sphere radius r0 (units of a); disorder with strength gamma (uniform
    radius) or delta/a (Gaussian jitter of radii and centres, truncated at
    4 delta).  Voxels inside any sphere get mat_void, the rest of the crystal
@@ -141,7 +154,8 @@ typedef struct {
   int32_t mat_bg, mat_void, mat_out;
 } fdtd_opal_desc;
 
-/* Launch tuning (per plan).  block: threads per workgroup, one (i,j) column per
+/* Launch tuning (per plan; an implementation choice the paper does not touch:
+   results do not depend on it).  block: threads per workgroup, one (i,j) column per
    thread (64..256, multiple of 64); tile_x: tile width along x (16, 32 or 64;
    the tile is tile_x x block/tile_x columns, and its one-cell halo ring,
    2 (tile_x + 2) + 2 block/tile_x cells, must not exceed block: 16 with any
@@ -152,94 +166,152 @@ typedef struct {
    kernel of the same gain flag (one launch for both); 2 every tile runs with the
    plan's most general kernel (one launch per step).  parallel: 1 makes the
    launches of a step parallel branches of the captured graph, 0 keeps them in
-   stream order.  Results do not depend on any of these. */
+   stream order.  stores: FDTD_STORES_AUTO (non-temporal field stores for a plan
+   whose step state exceeds four times the 256 MB Infinity Cache, ordinary ones
+   otherwise and in batches), FDTD_STORES_ORDINARY or FDTD_STORES_NONTEMPORAL.
+   Results do not depend on any of these. */
 typedef struct {
-  int32_t block, zchunk, graph_steps, max_blocks, tile_x, merge, parallel;
+  int32_t block, zchunk, graph_steps, max_blocks, tile_x, merge, parallel, stores;
 } fdtd_tuning;
 
+/* Message of the last failed call on this thread; library version string. */
 const char* fdtd_last_error(void);
 const char* fdtd_version(void);
 
-/* Create a plan (host only).  Checks sizes, boundaries and the Courant limit. */
+/* Create a plan (host only): the Yee grid of "Sample and numerical approach".
+   Checks sizes, boundaries and the Courant limit (FDTD_EUNSTABLE). *out owned by
+   the caller until fdtd_plan_destroy, which also releases the plan's graphs. */
 int fdtd_plan_create(const fdtd_grid_desc* g, fdtd_plan** out);
 void fdtd_plan_destroy(fdtd_plan* p);
 
-/* Material table (n <= FDTD_MAX_MATERIALS).  Coefficients are built in FP64 and
-   rounded once to FP32. */
+/* Material table (n <= FDTD_MAX_MATERIALS; "Sample and numerical approach").
+   Coefficients are built in FP64 and rounded once to FP32.  FDTD_EINVAL for bad
+   parameters, FDTD_EUNSUPPORTED for two gain models in one plan. */
 int fdtd_set_materials(fdtd_plan* p, const fdtd_material* tab, int32_t n);
 
-/* Build the opal: the sphere list on the host (FP64, Philox key (seed,
+/* Build the opal ("Sample and numerical approach": the inverted opal and its
+   random-number disorder): the sphere list on the host (FP64, Philox key (seed,
    realization), counter (site id, 0, 0, 0)) quantized to integers, then the
    integer-exact voxelization on the device at bind.  Site id = h + (2nx+1)(k +
    (2ny+1) l) for fcc sites (h, k, l)/2.  Alternatively give the map directly. */
 int fdtd_build_opal(fdtd_plan* p, const fdtd_opal_desc* d);
 int fdtd_set_material_map(fdtd_plan* p, const uint8_t* host_map);
-/* Quantized spheres: rows (site id, Cx, Cy, Cz, rho) in units of a/(2 res 2^16)
-   relative to the crystal origin.  out may be NULL to query n. */
+/* Quantized spheres of the opal (same passage): rows (site id, Cx, Cy, Cz, rho)
+   in units of a/(2 res 2^16) relative to the crystal origin.  out may be NULL to
+   query n; out holds 5 n int64 (caller-owned). */
 int fdtd_get_spheres(const fdtd_plan* p, int64_t* out, int64_t* n);
-/* Voxelized material map (after bind), [nz][ny][nx]. */
+/* Voxelized material map (after bind), [nz][ny][nx] bytes into caller memory:
+   the index profile of the Fig. 1 inset.  Synchronizes the stream. */
 int fdtd_get_material_map(fdtd_plan* p, uint8_t* host_map, void* stream);
 
+/* Add a source (the excitations of "Wide-band excitation and gap filling" and
+   "Dynamical diffusion and localization", or a point dipole); *id (may be NULL)
+   its index.  At most FDTD_MAX_SOURCES; FDTD_EINVAL outside the grid. */
 int fdtd_add_source(fdtd_plan* p, const fdtd_source_desc* s, int32_t* id);
-/* Probe of component comp (0..5 = Ex Ey Ez Hx Hy Hz) at (i,j,k), recorded after
-   every step (E^{n+1}, H^{n+1/2}). */
+/* Probe ("Wide-band excitation and gap filling": the field retrieved at a low
+   symmetry point inside the sample) of component comp (0..5 = Ex Ey Ez Hx Hy Hz)
+   at (i,j,k), recorded after every step (E^{n+1}, H^{n+1/2}). */
 int fdtd_add_probe(fdtd_plan* p, int32_t comp, int32_t i, int32_t j, int32_t k, int32_t* id);
-/* Flux plane normal to z at index k: T(t_{n+1/2}) = sum over the plane of the
-   time-centred S_z dx^2 every step, and the running DFT of Ex, Ey (time n) and
-   the z-averaged Hx, Hy (time n+1/2) at nf frequencies f (c/a) every decim steps,
-   FP64 accumulators. */
-int fdtd_add_flux_plane(fdtd_plan* p, int32_t k, const double* f, int32_t nf, int32_t decim,
+/* Flux plane ("Dynamical diffusion and localization": the transmitted power
+   T(t), the transversely integrated Poynting vector at the output face) normal
+   to axis (only 2, z, the launch direction; 0 and 1 give FDTD_EUNSUPPORTED) at
+   index k: T(t_{n+1/2}) = sum over the plane of the time-centred S_z dx^2 every
+   step, and the running DFT of Ex, Ey (time n) and the z-averaged Hx, Hy (time
+   n+1/2) at nf frequencies f (c/a, copied) every decim steps, FP64
+   accumulators. */
+int fdtd_add_flux_plane(fdtd_plan* p, int32_t axis, int32_t k, const double* f, int32_t nf, int32_t decim,
                         int32_t* id);
-/* Energy W^n = 1/2 sum (eps |E^n|^2 + H^{n-1/2} . H^{n+1/2}) dx^3 every ke steps. */
+/* Energy ("3+1D simulation of lasing": the stored electromagnetic energy
+   density) W^n = 1/2 sum (eps |E^n|^2 + H^{n-1/2} . H^{n+1/2}) dx^3 every ke
+   steps (0: off). */
 int fdtd_set_energy_interval(fdtd_plan* p, int32_t ke);
 /* Tuning is fixed at bind: call before fdtd_required_bytes / fdtd_bind_arena. */
 int fdtd_set_tuning(fdtd_plan* p, const fdtd_tuning* t);
 int fdtd_get_tuning(const fdtd_plan* p, fdtd_tuning* t);
 
-/* Device bytes the plan needs for up to max_steps steps. */
+/* Device bytes the plan needs for up to max_steps steps (layout of the arena;
+   no passage of the paper: the run length of "Wide-band excitation" is 10^5
+   steps). */
 int fdtd_required_bytes(fdtd_plan* p, int64_t max_steps, size_t* bytes);
-/* Bind the caller's device arena (fixes the layout, zero-fills, uploads tables,
-   voxelizes).  After this the plan's configuration is frozen. */
+/* Bind the caller's device arena dev (>= fdtd_required_bytes, 256-byte aligned,
+   owned by the caller and alive until destroy): fixes the layout, zero-fills,
+   uploads tables, voxelizes.  After this the plan's configuration is frozen.
+   FDTD_ENOMEM if bytes is too small; synchronizes the stream. */
 int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, void* stream);
 
-/* Advance n steps on the stream (asynchronous). */
+/* Advance n leapfrog steps ("Sample and numerical approach": FDTD after
+   Taflove, with the Maxwell-Bloch gain cells) on the stream, asynchronous;
+   FDTD_ESTATE past max_steps, leaving the state untouched.  Step count, cell
+   count and dt of the plan. */
 int fdtd_step(fdtd_plan* p, int64_t n, void* stream);
 int64_t fdtd_step_count(const fdtd_plan* p);
 int64_t fdtd_cell_count(const fdtd_plan* p);
 double fdtd_dt(const fdtd_plan* p);
 
-/* Field component comp (0..5), nx*ny*nz floats, host memory. */
+/* Field component comp (0..5) of the current step, nx*ny*nz floats in host
+   memory (caller-owned); write sets initial conditions.  Synchronize. */
 int fdtd_read_field(fdtd_plan* p, int32_t comp, float* host, void* stream);
 int fdtd_write_field(fdtd_plan* p, int32_t comp, const float* host, void* stream);
-/* Probe samples 0..n-1 (n = steps taken). */
+/* Probe samples 0..n-1 (n = steps taken) into host floats (max_steps room). */
 int fdtd_read_probe(fdtd_plan* p, int32_t id, float* host, int64_t* n, void* stream);
 /* T(t) samples (n = steps taken, may be NULL) and the flux spectrum
-   P(f) = Re sum (Ex Hy* - Ey Hx*) dx^2 (nf values, may be NULL). */
+   P(f) = Re sum (Ex Hy* - Ey Hx*) dx^2 (nf values, may be NULL) of flux plane id
+   ("Dynamical diffusion and localization"; the spectra of Fig. 1). */
 int fdtd_read_flux(fdtd_plan* p, int32_t id, double* T, double* spec, int64_t* n, void* stream);
-/* Populations n0..n3 (4 * cells floats; zero outside gain cells). */
+/* Populations n0..n3 of the four-level medium ("Sample and numerical approach":
+   the four-level system; the density matrix's diagonal for gain = 2), 4 * cells
+   floats, zero outside gain cells.  n0 is not stored: it is 1 - (n1 + n2 + n3),
+   so the sum of the four is 1 by construction. */
 int fdtd_read_populations(fdtd_plan* p, float* host, void* stream);
-/* Polarization P^n, 3 * cells floats. */
+/* Polarization P^n of the gain cells (same passage), 3 * cells floats. */
 int fdtd_read_polarization(fdtd_plan* p, float* host, void* stream);
-/* Density matrix of a gain = 2 plan, 15 * cells floats: rho_11, rho_22, rho_33,
+/* Density matrix ("Sample and numerical approach": the su(4) real form of the
+   four-level density matrix) of a gain = 2 plan, 15 * cells floats: rho_11, rho_22, rho_33,
    Re rho_01, Re rho_02, Re rho_03, Im rho_01, Im rho_02, Im rho_03, Re rho_12,
    Re rho_13, Re rho_23, Im rho_12, Im rho_13, Im rho_23 (zero outside gain
    cells).  FDTD_ESTATE for plans without such a medium. */
 int fdtd_read_density(fdtd_plan* p, float* host, void* stream);
-/* Energy samples W^0, W^ke, ... (n returned). */
+/* Energy samples W^0, W^ke, ... (n returned) into host doubles. */
 int fdtd_read_energy(fdtd_plan* p, double* host, int64_t* n, void* stream);
 
-/* Batches: bound plans that step together, one launch per tile class per step
-   over all plans' tiles (uneven sizes, each plan's own tuning and step count).
-   Stepping a batch advances every member; members must stay alive. */
-int fdtd_batch_create(fdtd_plan* const* plans, int32_t n, fdtd_batch** out);
+/* Batches ("Wide-band excitation and gap filling": results averaged over 10
+   realizations of the disorder): bound plans that step together, one launch
+   per tile class per step over all plans' tiles (uneven sizes, each plan's own
+   step count).  t (may be NULL: the first member's tuning) gives the batch's
+   launch settings (graph_steps, max_blocks, parallel, stores); its block and
+   tile_x must equal every member's (their tiles were laid out at bind; zchunk
+   and merge of t are not used).  Stepping a batch advances every member;
+   members must stay alive.  Creation allocates the batch's launch tables on the
+   device (hipMalloc; freed by destroy). */
+int fdtd_batch_create(fdtd_plan* const* plans, int32_t n, const fdtd_tuning* t, fdtd_batch** out);
+/* Replace a batch's members (same conditions as at creation; the batch keeps
+   its tuning) for continuous batching: requests join and leave between launches
+   without a new batch.  The device tables are rewritten in place and grow
+   (hipMalloc, once per new maximum) only when the new list needs more room; the
+   batch's captured graphs are dropped.  Synchronizes the stream first, since
+   launches already queued read the old tables.  A plan may belong to several
+   batches, but only one of them may step it at a time. */
+int fdtd_batch_set_members(fdtd_batch* b, fdtd_plan* const* plans, int32_t n, void* stream);
 int fdtd_batch_step(fdtd_batch* b, int64_t n, void* stream);
 void fdtd_batch_destroy(fdtd_batch* b);
 
-/* Time n steps of the bound plan (hipEvents recorded on the stream around the
+/* Measurement (no passage of the paper; it prints no performance figure).
+   Time n steps of the bound plan (hipEvents recorded on the stream around the
    launches; the plan's state advances).  Milliseconds in *ms. */
 int fdtd_time_steps(fdtd_plan* p, int64_t n, void* stream, double* ms);
 /* Same for a batch. */
 int fdtd_batch_time_steps(fdtd_batch* b, int64_t n, void* stream, double* ms);
+
+/* Autotuning: time ncand candidate tunings of plan p (bound or not; p itself is
+   not touched) on scratch plans with p's description and each candidate's
+   tuning, bound in turn to the caller's scratch arena (device memory, 256-byte
+   aligned, bytes long): warmup untimed steps, then steps timed ones on the
+   stream.  ms[q] = milliseconds per step, -1 for an invalid tuning, -2 if the
+   candidate needs more than bytes.  need (may be NULL) receives the largest
+   arena any candidate needs; with scratch NULL only need is computed.  Allocates
+   no device memory itself. */
+int fdtd_tune(const fdtd_plan* p, const fdtd_tuning* cand, int32_t ncand, int64_t warmup, int64_t steps,
+              void* scratch, size_t bytes, size_t* need, double* ms, void* stream);
 
 /* Kernel classes of a step: 0 plain tiles, 1 tiles touching z-CPML slabs only,
    2 tiles touching x or y slabs, 3-5 the same with gain cells; 6 is the
@@ -262,6 +334,9 @@ int fdtd_class_bytes(const fdtd_plan* p, double* bytes /* 7 */);
    and end timestamps); ms[c] = summed milliseconds and launches[c] = number of
    launches of class c (7 entries each, as above). */
 int fdtd_time_kernels(fdtd_plan* p, int64_t n, void* stream, double* ms, int64_t* launches);
+/* The same for a batch: the launches of its tile classes over all members (the
+   class bytes of a batch launch are the sum of its members' fdtd_class_bytes). */
+int fdtd_batch_time_kernels(fdtd_batch* b, int64_t n, void* stream, double* ms, int64_t* launches);
 
 #ifdef __cplusplus
 }

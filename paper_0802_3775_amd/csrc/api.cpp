@@ -142,7 +142,7 @@ struct fdtd_plan {
   std::vector<std::array<int, 4>> probes;
   std::vector<Flux> flux;
   int ke = 0;
-  fdtd_tuning tune{256, 4, 64, 0, 32, 1, 0};
+  fdtd_tuning tune{256, 4, 64, 0, 32, 1, 0, 0};
   // bound state
   bool bound = false;
   uint8_t* arena = nullptr;
@@ -185,6 +185,8 @@ struct fdtd_batch {
   std::vector<fd_dft_tile> dft;
   int maxnf = 0;
   void* dmem = nullptr;  // tile tables + desc pointer list (setup-time allocation)
+  size_t dcap = 0;       // bytes available at dmem
+  bool owns_dmem = false;  // dmem came from hipMalloc (freed by destroy)
   fd_tile* dtiles[FD_NCLASS] = {};
   fd_dft_tile* ddft = nullptr;
   fd_desc** ddescs = nullptr;
@@ -718,9 +720,12 @@ int fdtd_add_probe(fdtd_plan* p, int32_t comp, int32_t i, int32_t j, int32_t k, 
   return FDTD_OK;
 }
 
-int fdtd_add_flux_plane(fdtd_plan* p, int32_t k, const double* f, int32_t nf, int32_t decim, int32_t* id) {
+int fdtd_add_flux_plane(fdtd_plan* p, int32_t axis, int32_t k, const double* f, int32_t nf, int32_t decim,
+                        int32_t* id) {
   if (!p) return fail(FDTD_EINVAL, "null plan");
   if (p->bound) return fail(FDTD_ESTATE, "plan already bound");
+  if (axis < 0 || axis > 2) return fail(FDTD_EINVAL, "flux plane axis must be 0, 1 or 2");
+  if (axis != 2) return fail(FDTD_EUNSUPPORTED, "flux planes normal to z only (the output face of the crystal)");
   if (p->flux.size() >= FD_MAXFLUX) return fail(FDTD_EINVAL, "at most %d flux planes", FD_MAXFLUX);
   if (k < 0 || k >= p->g.nz || (k == 0 && p->g.bc[2] != FDTD_BC_PERIODIC))
     return fail(FDTD_EINVAL, "flux plane index out of range");
@@ -755,6 +760,7 @@ int fdtd_set_tuning(fdtd_plan* p, const fdtd_tuning* t) {
     return fail(FDTD_EINVAL, "tile_x %d with block %d: the tile's halo ring (2 (tile_x+2) + 2 block/tile_x cells) "
                 "exceeds block", t->tile_x, t->block);
   if (t->merge < 0 || t->merge > 2 || t->parallel < 0 || t->parallel > 1) return fail(FDTD_EINVAL, "bad merge/parallel");
+  if (t->stores < FDTD_STORES_AUTO || t->stores > FDTD_STORES_NONTEMPORAL) return fail(FDTD_EINVAL, "bad stores mode");
   p->tune = *t;
   return FDTD_OK;
 }
@@ -1126,7 +1132,9 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
     HIPCHK(hipMemcpyAsync(p->ddft, p->dft.data(), sizeof(fd_dft_tile) * p->dft.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
   p->step = 0;
-  p->ntst = step_state_bytes(p) > kNonTemporalBytes ? 1 : 0;
+  p->ntst = p->tune.stores == FDTD_STORES_NONTEMPORAL ? 1
+            : p->tune.stores == FDTD_STORES_ORDINARY ? 0
+            : (step_state_bytes(p) > kNonTemporalBytes ? 1 : 0);
   p->bound = true;
   return FDTD_OK;
 }
@@ -1514,36 +1522,110 @@ int fdtd_time_kernels(fdtd_plan* p, int64_t n, void* stream, double* ms, int64_t
   return FDTD_OK;
 }
 
+// ------------------------------------------------------------------- tuning
+
+namespace {
+
+// A fresh, unbound plan with p's description (grid, materials, geometry,
+// sources, probes, flux planes, energy interval) and the tuning t.
+fdtd_plan* clone_description(const fdtd_plan* p, const fdtd_tuning& t) {
+  fdtd_plan* c = new (std::nothrow) fdtd_plan();
+  if (!c) return nullptr;
+  c->g = p->g;
+  c->dx = p->dx;
+  c->dt = p->dt;
+  c->ncell = p->ncell;
+  c->mats = p->mats;
+  c->have_opal = p->have_opal;
+  c->opal = p->opal;
+  c->spheres = p->spheres;
+  c->map_given = p->map_given;
+  if (p->map_given) c->host_map = p->host_map;
+  c->sources = p->sources;
+  c->probes = p->probes;
+  c->flux = p->flux;
+  c->ke = p->ke;
+  c->tune = t;
+  return c;
+}
+
+}  // namespace
+
+int fdtd_tune(const fdtd_plan* p, const fdtd_tuning* cand, int32_t ncand, int64_t warmup, int64_t steps,
+              void* scratch, size_t bytes, size_t* need, double* ms, void* stream) {
+  if (!p || !cand || ncand < 1) return fail(FDTD_EINVAL, "need a plan and at least one candidate");
+  if (warmup < 0 || steps < 1 || warmup + steps > ((int64_t)1 << 31)) return fail(FDTD_EINVAL, "bad step counts");
+  if (scratch && (!ms || ((uintptr_t)scratch & 255) != 0))
+    return fail(FDTD_EINVAL, "timing needs ms[] and a 256-byte aligned scratch arena");
+  size_t most = 0;
+  for (int q = 0; q < ncand; ++q) {
+    std::unique_ptr<fdtd_plan, void (*)(fdtd_plan*)> c(clone_description(p, p->tune), fdtd_plan_destroy);
+    if (!c) return fail(FDTD_ENOMEM, "host allocation");
+    if (fdtd_set_tuning(c.get(), &cand[q]) != FDTD_OK) {  // not a valid tuning: skipped
+      if (ms) ms[q] = -1.0;
+      continue;
+    }
+    Layout L;
+    int r = compute_layout(c.get(), warmup + steps, L);
+    if (r) return r;
+    most = std::max(most, L.total);
+    if (!scratch) continue;
+    if (L.total > bytes) {
+      ms[q] = -2.0;
+      continue;
+    }
+    r = fdtd_bind_arena(c.get(), scratch, bytes, warmup + steps, stream);
+    if (r) return r;
+    r = plan_step(c.get(), warmup, (hipStream_t)stream);
+    if (r) return r;
+    double t = 0.0;
+    r = fdtd_time_steps(c.get(), steps, stream, &t);
+    if (r) return r;
+    ms[q] = t / (double)steps;
+  }
+  if (need) *need = most;
+  return FDTD_OK;
+}
+
 // ------------------------------------------------------------------ batches
 
-int fdtd_batch_create(fdtd_plan* const* plans, int32_t n, fdtd_batch** out) {
-  if (!plans || !out || n < 1) return fail(FDTD_EINVAL, "need at least one plan");
-  *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+// Checks a member list against the batch tuning bt; *gm receives the gain model
+// the members with gain share (0: none has gain).
+int batch_check(fdtd_plan* const* plans, int32_t n, const fdtd_tuning& bt, int* gm) {
+  if (!plans || n < 1) return fail(FDTD_EINVAL, "need at least one plan");
   for (int q = 0; q < n; ++q)
     if (!plans[q] || !plans[q]->bound) return fail(FDTD_ESTATE, "batch member %d not bound", q);
-  const int block = plans[0]->tune.block;
+  if (bt.graph_steps < 0 || bt.max_blocks < 0 || bt.parallel < 0 || bt.parallel > 1 ||
+      bt.stores < FDTD_STORES_AUTO || bt.stores > FDTD_STORES_NONTEMPORAL)
+    return fail(FDTD_EINVAL, "bad batch tuning");
   for (int q = 0; q < n; ++q) {
-    if (plans[q]->tune.block != block || plans[q]->tune.tile_x != plans[0]->tune.tile_x)
-      return fail(FDTD_EINVAL, "batch members must share the block size and tile width");
+    if (plans[q]->tune.block != bt.block || plans[q]->tune.tile_x != bt.tile_x)
+      return fail(FDTD_EINVAL, "batch members must share the block size and tile width of the batch tuning");
     for (int r = 0; r < q; ++r)
       if (plans[r] == plans[q]) return fail(FDTD_EINVAL, "plan listed twice");
   }
-  int gm = 0;
+  *gm = 0;
   for (int q = 0; q < n; ++q) {
-    if (plans[q]->gm && gm && plans[q]->gm != gm)
+    if (plans[q]->gm && *gm && plans[q]->gm != *gm)
       return fail(FDTD_EUNSUPPORTED, "batch members with gain must share the gain model");
-    if (plans[q]->gm) gm = plans[q]->gm;
+    if (plans[q]->gm) *gm = plans[q]->gm;
   }
-  fdtd_batch* b = new (std::nothrow) fdtd_batch();
-  if (!b) return fail(FDTD_ENOMEM, "host allocation");
+  return FDTD_OK;
+}
+
+// Host side of a batch: members' tile lists concatenated per class, their XCD
+// partitions and the DFT work units.
+void batch_layout(fdtd_batch* b, fdtd_plan* const* plans, int32_t n, int gm) {
   b->plans.assign(plans, plans + n);
-  b->block = block;
   b->gm = gm ? gm : 1;
-  b->tile_x = plans[0]->tune.tile_x;
-  b->parallel = plans[0]->tune.parallel;
-  b->max_blocks = plans[0]->tune.max_blocks;
-  b->graph_steps = plans[0]->tune.graph_steps;
+  b->maxnf = 0;
+  b->dft.clear();
   std::vector<double> bcost[FD_NCLASS];
+  for (int c = 0; c < FD_NCLASS; ++c) b->tiles[c].clear();
   for (fdtd_plan* p : b->plans) {
     for (int c = 0; c < FD_NCLASS; ++c) {
       b->tiles[c].insert(b->tiles[c].end(), p->tiles[c].begin(), p->tiles[c].end());
@@ -1553,56 +1635,125 @@ int fdtd_batch_create(fdtd_plan* const* plans, int32_t n, fdtd_batch** out) {
     b->maxnf = std::max(b->maxnf, p->maxnf);
   }
   for (int c = 0; c < FD_NCLASS; ++c) b->part[c] = xcd_partition(bcost[c], &b->pgrid[c]);
-  // Batches keep ordinary stores: over a 64-member ensemble of 1.9 GB the
-  // non-temporal form measured about 10% slower, while a single 2 GB grid gains.
-  b->ntst = 0;
+}
+
+// Device bytes of the batch's launch tables (tile lists, DFT units, descriptor
+// pointers) and their offsets.
+size_t batch_table_bytes(const fdtd_batch* b, size_t off_t[FD_NCLASS], size_t* off_d, size_t* off_p) {
   size_t bytes = 0;
-  size_t off_t[FD_NCLASS];
   for (int c = 0; c < FD_NCLASS; ++c) {
     off_t[c] = bytes;
     bytes = align256(bytes + sizeof(fd_tile) * b->tiles[c].size());
   }
-  const size_t off_d = bytes;
+  *off_d = bytes;
   bytes = align256(bytes + sizeof(fd_dft_tile) * std::max<size_t>(b->dft.size(), 1));
-  const size_t off_p = bytes;
-  bytes = align256(bytes + sizeof(fd_desc*) * (size_t)n);
-  // Setup-time allocation of the batch's launch tables (small; freed by destroy).
-  hipError_t e = hipMalloc(&b->dmem, bytes);
-  if (e != hipSuccess) {
-    delete b;
-    return fail(FDTD_EHIP, "hipMalloc(batch tables): %s", hipGetErrorString(e));
-  }
-  uint8_t* base = (uint8_t*)b->dmem;
-  std::vector<fd_desc*> dl;
-  for (fdtd_plan* p : b->plans) dl.push_back(p->ddesc);
-  e = hipSuccess;
-  for (int c = 0; c < FD_NCLASS && e == hipSuccess; ++c) {
-    b->dtiles[c] = (fd_tile*)(base + off_t[c]);
-    if (!b->tiles[c].empty())
-      e = hipMemcpy(b->dtiles[c], b->tiles[c].data(), sizeof(fd_tile) * b->tiles[c].size(), hipMemcpyHostToDevice);
-  }
-  b->ddft = (fd_dft_tile*)(base + off_d);
-  if (e == hipSuccess && !b->dft.empty())
-    e = hipMemcpy(b->ddft, b->dft.data(), sizeof(fd_dft_tile) * b->dft.size(), hipMemcpyHostToDevice);
-  b->ddescs = (fd_desc**)(base + off_p);
-  if (e == hipSuccess) e = hipMemcpy(b->ddescs, dl.data(), sizeof(fd_desc*) * dl.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    (void)hipFree(b->dmem);
-    delete b;
-    return fail(FDTD_EHIP, "batch table upload: %s", hipGetErrorString(e));
-  }
-  *out = b;
-  return FDTD_OK;
+  *off_p = bytes;
+  return align256(bytes + sizeof(fd_desc*) * b->plans.size());
 }
 
-void fdtd_batch_destroy(fdtd_batch* b) {
-  if (!b) return;
+void batch_drop_graphs(fdtd_batch* b) {
   for (auto& kv : b->graphs) {
     if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
     if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
   }
+  b->graphs.clear();
+}
+
+// Writes the launch tables of b's members to b->dmem (b->dcap bytes, the
+// caller has checked they fit) and points the launch arguments at them.
+int batch_upload(fdtd_batch* b) {
+  size_t off_t[FD_NCLASS], off_d, off_p;
+  (void)batch_table_bytes(b, off_t, &off_d, &off_p);
+  uint8_t* base = (uint8_t*)b->dmem;
+  std::vector<fd_desc*> dl;
+  for (fdtd_plan* p : b->plans) dl.push_back(p->ddesc);
+  for (int c = 0; c < FD_NCLASS; ++c) {
+    b->dtiles[c] = (fd_tile*)(base + off_t[c]);
+    if (!b->tiles[c].empty())
+      HIPCHK(hipMemcpy(b->dtiles[c], b->tiles[c].data(), sizeof(fd_tile) * b->tiles[c].size(), hipMemcpyHostToDevice));
+  }
+  b->ddft = (fd_dft_tile*)(base + off_d);
+  if (!b->dft.empty())
+    HIPCHK(hipMemcpy(b->ddft, b->dft.data(), sizeof(fd_dft_tile) * b->dft.size(), hipMemcpyHostToDevice));
+  b->ddescs = (fd_desc**)(base + off_p);
+  HIPCHK(hipMemcpy(b->ddescs, dl.data(), sizeof(fd_desc*) * dl.size(), hipMemcpyHostToDevice));
+  return FDTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fdtd_batch_create(fdtd_plan* const* plans, int32_t n, const fdtd_tuning* t, fdtd_batch** out) {
+  if (!plans || !out || n < 1) return fail(FDTD_EINVAL, "need at least one plan");
+  *out = nullptr;
+  if (!plans[0]) return fail(FDTD_ESTATE, "batch member 0 not bound");
+  const fdtd_tuning bt = t ? *t : plans[0]->tune;
+  int gm = 0;
+  if (int r = batch_check(plans, n, bt, &gm)) return r;
+  std::unique_ptr<fdtd_batch> b(new (std::nothrow) fdtd_batch());
+  if (!b) return fail(FDTD_ENOMEM, "host allocation");
+  b->block = bt.block;
+  b->tile_x = bt.tile_x;
+  b->parallel = bt.parallel;
+  b->max_blocks = bt.max_blocks;
+  b->graph_steps = bt.graph_steps;
+  // Batches keep ordinary stores unless asked: over a 64-member ensemble of
+  // 1.9 GB the non-temporal form measured about 10% slower, while a single 2 GB
+  // grid gains.
+  b->ntst = bt.stores == FDTD_STORES_NONTEMPORAL ? 1 : 0;
+  batch_layout(b.get(), plans, n, gm);
+  size_t off_t[FD_NCLASS], off_d, off_p;
+  const size_t bytes = batch_table_bytes(b.get(), off_t, &off_d, &off_p);
+  // Set-up allocation of the batch's launch tables (small; grown by
+  // fdtd_batch_set_members only when a member list needs more; freed by destroy).
+  HIPCHK(hipMalloc(&b->dmem, bytes));
+  b->dcap = bytes;
+  b->owns_dmem = true;
+  if (int r = batch_upload(b.get())) {
+    (void)hipFree(b->dmem);
+    b->dmem = nullptr;
+    return r;
+  }
+  *out = b.release();
+  return FDTD_OK;
+}
+
+int fdtd_batch_set_members(fdtd_batch* b, fdtd_plan* const* plans, int32_t n, void* stream) {
+  if (!b) return fail(FDTD_EINVAL, "null batch");
+  fdtd_tuning bt{};
+  bt.block = b->block;
+  bt.tile_x = b->tile_x;
+  bt.graph_steps = b->graph_steps;
+  bt.max_blocks = b->max_blocks;
+  bt.parallel = b->parallel;
+  bt.stores = b->ntst ? FDTD_STORES_NONTEMPORAL : FDTD_STORES_ORDINARY;
+  int gm = 0;
+  if (int r = batch_check(plans, n, bt, &gm)) return r;
+  // the launches already queued read the current tables: wait for them
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  fdtd_batch next;
+  batch_layout(&next, plans, n, gm);
+  size_t off_t[FD_NCLASS], off_d, off_p;
+  const size_t bytes = batch_table_bytes(&next, off_t, &off_d, &off_p);
+  if (bytes > b->dcap) {
+    if (!b->owns_dmem) return fail(FDTD_ENOMEM, "member tables of %zu bytes exceed the %zu available", bytes, b->dcap);
+    void* grown = nullptr;
+    HIPCHK(hipMalloc(&grown, bytes + bytes / 2));
+    (void)hipFree(b->dmem);
+    b->dmem = grown;
+    b->dcap = bytes + bytes / 2;
+  }
+  batch_drop_graphs(b);
+  batch_layout(b, plans, n, gm);
+  return batch_upload(b);
+}
+
+void fdtd_batch_destroy(fdtd_batch* b) {
+  if (!b) return;
+  batch_drop_graphs(b);
   if (b->cap) (void)hipStreamDestroy(b->cap);
-  if (b->dmem) (void)hipFree(b->dmem);
+  if (b->dmem && b->owns_dmem) (void)hipFree(b->dmem);
   delete b;
 }
 
@@ -1671,6 +1822,70 @@ static int batch_step(fdtd_batch* b, int64_t n, hipStream_t st) {
 int fdtd_batch_step(fdtd_batch* b, int64_t n, void* stream) {
   if (!b) return fail(FDTD_EINVAL, "null batch");
   return batch_step(b, n, (hipStream_t)stream);
+}
+
+int fdtd_batch_time_kernels(fdtd_batch* b, int64_t n, void* stream, double* ms, int64_t* launches) {
+  if (!b || !ms || !launches) return fail(FDTD_EINVAL, "null argument");
+  if (n < 0) return fail(FDTD_EINVAL, "negative step count");
+  for (fdtd_plan* p : b->plans)
+    if (p->step + n > p->max_steps) return fail(FDTD_ESTATE, "a member would exceed its max_steps");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<std::array<hipEvent_t, 2>> ev;
+  std::vector<int> cls;
+  auto cleanup = [&]() {
+    for (auto& e : ev) {
+      (void)hipEventDestroy(e[0]);
+      (void)hipEventDestroy(e[1]);
+    }
+  };
+  auto pair = [&](int c, hipEvent_t* a, hipEvent_t* z) -> int {
+    std::array<hipEvent_t, 2> e{};
+    HIPCHK(hipEventCreate(&e[0]));
+    HIPCHK(hipEventCreate(&e[1]));
+    ev.push_back(e);
+    cls.push_back(c);
+    *a = e[0];
+    *z = e[1];
+    return FDTD_OK;
+  };
+  for (int64_t s = 0; s < n; ++s) {
+    for (int c = 0; c < FD_NCLASS; ++c) {
+      const int nt = (int)b->tiles[c].size();
+      if (nt == 0) continue;
+      const int grid = b->max_blocks > 0 ? std::min(nt, b->max_blocks) : b->pgrid[c];
+      const fd_xcd* pc = b->max_blocks > 0 ? nullptr : &b->part[c];
+      hipEvent_t a, z;
+      if (int r = pair(c, &a, &z)) { cleanup(); return r; }
+      const hipError_t e = fd_launch_step(c, b->dtiles[c], nt, b->tile_x, b->block, grid, (int)s, pc, b->ntst, b->gm,
+                                          st, a, z);
+      if (e != hipSuccess) { cleanup(); return fail(FDTD_EHIP, "batch_time_kernels: %s", hipGetErrorString(e)); }
+    }
+    if (batch_dft_due(b, s) && !b->dft.empty()) {
+      hipEvent_t a, z;
+      if (int r = pair(FD_NCLASS, &a, &z)) { cleanup(); return r; }
+      const hipError_t e = fd_launch_dft(b->ddft, (int)b->dft.size(), (int)s, st, a, z);
+      if (e != hipSuccess) { cleanup(); return fail(FDTD_EHIP, "batch_time_kernels: %s", hipGetErrorString(e)); }
+    }
+  }
+  hipError_t e = fd_launch_advance(b->ddescs, (int)b->plans.size(), n, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(FDTD_EHIP, "batch_time_kernels: %s", hipGetErrorString(e));
+  }
+  for (fdtd_plan* p : b->plans) p->step += n;
+  for (int c = 0; c <= FD_NCLASS; ++c) {
+    ms[c] = 0.0;
+    launches[c] = 0;
+  }
+  for (size_t q = 0; q < ev.size(); ++q) {
+    float f = 0.0f;
+    (void)hipEventElapsedTime(&f, ev[q][0], ev[q][1]);
+    ms[cls[q]] += f;
+    launches[cls[q]] += 1;
+  }
+  cleanup();
+  return FDTD_OK;
 }
 
 int fdtd_batch_time_steps(fdtd_batch* b, int64_t n, void* stream, double* ms) {

@@ -59,7 +59,18 @@ class OpalDesc(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("zchunk", C.c_int32), ("graph_steps", C.c_int32),
                 ("max_blocks", C.c_int32), ("tile_x", C.c_int32), ("merge", C.c_int32),
-                ("parallel", C.c_int32)]
+                ("parallel", C.c_int32), ("stores", C.c_int32)]
+
+
+STORES = {"auto": 0, "ordinary": 1, "nontemporal": 2}
+TUNING_KEYS = ("block", "zchunk", "graph_steps", "max_blocks", "tile_x", "merge", "parallel", "stores")
+
+
+def make_tuning(t):
+    """Tuning struct from a tuning dict (missing keys take the defaults)."""
+    d = dict(default_tuning())
+    d.update(t or {})
+    return Tuning(*[int(d[k]) for k in TUNING_KEYS])
 
 
 # Every exported symbol of include/fdtd.h with its ctypes signature.
@@ -77,7 +88,7 @@ SIGNATURES = {
     "fdtd_get_material_map": ([VP, P(C.c_uint8), VP], C.c_int),
     "fdtd_add_source": ([VP, P(SourceDesc), P(C.c_int32)], C.c_int),
     "fdtd_add_probe": ([VP, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P(C.c_int32)], C.c_int),
-    "fdtd_add_flux_plane": ([VP, C.c_int32, P(C.c_double), C.c_int32, C.c_int32, P(C.c_int32)], C.c_int),
+    "fdtd_add_flux_plane": ([VP, C.c_int32, C.c_int32, P(C.c_double), C.c_int32, C.c_int32, P(C.c_int32)], C.c_int),
     "fdtd_set_energy_interval": ([VP, C.c_int32], C.c_int),
     "fdtd_set_tuning": ([VP, P(Tuning)], C.c_int),
     "fdtd_get_tuning": ([VP, P(Tuning)], C.c_int),
@@ -95,14 +106,18 @@ SIGNATURES = {
     "fdtd_read_polarization": ([VP, P(C.c_float), VP], C.c_int),
     "fdtd_read_density": ([VP, P(C.c_float), VP], C.c_int),
     "fdtd_read_energy": ([VP, P(C.c_double), P(C.c_int64), VP], C.c_int),
-    "fdtd_batch_create": ([P(VP), C.c_int32, P(VP)], C.c_int),
+    "fdtd_batch_create": ([P(VP), C.c_int32, P(Tuning), P(VP)], C.c_int),
     "fdtd_batch_step": ([VP, C.c_int64, VP], C.c_int),
+    "fdtd_batch_set_members": ([VP, P(VP), C.c_int32, VP], C.c_int),
     "fdtd_batch_destroy": ([VP], None),
     "fdtd_time_steps": ([VP, C.c_int64, VP, P(C.c_double)], C.c_int),
     "fdtd_batch_time_steps": ([VP, C.c_int64, VP, P(C.c_double)], C.c_int),
     "fdtd_class_cells": ([VP, P(C.c_int64)], C.c_int),
     "fdtd_class_bytes": ([VP, P(C.c_double)], C.c_int),
     "fdtd_time_kernels": ([VP, C.c_int64, VP, P(C.c_double), P(C.c_int64)], C.c_int),
+    "fdtd_batch_time_kernels": ([VP, C.c_int64, VP, P(C.c_double), P(C.c_int64)], C.c_int),
+    "fdtd_tune": ([VP, P(Tuning), C.c_int32, C.c_int64, C.c_int64, VP, C.c_size_t, P(C.c_size_t), P(C.c_double),
+                   VP], C.c_int),
 }
 
 _lib = None
@@ -172,7 +187,7 @@ def _material(m):
 
 def default_tuning(cfg=None):
     return {"block": 256, "zchunk": 4, "graph_steps": 64, "max_blocks": 0, "tile_x": 32, "merge": 1,
-            "parallel": 0}
+            "parallel": 0, "stores": 0}
 
 
 class Plan:
@@ -221,23 +236,20 @@ class Plan:
         self.nf = []
         for f in cfg.get("flux", []):
             fr = np.ascontiguousarray(f["freqs"], dtype=np.float64)
-            _check(lib().fdtd_add_flux_plane(self.h, int(f["k"]), _ptr(fr, C.c_double), len(fr),
-                                             int(f.get("decim", 1)), None))
+            _check(lib().fdtd_add_flux_plane(self.h, int(f.get("axis", 2)), int(f["k"]), _ptr(fr, C.c_double),
+                                             len(fr), int(f.get("decim", 1)), None))
             self.nf.append(len(fr))
         if cfg.get("energy_interval"):
             _check(lib().fdtd_set_energy_interval(self.h, int(cfg["energy_interval"])))
         t = dict(default_tuning(cfg))
         t.update(tuning or {})
-        tu = Tuning(t["block"], t["zchunk"], t["graph_steps"], t["max_blocks"], t["tile_x"], t["merge"],
-                    t["parallel"])
+        tu = make_tuning(t)
         _check(lib().fdtd_set_tuning(self.h, C.byref(tu)))
         self.tuning = t
         self.max_steps = int(max_steps if max_steps is not None else cfg.get("steps", 0))
         self.arena = None
         if bind:
             self.bind(stream)
-        for comp, a in (cfg.get("init_fields") or {}).items():
-            self.write_field(comp, a)
 
     def required_bytes(self):
         b = C.c_size_t()
@@ -251,6 +263,8 @@ class Plan:
         base = self.arena.data_ptr()
         aligned = (base + 255) & ~255
         _check(lib().fdtd_bind_arena(self.h, C.c_void_p(aligned), nbytes, self.max_steps, _stream(stream)))
+        for comp, a in (self.cfg.get("init_fields") or {}).items():
+            self.write_field(comp, a, stream)
 
     def close(self):
         if getattr(self, "h", None) and self.h.value:
@@ -263,6 +277,26 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def tune(self, candidates, steps, warmup=4, stream=None):
+        """Milliseconds per step of each candidate tuning (dicts), timed by
+        fdtd_tune on scratch plans of this plan's description bound to one torch
+        scratch arena; None for an invalid candidate."""
+        import torch
+        cand = (Tuning * len(candidates))(*[make_tuning(t) for t in candidates])
+        need = C.c_size_t()
+        _check(lib().fdtd_tune(self.h, cand, len(candidates), int(warmup), int(steps), None, 0, C.byref(need),
+                               None, _stream(stream)))
+        scratch = torch.empty(need.value + 256, dtype=torch.uint8, device="cuda")
+        base = (scratch.data_ptr() + 255) & ~255
+        ms = np.zeros(len(candidates), dtype=np.float64)
+        try:
+            _check(lib().fdtd_tune(self.h, cand, len(candidates), int(warmup), int(steps), C.c_void_p(base),
+                                   need.value, None, _ptr(ms, C.c_double), _stream(stream)))
+        finally:
+            torch.cuda.synchronize()
+            del scratch
+        return [float(v) if v >= 0 else None for v in ms]
 
     # -------------------------------------------------------------- stepping
     def step(self, n, stream=None):
@@ -367,13 +401,28 @@ class Plan:
 
 
 class Batch:
-    """Bound plans stepped together: one launch per tile class per step."""
+    """Bound plans stepped together: one launch per tile class per step.
+    tuning: the batch's launch settings (graph_steps, max_blocks, parallel,
+    stores; block and tile_x must be the members'); None takes the first
+    member's."""
 
-    def __init__(self, plans):
+    def __init__(self, plans, tuning=None):
         self.plans = list(plans)
         arr = (C.c_void_p * len(self.plans))(*[p.h.value for p in self.plans])
         self.h = C.c_void_p()
-        _check(lib().fdtd_batch_create(arr, len(self.plans), C.byref(self.h)))
+        t = None
+        if tuning is not None:
+            base = dict(self.plans[0].tuning)
+            base.update(tuning)
+            t = C.byref(make_tuning(base))
+        _check(lib().fdtd_batch_create(arr, len(self.plans), t, C.byref(self.h)))
+
+    def set_members(self, plans, stream=None):
+        """Replace the members in place (tables rewritten, grown only if needed)."""
+        plans = list(plans)
+        arr = (C.c_void_p * len(plans))(*[p.h.value for p in plans])
+        _check(lib().fdtd_batch_set_members(self.h, arr, len(plans), _stream(stream)))
+        self.plans = plans
 
     def step(self, n, stream=None):
         _check(lib().fdtd_batch_step(self.h, int(n), _stream(stream)))
@@ -382,6 +431,21 @@ class Batch:
         ms = C.c_double()
         _check(lib().fdtd_batch_time_steps(self.h, int(n), _stream(stream), C.byref(ms)))
         return ms.value
+
+    def time_kernels(self, n, stream=None):
+        """Per kernel class: (total ms, launches) over n eager batch steps."""
+        ms = np.zeros(7, dtype=np.float64)
+        cnt = np.zeros(7, dtype=np.int64)
+        _check(lib().fdtd_batch_time_kernels(self.h, int(n), _stream(stream), _ptr(ms, C.c_double),
+                                             _ptr(cnt, C.c_int64)))
+        return ms, cnt
+
+    def class_bytes(self):
+        """Algorithmic bytes of one launch of each class over all members."""
+        return np.sum([p.class_bytes() for p in self.plans], axis=0)
+
+    def class_cells(self):
+        return np.sum([p.class_cells() for p in self.plans], axis=0)
 
     def close(self):
         if getattr(self, "h", None) and self.h.value:

@@ -6,16 +6,16 @@ z-planes each tile marches, the number of steps captured in one hipGraph, an
 optional cap on resident workgroups, how tile classes are folded into launches
 and whether a step's launches are parallel graph branches.  Fields are bit-identical for every tuning (each cell's
 arithmetic does not depend on the tiling), so the tuner is free to pick the
-fastest.  It times candidate tunings on a scratch plan of the same shape
-(same grid, materials, sources and diagnostics; its own arena), keeps the
-fastest, and caches the choice per shape bin in a JSON file.
+fastest.  It times candidate tunings through the library's fdtd_tune (scratch plans of
+the same description bound in turn to one scratch arena), keeps the fastest,
+and caches the choice per shape bin in a JSON file.
 """
 import itertools
 import json
 import os
 import time
 
-CACHE_VERSION = 5
+CACHE_VERSION = 6
 
 
 def _cache_path():
@@ -72,17 +72,20 @@ def _save_cache(cache):
         pass
 
 
-def _time_candidate(cfg, tune, steps, warm):
-    import torch
+def _time_candidates(cfg, tunes, steps, warm):
+    """Milliseconds per step of each tuning, timed by the library's fdtd_tune on
+    scratch plans of cfg's description (one scratch arena for all); infinity for
+    a tuning the library rejects."""
     from . import fdtd
-    plan = fdtd.Plan(cfg, max_steps=warm + steps, tuning=tune)
+    plan = fdtd.Plan(cfg, max_steps=warm + steps, bind=False)
     try:
-        plan.step(warm)
-        torch.cuda.synchronize()
-        ms = plan.time_steps(steps)
-        return ms / steps
+        return [float("inf") if ms is None else ms for ms in plan.tune(tunes, steps, warmup=warm)]
     finally:
         plan.close()
+
+
+def _time_candidate(cfg, tune, steps, warm):
+    return _time_candidates(cfg, [tune], steps, warm)[0]
 
 
 def autotune(cfg, budget_s=20.0, quick=False, use_cache=True, graph_steps=(50, 200), verbose=False):
@@ -97,16 +100,17 @@ def autotune(cfg, budget_s=20.0, quick=False, use_cache=True, graph_steps=(50, 2
     t_end = time.perf_counter() + budget_s
     best, best_ms = None, float("inf")
     results = []
-    for cand in candidates(cfg, quick=quick):
+    cands = [dict(c, graph_steps=min(graph_steps)) for c in candidates(cfg, quick=quick)]
+    for q0 in range(0, len(cands), 6):  # a few candidates per library call, budget checked between
         if time.perf_counter() > t_end and best is not None:
             break
-        tune = dict(cand, graph_steps=min(graph_steps))
-        ms = _time_candidate(dict(cfg, steps=steps + 4), tune, steps, 4)
-        results.append((ms, tune))
-        if verbose:
-            print("tune %s: %.2f us/step" % (tune, ms * 1e3), flush=True)
-        if ms < best_ms:
-            best, best_ms = tune, ms
+        group = cands[q0:q0 + 6]
+        for tune, ms in zip(group, _time_candidates(dict(cfg, steps=steps + 4), group, steps, 4)):
+            results.append((ms, tune))
+            if verbose:
+                print("tune %s: %.2f us/step" % (tune, ms * 1e3), flush=True)
+            if ms < best_ms:
+                best, best_ms = tune, ms
     # launch grouping: classes folded into fewer launches, or launches as
     # parallel graph branches
     base = dict(best)

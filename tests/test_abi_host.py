@@ -62,17 +62,47 @@ def test_add_calls_reject_out_of_range():
     assert L.fdtd_add_probe(h, 0, 99, 0, 0, None) == -1
     assert L.fdtd_add_probe(h, 7, 0, 0, 0, None) == -1
     fr = np.array([0.8])
-    assert L.fdtd_add_flux_plane(h, 0, F._ptr(fr, C.c_double), 1, 1, None) == -1  # k=0 on a PEC axis
-    assert L.fdtd_add_flux_plane(h, 5, F._ptr(fr, C.c_double), 1, 0, None) == -1  # decim 0
+    assert L.fdtd_add_flux_plane(h, 2, 0, F._ptr(fr, C.c_double), 1, 1, None) == -1  # k=0 on a PEC axis
+    assert L.fdtd_add_flux_plane(h, 2, 5, F._ptr(fr, C.c_double), 1, 0, None) == -1  # decim 0
+    assert L.fdtd_add_flux_plane(h, 3, 5, F._ptr(fr, C.c_double), 1, 1, None) == -1  # no such axis
+    assert L.fdtd_add_flux_plane(h, 0, 5, F._ptr(fr, C.c_double), 1, 1, None) == -6  # x-normal: unsupported
+    assert b"normal to z" in L.fdtd_last_error()
+    assert L.fdtd_add_flux_plane(h, 2, 5, F._ptr(fr, C.c_double), 1, 1, None) == 0
     t = F.Tuning(100, 8, 0, 0)
     assert L.fdtd_set_tuning(h, C.byref(t)) == -1  # block not a multiple of 64
     # the tile's halo ring must fit one cell per thread: 2 (tx+2) + 2 block/tx <= block
     for block, tx, ok in ((64, 16, True), (64, 32, False), (128, 32, True), (128, 64, False), (256, 64, True)):
         t = F.Tuning(block, 4, 0, 0, tx, 1, 0)
         assert (L.fdtd_set_tuning(h, C.byref(t)) == 0) == ok, (block, tx)
+    t = F.make_tuning({"stores": 3})
+    assert L.fdtd_set_tuning(h, C.byref(t)) == -1  # no such store mode
     size = C.c_size_t()
+    assert L.fdtd_set_tuning(h, C.byref(F.make_tuning({}))) == 0
     assert L.fdtd_required_bytes(h, 100, C.byref(size)) == 0 and size.value > 0
     L.fdtd_plan_destroy(h)
+
+
+def test_tune_sizes_its_scratch_arena_on_the_host():
+    """fdtd_tune with no scratch arena only sizes it: the largest arena any valid
+    candidate needs for warmup + steps steps, equal to fdtd_required_bytes of a
+    plan with that candidate; invalid candidates are skipped, the plan untouched."""
+    cfg = W.slab(res=8, cells=(1, 1, 2), steps=10, nf=4)
+    plan = F.Plan(cfg, max_steps=10, bind=False)
+    L = F.lib()
+    tunes = [{"tile_x": 16, "block": 128, "zchunk": 1}, {"tile_x": 64, "block": 128}, {"zchunk": 8}]
+    arr = (F.Tuning * 3)(*[F.make_tuning(t) for t in tunes])
+    need = C.c_size_t()
+    assert L.fdtd_tune(plan.h, arr, 3, 2, 6, None, 0, C.byref(need), None, None) == 0
+    sizes = []
+    for t in (tunes[0], tunes[2]):
+        p2 = F.Plan(cfg, max_steps=8, tuning=t, bind=False)
+        sizes.append(p2.required_bytes())
+        p2.close()
+    assert need.value == max(sizes)
+    assert plan.required_bytes() > 0 and plan.tuning == F.default_tuning()
+    assert L.fdtd_tune(plan.h, arr, 0, 2, 6, None, 0, C.byref(need), None, None) == -1
+    assert L.fdtd_tune(plan.h, arr, 3, 2, 0, None, 0, C.byref(need), None, None) == -1
+    plan.close()
 
 
 @pytest.mark.parametrize("maker", [
