@@ -112,9 +112,17 @@ def test_density_lasing_box_parity(merge):
     qo, fo = emission_peak_bin(orc.probe(0), orc.dt, onset)
     _say("emission peak", fg, fo)
     assert abs(qg - qo) <= 1
-    pops = plan.populations().astype(np.float64)
-    assert np.max(np.abs(pops[:, gain].sum(axis=0) - 1.0)) <= 1e-6
-    assert np.all(pops[:, gain] >= -1e-4)
+    # rho_00 is not stored on the GPU (1 - the upper populations, so the trace is
+    # 1 by construction); the oracle propagates the full 4x4 matrix, so its rho_00
+    # is evolved separately: the changes of all four populations agree
+    pops = plan.populations().astype(np.float64)[:, gain]
+    pops[0] = 1.0 - pops[1:].sum(axis=0)
+    opops = orc.populations()[:, gain]
+    init = np.array(cfg["materials"][1]["n_init"])[:, None]
+    dg, do = pops - init, opops - init
+    _say("populations: max change %.3e, max |dN_gpu - dN_oracle| %.3e" % (np.abs(do).max(), np.abs(dg - do).max()))
+    assert np.abs(dg - do).max() <= 1e-3 * np.abs(do).max()
+    assert np.all(pops >= -1e-4)
     assert plan.energy()[-1] > 10 * plan.energy()[1]  # it lases
     plan.close()
 

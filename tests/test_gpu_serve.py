@@ -75,3 +75,28 @@ def test_budget_forces_queueing():
     # never more than one large request resident at a time
     admits = [t for ev, _, t in srv.log if ev == "admit"]
     assert len(admits) == 3
+
+
+def test_served_requests_match_the_oracle():
+    """Requests served in the mix (a linear slab and a Lorentz lasing box joining
+    while others run) against the oracle's runs of the same request
+    configurations: probe, T(t), spectra and energy."""
+    from gpu_common import rel_l2, run_oracle
+    from paper_0802_3775_amd import fdtd
+    from paper_0802_3775_amd.serve import GpuBackend, Server, request_config
+    backend = GpuBackend(fdtd.default_tuning())
+    srv = Server(backend, budget_bytes=8 << 30, chunk=200)
+    reqs = _trace()
+    srv.run(reqs)
+    assert not srv.failed, srv.failed
+    for rid, tol in ((3, 1e-4), (4, 1e-3)):
+        req = reqs[rid]
+        orc = run_oracle(request_config(req), req["steps"])
+        got = srv.results[rid]
+        perr = rel_l2(got["probe"][0], orc.probe(0))
+        werr = rel_l2(got["energy"], orc.energy())
+        print("request", rid, req["kind"], "probe", perr, "energy", werr, flush=True)
+        assert perr <= tol and werr <= tol
+        for f, (T, S) in enumerate(got.get("flux", [])):
+            To, So = orc.flux(f)
+            assert rel_l2(T, To) <= 1e-3 and rel_l2(S, So) <= 1e-3
