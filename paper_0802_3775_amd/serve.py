@@ -3,13 +3,21 @@
 Requests (linear transmission runs or lasing runs of given size, resolution,
 disorder and seed) arrive over time.  The server admits them in arrival order
 while their HBM footprint fits the budget, keeps every admitted request's
-fields resident in its own device arena, and steps all admitted requests
-together in batched launches of `chunk` steps.  At every launch boundary it
+fields resident in its own device arena, and steps admitted requests together
+in batched launches of up to `chunk` steps.  At every launch boundary it
 retires finished requests (results copied to the host), frees their arenas,
 and admits waiting requests into the freed memory, so new work joins while
 older work is still running.  Each request keeps its own step counter, source
 timing and DFT phase, so its result is bit-identical to a run of the same
 request alone.
+
+Which admitted requests a launch steps: with policy "srpt" (the default), the
+group whose remaining work (cells x remaining steps, lasing cells weighted by
+their higher per-cell cost) is within `group_factor` of the smallest -- the
+shortest-remaining-work-first order, which minimises mean latency on one
+device, with similar requests batched together; with policy "all", every
+admitted request.  Requests outside the group stay resident and continue when
+they become the smallest.
 
 The scheduling policy (Server) is independent of the device: a Backend does
 the work.  GpuBackend drives libfdtd; tests drive the same policy with a host
@@ -19,6 +27,15 @@ import math
 import time
 
 from . import workloads as W
+
+# Launch shape of served requests: one block size and tile width for all (batch
+# members share them); CPML on all faces (lasing boxes) folds every tile into
+# the all-axes kernel, the z-CPML slabs keep interior tiles in the lighter one.
+SERVE_TUNING = {"block": 256, "tile_x": 32, "zchunk": 8, "graph_steps": 50, "max_blocks": 0, "merge": 1,
+                "parallel": 0, "stores": 0}
+SERVE_TUNING_LASING = dict(SERVE_TUNING, zchunk=4, merge=2)
+# per-cell cost of a lasing request relative to a linear one (gain state, CPML on all faces)
+LASING_COST = 3.0
 
 
 def request_config(req):
@@ -38,28 +55,42 @@ def request_config(req):
     return cfg
 
 
+def request_cells(req):
+    """Cells of the request's grid (crystal, margins and CPML)."""
+    n = request_config(dict(req, steps=1))["grid"]["n"]
+    return n[0] * n[1] * n[2]
+
+
 class GpuBackend:
-    """libfdtd plans and batches; one torch uint8 arena per request.  Requests
-    with the density-matrix medium step in a batch of their own (members of one
-    batch share a gain model); linear and Lorentz requests share the other."""
+    """libfdtd plans and batches; one torch uint8 arena per request.  A group of
+    one steps on the plain stepper; larger groups step as one batch per gain
+    model (members of a batch share a gain model: density-matrix requests in one,
+    linear and Lorentz requests in the other), kept for the whole run and given
+    its new members in place when the group changes."""
 
     def __init__(self, tuning=None):
         import torch
         from . import fdtd
         self.fdtd = fdtd
         self.torch = torch
-        self.tuning = tuning or fdtd.default_tuning()
+        self.tuning = tuning
         self._batch = {}
         self._members = {}
 
     def prepare(self, req):
         cfg = request_config(req)
-        plan = self.fdtd.Plan(cfg, max_steps=req["steps"], tuning=self.tuning, bind=False)
+        lasing = req["kind"] != "linear"
+        tune = self.tuning or (SERVE_TUNING_LASING if lasing else SERVE_TUNING)
+        plan = self.fdtd.Plan(cfg, max_steps=req["steps"], tuning=tune, bind=False)
         dm = any(int(m.get("gain") or 0) == 2 for m in cfg["materials"])
-        return {"plan": plan, "cfg": cfg, "bytes": plan.required_bytes() + 256, "group": int(dm)}
+        return {"plan": plan, "cfg": cfg, "bytes": plan.required_bytes() + 256, "group": int(dm),
+                "cells": plan.ncell, "cost": LASING_COST if lasing else 1.0}
 
     def footprint(self, h):
         return h["bytes"]
+
+    def work(self, h, steps):
+        return h["cells"] * h["cost"] * steps
 
     def bind(self, h):
         h["plan"].bind()
@@ -73,11 +104,12 @@ class GpuBackend:
                 g[0]["plan"].step(n)   # a lone request runs on the plain stepper
                 continue
             members = tuple(id(h["plan"]) for h in g)
-            if members != self._members.get(key):
-                if self._batch.get(key) is not None:
-                    self._batch[key].close()
-                self._batch[key] = self.fdtd.Batch([h["plan"] for h in g])
-                self._members[key] = members
+            plans = [h["plan"] for h in g]
+            if self._batch.get(key) is None:
+                self._batch[key] = self.fdtd.Batch(plans)
+            elif members != self._members.get(key):
+                self._batch[key].set_members(plans)
+            self._members[key] = members
             self._batch[key].step(n)
 
     def sync(self):
@@ -105,19 +137,29 @@ class GpuBackend:
         return out
 
     def release(self, h):
+        # a batch whose member list still names this plan is not stepped again
+        # before set_members gives it the next group
         for key in list(self._members):
             if id(h["plan"]) in self._members[key]:
-                if self._batch.get(key) is not None:
-                    self._batch[key].close()
-                self._batch.pop(key, None)
-                self._members.pop(key, None)
+                self._members[key] = ()
         h["plan"].close()
+
+    def close(self):
+        for b in self._batch.values():
+            if b is not None:
+                b.close()
+        self._batch, self._members = {}, {}
 
 
 class Server:
     """Arrival-ordered admission by footprint; batched stepping in chunks."""
 
-    def __init__(self, backend, budget_bytes, chunk=400, max_active=64, clock=None, sleep=None):
+    def __init__(self, backend, budget_bytes, chunk=400, max_active=64, clock=None, sleep=None, policy="srpt",
+                 group_factor=4.0):
+        if policy not in ("srpt", "all"):
+            raise ValueError("policy must be 'srpt' or 'all'")
+        self.policy = policy
+        self.group_factor = float(group_factor)
         self.backend = backend
         self.budget = int(budget_bytes)
         self.chunk = int(chunk)
@@ -173,6 +215,14 @@ class Server:
         self.backend.release(entry["h"])
         self.used -= self.backend.footprint(entry["h"])
 
+    def _group(self):
+        """The admitted requests the next launch steps (see the module notes)."""
+        if self.policy == "all" or len(self.active) == 1 or not hasattr(self.backend, "work"):
+            return list(self.active)
+        w = [self.backend.work(e["h"], e["req"]["steps"] - e["done"]) for e in self.active]
+        wmin = min(w)
+        return [e for e, x in zip(self.active, w) if x <= self.group_factor * wmin]
+
     def run(self, requests):
         """Serve the requests (each with an 'arrival' time in seconds relative to the
         start of run); returns wall time."""
@@ -198,11 +248,12 @@ class Server:
                     self._retire(e, self.clock() - t0, ok=False, why="cancelled")
             if not self.active:
                 continue
-            n = min(self.chunk, min(e["req"]["steps"] - e["done"] for e in self.active))
-            self.backend.step([e["h"] for e in self.active], n)
+            group = self._group()
+            n = min(self.chunk, min(e["req"]["steps"] - e["done"] for e in group))
+            self.backend.step([e["h"] for e in group], n)
             self.backend.sync()
             now = self.clock() - t0
-            for e in list(self.active):
+            for e in group:
                 e["done"] += n
                 if not self.backend.healthy(e["h"]):
                     self.active.remove(e)

@@ -126,6 +126,53 @@ def test_sequential_baseline_and_summary():
         assert srv.results[r["id"]]["value"] == srv2.results[r["id"]]["value"]
 
 
+class SizedBackend(MockBackend):
+    """Steps cost time in proportion to the cells they advance (a device that
+    is busy with every member of a launch), and each request has a size."""
+
+    def prepare(self, req):
+        return {"id": req["id"], "mem": req["mem"], "done": 0, "cells": req["cells"]}
+
+    def work(self, h, steps):
+        return h["cells"] * steps
+
+    def step(self, hs, n):
+        self.batches.append(sorted(h["id"] for h in hs))
+        for h in hs:
+            h["done"] += n
+        self.clock.t += n * self.step_cost * sum(h["cells"] for h in hs)
+
+
+def _sized(i, arrival, steps, cells):
+    return {"id": i, "arrival": arrival, "steps": steps, "mem": 10, "cells": cells}
+
+
+def test_shortest_remaining_work_first_groups_similar_requests():
+    """With policy srpt a launch steps the admitted requests whose remaining work
+    is within group_factor of the smallest: a small request that arrives while a
+    large one runs is served ahead of it, similar requests share launches, and
+    every request still completes with all its steps."""
+    reqs = [_sized(0, 0.0, 1000, 100), _sized(1, 0.01, 1000, 5), _sized(2, 0.01, 1000, 6), _sized(3, 0.02, 500, 100)]
+    out = {}
+    for policy in ("srpt", "all"):
+        clk = FakeClock()
+        be = SizedBackend(clk, step_cost=1e-6)
+        srv = Server(be, budget_bytes=1000, chunk=100, clock=clk, sleep=clk.sleep, policy=policy)
+        srv.run(reqs)
+        assert set(srv.results) == {0, 1, 2, 3} and not srv.failed
+        assert all(srv.results[r["id"]]["steps"] == r["steps"] for r in reqs)
+        done = {rid: t for ev, rid, t in srv.log if ev == "done"}
+        out[policy] = (be.batches, done, summarize(reqs, srv.clock(), srv.results, srv.failed))
+    batches, done, s_srpt = out["srpt"]
+    # the two small requests ran together, apart from the large ones, and finished first
+    assert [1, 2] in batches and not any(1 in b and 0 in b for b in batches)
+    assert max(done[1], done[2]) < min(done[0], done[3])
+    # and their latency beats stepping every admitted request at once
+    _, done_all, s_all = out["all"]
+    assert max(done[1], done[2]) < max(done_all[1], done_all[2])
+    assert s_srpt["p50_s"] < s_all["p50_s"]
+
+
 def test_percentile():
     assert percentile([1, 2, 3, 4], 50) == 2.5
     assert percentile([5], 99) == 5
