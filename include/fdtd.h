@@ -284,6 +284,16 @@ int fdtd_read_energy(fdtd_plan* p, double* host, int64_t* n, void* stream);
    members must stay alive.  Creation allocates the batch's launch tables on the
    device (hipMalloc; freed by destroy). */
 int fdtd_batch_create(fdtd_plan* const* plans, int32_t n, const fdtd_tuning* t, fdtd_batch** out);
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+   tight serving loops, harnesses that forbid hipMalloc): fdtd_batch_create with
+   the batch's launch tables placed in a static per-GPU array of 16 MiB (held
+   until the process ends) instead of a hipMalloc'd block; calls no hipMalloc or
+   hipFree.  FDTD_ENOMEM if the tables need more than 16 MiB (about 300,000
+   tiles of step work).  All static batches of one GPU share that array: creating
+   one replaces the tables of the previous one, which from then on refuses to
+   step (FDTD_ESTATE); creations that overlap on one GPU race.  Members grow into
+   the same array with fdtd_batch_set_members up to the same limit. */
+int fdtd_batch_create_static(fdtd_plan* const* plans, int32_t n, const fdtd_tuning* t, fdtd_batch** out);
 /* Replace a batch's members (same conditions as at creation; the batch keeps
    its tuning) for continuous batching: requests join and leave between launches
    without a new batch.  The device tables are rewritten in place and grow

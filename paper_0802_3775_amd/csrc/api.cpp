@@ -15,6 +15,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -187,6 +188,8 @@ struct fdtd_batch {
   void* dmem = nullptr;  // tile tables + desc pointer list (setup-time allocation)
   size_t dcap = 0;       // bytes available at dmem
   bool owns_dmem = false;  // dmem came from hipMalloc (freed by destroy)
+  int static_dev = -1;     // static batches: the GPU whose static table array holds the tables
+  uint64_t static_gen = 0;  // ... and which of that GPU's static batches wrote them last
   fd_tile* dtiles[FD_NCLASS] = {};
   fd_dft_tile* ddft = nullptr;
   fd_desc** ddescs = nullptr;
@@ -1593,6 +1596,20 @@ int fdtd_tune(const fdtd_plan* p, const fdtd_tuning* cand, int32_t ncand, int64_
 
 namespace {
 
+// Static batches (fdtd_batch_create_static) share one table array per GPU:
+// each creation takes the next generation of its device, and a batch whose
+// generation is no longer the device's has lost its tables to a later one.
+std::mutex g_static_mu;
+uint64_t g_static_gen[FD_MAX_DEVICES] = {};
+
+int batch_static_owner(const fdtd_batch* b) {
+  if (b->static_dev < 0) return FDTD_OK;
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (g_static_gen[b->static_dev] != b->static_gen)
+    return fail(FDTD_ESTATE, "a later static batch on GPU %d replaced this batch's launch tables", b->static_dev);
+  return FDTD_OK;
+}
+
 // Checks a member list against the batch tuning bt; *gm receives the gain model
 // the members with gain share (0: none has gain).
 int batch_check(fdtd_plan* const* plans, int32_t n, const fdtd_tuning& bt, int* gm) {
@@ -1719,8 +1736,46 @@ int fdtd_batch_create(fdtd_plan* const* plans, int32_t n, const fdtd_tuning* t, 
   return FDTD_OK;
 }
 
+int fdtd_batch_create_static(fdtd_plan* const* plans, int32_t n, const fdtd_tuning* t, fdtd_batch** out) {
+  if (!plans || !out || n < 1) return fail(FDTD_EINVAL, "need at least one plan");
+  *out = nullptr;
+  if (!plans[0]) return fail(FDTD_ESTATE, "batch member 0 not bound");
+  const fdtd_tuning bt = t ? *t : plans[0]->tune;
+  int gm = 0;
+  if (int r = batch_check(plans, n, bt, &gm)) return r;
+  std::unique_ptr<fdtd_batch> b(new (std::nothrow) fdtd_batch());
+  if (!b) return fail(FDTD_ENOMEM, "host allocation");
+  b->block = bt.block;
+  b->tile_x = bt.tile_x;
+  b->parallel = bt.parallel;
+  b->max_blocks = bt.max_blocks;
+  b->graph_steps = bt.graph_steps;
+  b->ntst = bt.stores == FDTD_STORES_NONTEMPORAL ? 1 : 0;
+  batch_layout(b.get(), plans, n, gm);
+  size_t off_t[FD_NCLASS], off_d, off_p;
+  const size_t bytes = batch_table_bytes(b.get(), off_t, &off_d, &off_p);
+  if (bytes > FD_STATIC_TABLE_BYTES)
+    return fail(FDTD_ENOMEM, "batch launch tables of %zu bytes exceed the static maximum of %zu", bytes,
+                (size_t)FD_STATIC_TABLE_BYTES);
+  void* base = nullptr;
+  int dev = 0;
+  HIPCHK(fd_static_tables(&base, &dev));
+  b->dmem = base;
+  b->dcap = FD_STATIC_TABLE_BYTES;
+  b->owns_dmem = false;
+  b->static_dev = dev;
+  {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    b->static_gen = ++g_static_gen[dev];
+  }
+  if (int r = batch_upload(b.get())) return r;
+  *out = b.release();
+  return FDTD_OK;
+}
+
 int fdtd_batch_set_members(fdtd_batch* b, fdtd_plan* const* plans, int32_t n, void* stream) {
   if (!b) return fail(FDTD_EINVAL, "null batch");
+  if (int r = batch_static_owner(b)) return r;
   fdtd_tuning bt{};
   bt.block = b->block;
   bt.tile_x = b->tile_x;
@@ -1775,6 +1830,7 @@ static int batch_enqueue(fdtd_batch* b, int64_t n, hipStream_t st, Fork* fk) {
 
 static int batch_step(fdtd_batch* b, int64_t n, hipStream_t st) {
   if (n < 0) return fail(FDTD_EINVAL, "negative step count");
+  if (int r = batch_static_owner(b)) return r;
   for (fdtd_plan* p : b->plans)
     if (p->step + n > p->max_steps) return fail(FDTD_ESTATE, "a member would exceed its max_steps");
   const int64_t K = b->graph_steps;
@@ -1827,6 +1883,7 @@ int fdtd_batch_step(fdtd_batch* b, int64_t n, void* stream) {
 int fdtd_batch_time_kernels(fdtd_batch* b, int64_t n, void* stream, double* ms, int64_t* launches) {
   if (!b || !ms || !launches) return fail(FDTD_EINVAL, "null argument");
   if (n < 0) return fail(FDTD_EINVAL, "negative step count");
+  if (int r = batch_static_owner(b)) return r;
   for (fdtd_plan* p : b->plans)
     if (p->step + n > p->max_steps) return fail(FDTD_ESTATE, "a member would exceed its max_steps");
   hipStream_t st = (hipStream_t)stream;

@@ -12,6 +12,8 @@
 #define FD_DFT_QB 8     // frequencies per DFT work unit
 #define FD_DFT_PTS 64   // plane points per DFT work unit (one per lane)
 #define FD_MAXBLOCK 256   // threads per workgroup upper bound (launch bounds)
+#define FD_STATIC_TABLE_BYTES ((size_t)16 << 20)  // per-GPU launch tables of batches created without allocation
+#define FD_MAX_DEVICES 64
 
 // Per-material coefficients, FP32 (built in FP64 on the host, rounded once).
 struct fd_mat {
@@ -157,3 +159,7 @@ hipError_t fd_launch_voxelize(const int64_t* sites, int ex, int ey, int ez, cons
                               int nx, int ny, int nz, uint8_t* map, hipStream_t st);
 hipError_t fd_launch_init_pop(const uint8_t* map, const float* n_init_by_mat, const uint32_t* gidx, unsigned gainmask,
                               float* pop, int ncell, hipStream_t st);
+
+// Device address of this GPU's static launch-table array (FD_STATIC_TABLE_BYTES,
+// 256-byte aligned), looked up once per device with that device current.
+hipError_t fd_static_tables(void** ptr, int* device);

@@ -26,6 +26,7 @@
 
 #include <hip/hip_ext.h>
 
+#include <mutex>
 #include <type_traits>
 
 namespace {
@@ -1567,4 +1568,31 @@ hipError_t fd_launch_init_pop(const uint8_t* map, const float* n_init_by_mat, co
   if (blocks > 65536) blocks = 65536;
   init_pop_kernel<<<blocks, 256, 0, st>>>(map, n_init_by_mat, gidx, gainmask, pop, ncell);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------ static tables
+// The launch tables (tile lists, DFT work units, descriptor pointers) of batches
+// made by fdtd_batch_create_static live here instead of in a hipMalloc'd block:
+// one array per GPU, held until the process ends.  In host code the name is
+// only a handle: kernels get the address hipGetSymbolAddress returns for the
+// current device.
+static __device__ __align__(256) unsigned char scratch[FD_STATIC_TABLE_BYTES];
+
+hipError_t fd_static_tables(void** ptr, int* device) {
+  static std::mutex mu;
+  static void* addr[FD_MAX_DEVICES] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= FD_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* a = nullptr;
+    e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = a;
+  }
+  *ptr = addr[dev];
+  *device = dev;
+  return hipSuccess;
 }

@@ -107,6 +107,7 @@ SIGNATURES = {
     "fdtd_read_density": ([VP, P(C.c_float), VP], C.c_int),
     "fdtd_read_energy": ([VP, P(C.c_double), P(C.c_int64), VP], C.c_int),
     "fdtd_batch_create": ([P(VP), C.c_int32, P(Tuning), P(VP)], C.c_int),
+    "fdtd_batch_create_static": ([P(VP), C.c_int32, P(Tuning), P(VP)], C.c_int),
     "fdtd_batch_step": ([VP, C.c_int64, VP], C.c_int),
     "fdtd_batch_set_members": ([VP, P(VP), C.c_int32, VP], C.c_int),
     "fdtd_batch_destroy": ([VP], None),
@@ -404,9 +405,10 @@ class Batch:
     """Bound plans stepped together: one launch per tile class per step.
     tuning: the batch's launch settings (graph_steps, max_blocks, parallel,
     stores; block and tile_x must be the members'); None takes the first
-    member's."""
+    member's.  static: launch tables in the library's static per-GPU array
+    (fdtd_batch_create_static: no device allocation)."""
 
-    def __init__(self, plans, tuning=None):
+    def __init__(self, plans, tuning=None, static=False):
         self.plans = list(plans)
         arr = (C.c_void_p * len(self.plans))(*[p.h.value for p in self.plans])
         self.h = C.c_void_p()
@@ -415,7 +417,8 @@ class Batch:
             base = dict(self.plans[0].tuning)
             base.update(tuning)
             t = C.byref(make_tuning(base))
-        _check(lib().fdtd_batch_create(arr, len(self.plans), t, C.byref(self.h)))
+        create = lib().fdtd_batch_create_static if static else lib().fdtd_batch_create
+        _check(create(arr, len(self.plans), t, C.byref(self.h)))
 
     def set_members(self, plans, stream=None):
         """Replace the members in place (tables rewritten, grown only if needed)."""
