@@ -323,26 +323,32 @@ int fdtd_batch_time_steps(fdtd_batch* b, int64_t n, void* stream, double* ms);
 int fdtd_tune(const fdtd_plan* p, const fdtd_tuning* cand, int32_t ncand, int64_t warmup, int64_t steps,
               void* scratch, size_t bytes, size_t* need, double* ms, void* stream);
 
-/* Kernel classes of a step: 0 plain tiles, 1 tiles touching z-CPML slabs only,
-   2 tiles touching x or y slabs, 3-5 the same with gain cells; 6 is the
-   running-DFT update.  cells[c] = cells covered by the plan's tiles of class c
-   (c < 6), cells[6] = flux-plane points (7 entries). */
-int fdtd_class_cells(const fdtd_plan* p, int64_t* cells /* 7 */);
-/* Algorithmic bytes one launch of each class moves (7 entries): 49 per cell
-   (E, H and the material index in, E and H out) + 32 per cell and CPML axis
-   whose slab holds it (2 E-side psi read+write, 2 H-side psi read + write) + 84
-   per Lorentz gain cell (P^n, P^{n-1}, populations in; P^{n+1}, populations
-   out) or 144 per density-matrix gain cell (18 floats in and out) + 4 per cell
-   of a gain tile (the cell's gain ordinal, which addresses the gain state); the
-   DFT entry is the average bytes of one call: the plane sample (24 bytes read,
-   16 written per point) and, once per 32 samples, the 4 complex FP64
+/* Kernels of a step (FDTD_NKERNEL entries): 0 plain tiles, 1 tiles touching
+   z-CPML slabs only, 2 tiles touching x or y slabs, 3-5 the same with Lorentz
+   gain cells; 6 the running-DFT update; 7-10 the passes of the density-matrix
+   medium (predictor, corrector, edges, diagnostics).  cells[c] = cells covered
+   by the plan's tiles of class c (c < 6), flux-plane points (6), gain cells (7,
+   8), cells of the edge pass (9), flux-plane points and probes (10). */
+#define FDTD_NKERNEL 11
+int fdtd_class_cells(const fdtd_plan* p, int64_t* cells /* FDTD_NKERNEL */);
+/* Algorithmic bytes one launch of each kernel moves (FDTD_NKERNEL entries):
+   49 per cell (E, H and the material index in, E and H out) + 32 per cell and
+   CPML axis whose slab holds it (2 E-side psi read+write, 2 H-side psi read +
+   write) + 4 per cell of a Lorentz gain tile (its gain ordinal) + 84 per
+   Lorentz gain cell (P^n, P^{n-1}, populations in; P^{n+1}, populations out);
+   the DFT entry is the average bytes of one call: the plane sample (24 bytes
+   read, 16 written per point) and, once per 32 samples, the 4 complex FP64
    accumulators read + written per plane point and frequency plus the sample
-   ring read. */
-int fdtd_class_bytes(const fdtd_plan* p, double* bytes /* 7 */);
+   ring read; per density-matrix gain cell 117 (predictor: 18 state floats, the
+   cell's share of E^n and A, map, list and ordinal, Q*) and 201 (corrector: the
+   state read and written, fields, neighbours' Q*, Q), 1 per cell of the edge
+   range + 41 per cell whose edges touch gain (A in, E out, Q, neighbours' map
+   and ordinals), 32 per flux-plane point + 8 per probe for the diagnostics. */
+int fdtd_class_bytes(const fdtd_plan* p, double* bytes /* FDTD_NKERNEL */);
 /* Advance n steps without graphs, launching every kernel with a pair of hipEvents
    bound to the launch (hipExtLaunchKernelGGL start/stop: the kernel's own begin
    and end timestamps); ms[c] = summed milliseconds and launches[c] = number of
-   launches of class c (7 entries each, as above). */
+   launches of kernel c (FDTD_NKERNEL entries each, as above). */
 int fdtd_time_kernels(fdtd_plan* p, int64_t n, void* stream, double* ms, int64_t* launches);
 /* The same for a batch: the launches of its tile classes over all members (the
    class bytes of a batch launch are the sum of its members' fdtd_class_bytes). */

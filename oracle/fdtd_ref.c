@@ -11,12 +11,21 @@
  *   4. E^{n+1} = E^n + dt/(eps dx) (curl H^{n+1/2} - dx J^{n+1/2}) - (P^{n+1}-P^n)/eps.
  *   5. four-level populations by Crank-Nicolson with the stimulated transfer
  *        u = sum_c (E_c^n + E_c^{n+1})/2 (P_c^{n+1} - P_c^n)/dt   (-u from n1, +u to n2).
- * Density-matrix gain cells (bloch_ref.h) replace 2-5 by: the noise current
- * sigma_N sqrt(rho_cc) g_c / sqrt(dt dx^3) on E_c, A = E^n + dt/(eps dx) (curl H -
- * dx J), and one predictor-corrector pass of the implicit midpoint coupling
- *        E^(0) = (E^n + A)/2,  rho* = S(rho^n; E^(0)),  E* = A - (P(rho*) - P^n)/eps,
- *        E^(1) = (E^n + E*)/2, rho^{n+1} = S(rho^n; E^(1)),
- *        E^{n+1} = A - (P(rho^{n+1}) - P^n)/eps,   P_c(rho) = 2 kappa Re rho_0c.
+ * Density-matrix gain cells (bloch_ref.h) hold their density matrix at the
+ * cell centre (the paper solves the density-matrix equations in the middle of
+ * the Yee cell) and replace 2-5 by: A = E^n + dt/(eps dx) (curl H - dx J) on
+ * every edge; at each gain-cell centre the average <.> of the four edges of
+ * each component; and one predictor-corrector pass of the implicit midpoint
+ * coupling,
+ *        E^(0) = <(E^n + A)/2>,  rho* = S(rho^n; E^(0)),  Q* = P(rho*) - P(rho^n) + dt J,
+ *        E*    = A - [Q*]/eps,
+ *        E^(1) = <(E^n + E*)/2>, rho^{n+1} = S(rho^n; E^(1)), Q = P(rho^{n+1}) - P(rho^n) + dt J,
+ *        E^{n+1} = A - [Q]/eps,
+ * where [Q] on an edge is a quarter of the sum of Q over the (up to four) cells
+ * that share the edge (the adjoint of the average, so sum_edges E [Q] =
+ * sum_cells <E> Q), P_c(rho) = 2 kappa Re rho_0c, eps the permittivity of the
+ * edge's own voxel, and J the spontaneous-emission noise current
+ * sigma_N sqrt(rho_cc) g_c / sqrt(dt dx^3) at the centre.
  *   6. diagnostics: probes E^{n+1}; transmitted power T at the flux plane
  *      (paper, section "Dynamical diffusion and localization": transversely
  *      integrated Poynting vector); running DFT of the plane fields; energy.
@@ -73,6 +82,11 @@ struct orc_sim {
   int has_bloch;
   orc_bloch_c bc[ORC_MAXMAT];
   orc_z* rho;       /* [ncell][4][4], zero outside gain-2 cells */
+  double* Eo[3];    /* E^n of every edge during a density-matrix step */
+  double* Es[3];    /* E* of every edge (predictor field) */
+  double* Qd[3];    /* per cell: polarization increment of the predictor / corrector + dt J */
+  double* Jd[3];    /* per cell: dt J, the noise current's polarization increment */
+  double* Pd[3];    /* per cell: P(rho^n) */
   /* sources */
   int nsrc;
   orc_source src[ORC_MAXSRC];
@@ -249,7 +263,16 @@ orc_sim* orc_create(const orc_grid* g, const orc_material* mats, int32_t nmat, i
       return NULL;
     }
   }
-  if (s->has_bloch) s->rho = (orc_z*)calloc((size_t)s->ncell * 16, sizeof(orc_z));
+  if (s->has_bloch) {
+    s->rho = (orc_z*)calloc((size_t)s->ncell * 16, sizeof(orc_z));
+    for (int c = 0; c < 3; ++c) {
+      s->Eo[c] = zalloc(s->ncell);
+      s->Es[c] = zalloc(s->ncell);
+      s->Qd[c] = zalloc(s->ncell);
+      s->Jd[c] = zalloc(s->ncell);
+      s->Pd[c] = zalloc(s->ncell);
+    }
+  }
   if (s->has_gain) {
     for (int c = 0; c < 3; ++c) { s->P[c] = zalloc(s->ncell); s->Pold[c] = zalloc(s->ncell); }
     for (int q = 0; q < 4; ++q) s->N[q] = zalloc(s->ncell);
@@ -264,6 +287,7 @@ void orc_destroy(orc_sim* s) {
     free(s->E[c]); free(s->H[c]); free(s->Hprev[c]);
     free(s->P[c]); free(s->Pold[c]);
     for (int w = 0; w < 3; ++w) { free(s->psiE[c][w]); free(s->psiH[c][w]); }
+    free(s->Eo[c]); free(s->Es[c]); free(s->Qd[c]); free(s->Jd[c]); free(s->Pd[c]);
     free(s->kE[c]); free(s->bE[c]); free(s->cE[c]);
     free(s->kH[c]); free(s->bH[c]); free(s->cH[c]);
   }
@@ -441,18 +465,9 @@ static void update_E_and_matter(orc_sim* s, int64_t n) {
         double Eold[3], Pnew[3] = {0, 0, 0}, Pcur[3] = {0, 0, 0}, A[3];
         int pec[3] = {0, 0, 0};
         for (int c = 0; c < 3; ++c) Eold[c] = s->E[c][q];
-        /* density-matrix cells: noise current (dx J) on the E update */
-        orc_z(*r)[4] = mt->gain == 2 ? (orc_z(*)[4])(s->rho + 16 * q) : NULL;
-        double jn[3] = {0, 0, 0};
-        if (r && mt->noise != 0.0) {
-          const uint32_t ctr[4] = {(uint32_t)n, (uint32_t)q, 0u, 2u};
-          double gs[4];
-          orc_normals4(ctr, key, gs);
-          for (int c = 0; c < 3; ++c) {
-            const double pc = creal(r[c + 1][c + 1]) > 0.0 ? creal(r[c + 1][c + 1]) : 0.0;
-            jn[c] = dx * s->bc[m].noise * sqrt(pc) * gs[c];
-          }
-        }
+        /* density-matrix plans: keep E^n of every edge for the centre coupling */
+        if (s->has_bloch)
+          for (int c = 0; c < 3; ++c) s->Eo[c][q] = Eold[c];
         /* 2-3: noise and Lorentz polarization in gain cells */
         if (mt->gain == 1) {
           double F[3] = {0, 0, 0};
@@ -503,30 +518,10 @@ static void update_E_and_matter(orc_sim* s, int64_t n) {
             if (src->kind != ORC_SRC_DIPOLE && src->k != k) continue;
             curl -= src->kind == ORC_SRC_BEAM ? dxJ[rr] * beam_weight(s, src, c, i, j) : dxJ[rr];
           }
-          curl -= jn[c];
           A[c] = Eold[c] + cb * curl;
         }
-        if (r) {
-          /* density matrix: predictor-corrector on the midpoint field */
-          const orc_bloch_c* bc = &s->bc[m];
-          double Pn[3], Em[3], Es[3];
-          orc_z t[4][4];
-          for (int c = 0; c < 3; ++c) {
-            Pn[c] = 2.0 * bc->kappa * creal(r[0][c + 1]);
-            Em[c] = 0.5 * (Eold[c] + A[c]);
-          }
-          orc_bloch_step(bc, dt, Em, r, t);
-          for (int c = 0; c < 3; ++c) {
-            Es[c] = pec[c] ? 0.0 : A[c] - (2.0 * bc->kappa * creal(t[0][c + 1]) - Pn[c]) / eps;
-            Em[c] = 0.5 * (Eold[c] + Es[c]);
-          }
-          orc_bloch_step(bc, dt, Em, r, t);
-          memcpy(r, t, sizeof(t));
-          for (int c = 0; c < 3; ++c)
-            s->E[c][q] = pec[c] ? 0.0 : A[c] - (2.0 * bc->kappa * creal(r[0][c + 1]) - Pn[c]) / eps;
-        } else {
-          for (int c = 0; c < 3; ++c) s->E[c][q] = pec[c] ? 0.0 : A[c] - (Pnew[c] - Pcur[c]) / eps;
-        }
+        /* density-matrix plans: E holds A until the centre coupling (bloch_cells) */
+        for (int c = 0; c < 3; ++c) s->E[c][q] = pec[c] ? 0.0 : A[c] - (Pnew[c] - Pcur[c]) / eps;
         /* 5: populations */
         if (mt->gain == 1) {
           double u = 0.0;
@@ -547,6 +542,124 @@ static void update_E_and_matter(orc_sim* s, int64_t n) {
           }
         }
       }
+}
+
+/* ------------------------------------------- density matrix at cell centres */
+
+/* Wraps index p along axis d; -1 beyond a PEC wall. */
+static int64_t wrap_axis(const orc_sim* s, int d, int64_t p) {
+  const int64_t n[3] = {s->nx, s->ny, s->nz};
+  if (p >= 0 && p < n[d]) return p;
+  if (!s->g.periodic[d]) return -1;
+  return ((p % n[d]) + n[d]) % n[d];
+}
+
+/* Tangential E held at zero on a PEC wall (index 0 of a non-periodic axis
+   transverse to the component). */
+static int pec_held(const orc_sim* s, int c, const int64_t p[3]) {
+  const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+  return (!s->g.periodic[a1] && p[a1] == 0) || (!s->g.periodic[a2] && p[a2] == 0);
+}
+
+/* Average over the four edges of component c around the centre of cell p:
+   the edges sit at offsets {0, 1} along the two axes transverse to c (edges
+   beyond a PEC wall hold zero). */
+static double centre_average(const orc_sim* s, const double* F, int c, const int64_t p[3]) {
+  const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+  double acc = 0.0;
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) {
+      int64_t e[3] = {p[0], p[1], p[2]};
+      e[a1] = wrap_axis(s, a1, p[a1] + u);
+      e[a2] = wrap_axis(s, a2, p[a2] + v);
+      if (e[a1] < 0 || e[a2] < 0) continue;
+      acc += F[idx3(s, e[0], e[1], e[2])];
+    }
+  return 0.25 * acc;
+}
+
+/* A quarter of the sum of Q over the (up to four) cells that share edge c of
+   cell p: the cells at offsets {0, -1} along the two transverse axes. */
+static double edge_share(const orc_sim* s, const double* Q, int c, const int64_t p[3]) {
+  const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+  double acc = 0.0;
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) {
+      int64_t e[3] = {p[0], p[1], p[2]};
+      e[a1] = wrap_axis(s, a1, p[a1] - u);
+      e[a2] = wrap_axis(s, a2, p[a2] - v);
+      if (e[a1] < 0 || e[a2] < 0) continue;
+      acc += Q[idx3(s, e[0], e[1], e[2])];
+    }
+  return 0.25 * acc;
+}
+
+/* One coupling stage: every density-matrix cell steps rho^n with the centre
+   average of (E^n + F)/2 (F = A for the predictor, E* for the corrector) and
+   stores Q = P(new rho) - P(rho^n) + dt J; the corrector keeps the new rho. */
+static void bloch_stage(orc_sim* s, double* const F[3], int keep) {
+  const double dt = s->dt;
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < s->nz; ++k)
+    for (int64_t j = 0; j < s->ny; ++j)
+      for (int64_t i = 0; i < s->nx; ++i) {
+        const int64_t q = idx3(s, i, j, k);
+        const int m = s->map[q];
+        if (s->mat[m].gain != 2) continue;
+        const int64_t p[3] = {i, j, k};
+        double Em[3];
+        for (int c = 0; c < 3; ++c)
+          Em[c] = 0.5 * (centre_average(s, s->Eo[c], c, p) + centre_average(s, F[c], c, p));
+        orc_z(*r)[4] = (orc_z(*)[4])(s->rho + 16 * q);
+        orc_z t[4][4];
+        orc_bloch_step(&s->bc[m], dt, Em, r, t);
+        for (int c = 0; c < 3; ++c)
+          s->Qd[c][q] = 2.0 * s->bc[m].kappa * creal(t[0][c + 1]) - s->Pd[c][q] + s->Jd[c][q];
+        if (keep) memcpy(r, t, sizeof(t));
+      }
+}
+
+/* out = A - [Q]/eps on every edge not held by a PEC wall (A is in s->E). */
+static void bloch_edges(orc_sim* s, double* const out[3]) {
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < s->nz; ++k)
+    for (int64_t j = 0; j < s->ny; ++j)
+      for (int64_t i = 0; i < s->nx; ++i) {
+        const int64_t q = idx3(s, i, j, k);
+        const int64_t p[3] = {i, j, k};
+        const double eps = s->mat[s->map[q]].eps;
+        for (int c = 0; c < 3; ++c)
+          out[c][q] = pec_held(s, c, p) ? 0.0 : s->E[c][q] - edge_share(s, s->Qd[c], c, p) / eps;
+      }
+}
+
+/* The density-matrix cells of step n, after the edge loop has left A in s->E
+   and E^n in s->Eo: noise and P(rho^n) per cell, predictor, E*, corrector,
+   E^{n+1}. */
+static void bloch_cells(orc_sim* s, int64_t n) {
+  const uint32_t key[2] = {s->g.seed, s->g.realization};
+  const double dt = s->dt;
+#pragma omp parallel for schedule(static)
+  for (int64_t q = 0; q < s->ncell; ++q) {
+    const int m = s->map[q];
+    for (int c = 0; c < 3; ++c) s->Jd[c][q] = s->Pd[c][q] = s->Qd[c][q] = 0.0;
+    if (s->mat[m].gain != 2) continue;
+    const orc_z* r = s->rho + 16 * q;
+    for (int c = 0; c < 3; ++c) s->Pd[c][q] = 2.0 * s->bc[m].kappa * creal(r[c + 1]);
+    if (s->mat[m].noise != 0.0) {
+      const uint32_t ctr[4] = {(uint32_t)n, (uint32_t)q, 0u, 2u};
+      double gs[4];
+      orc_normals4(ctr, key, gs);
+      for (int c = 0; c < 3; ++c) {
+        const double pc = creal(r[5 * (c + 1)]) > 0.0 ? creal(r[5 * (c + 1)]) : 0.0;
+        s->Jd[c][q] = dt * s->bc[m].noise * sqrt(pc) * gs[c];
+      }
+    }
+  }
+  bloch_stage(s, s->E, 0);
+  bloch_edges(s, s->Es);
+  bloch_stage(s, s->Es, 1);
+  bloch_edges(s, s->E);
 }
 
 static double energy_now(orc_sim* s) {
@@ -633,6 +746,7 @@ int orc_step(orc_sim* s, int64_t nsteps) {
     update_H(s);
     if (energy_due) s->elog[n / s->ke] = energy_now(s);
     update_E_and_matter(s, n);
+    if (s->has_bloch) bloch_cells(s, n);
     flux_after(s, n);
     for (int p = 0; p < s->nprobe; ++p) s->plog[p][n] = (s->pc[p] < 3 ? s->E[s->pc[p]] : s->H[s->pc[p] - 3])[s->pidx[p]];
     s->step = n + 1;

@@ -71,6 +71,7 @@ struct Layout {
   size_t tiles[FD_NCLASS];
   size_t dft;
   size_t sites;
+  size_t glist, dmq[2], dmunits;  // density-matrix plans: gain-cell list, Q buffers, pass work units
 };
 
 struct GraphEntry {
@@ -163,6 +164,11 @@ struct fdtd_plan {
   std::vector<fd_dft_tile> dft;
   fd_dft_tile* ddft = nullptr;
   int maxnf = 0;
+  // density-matrix passes: work units (cells, edges, diagnostics) and their device copy
+  std::vector<fd_dm_unit> dmu[3];
+  fd_dm_unit* ddm = nullptr;
+  int64_t dm_cells[4] = {0, 0, 0, 0};  // cells each pass covers (predictor, corrector, edges, diagnostics)
+  double dm_bytes[4] = {0, 0, 0, 0};   // algorithmic bytes of one launch of each pass
   int src_len[FD_MAXSRC] = {0, 0, 0, 0};
   bool has_gain = false;
   int gm = 0;  // gain model of the plan's gain materials: 0 none, 1 Lorentz, 2 density matrix
@@ -185,6 +191,8 @@ struct fdtd_batch {
   int gm = 1;  // gain model shared by the members with gain
   std::vector<fd_dft_tile> dft;
   int maxnf = 0;
+  std::vector<fd_dm_unit> dmu[3];  // members' density-matrix pass units
+  fd_dm_unit* ddm[3] = {};
   void* dmem = nullptr;  // tile tables + desc pointer list (setup-time allocation)
   size_t dcap = 0;       // bytes available at dmem
   bool owns_dmem = false;  // dmem came from hipMalloc (freed by destroy)
@@ -234,7 +242,8 @@ int build_density_material(const fdtd_plan* p, const fdtd_material& m, fd_mat& o
   out.beinf = (float)(gp + g1 > 0.0 ? gp / (gp + g1) : 0.0);
   out.bg1m = (float)(-std::expm1(-0.5 * (gp + g1) * dt));
   out.bh1m = (float)(-std::expm1(-0.5 * g1 * dt));
-  out.noise = (float)(m.noise * p->dx / std::sqrt(dt * p->dx * p->dx * p->dx));
+  // dt J per standard normal, J = sigma_N sqrt(rho_cc) g / sqrt(dt dx^3) at the cell centre
+  out.noise = (float)(m.noise * dt / std::sqrt(dt * p->dx * p->dx * p->dx));
   return FDTD_OK;
 }
 
@@ -362,7 +371,6 @@ int gain_model_of(const std::vector<fdtd_material>& mats) {
 // Algorithmic bytes of one gain cell per step beyond the linear 49: Lorentz
 // P^n, P^{n-1}, populations in and P^{n+1}, populations out (84); density
 // matrix 18 floats in and out (144).
-double gain_cell_bytes(int gm) { return gm == 2 ? 144.0 : 84.0; }
 
 // Bytes a step streams through: both field buffers, the material map, the psi
 // slabs and the gain arrays.  Above four times the Infinity Cache (256 MB on
@@ -428,6 +436,8 @@ int compute_layout(fdtd_plan* p, int64_t max_steps, Layout& L) {
     for (int c = 0; c < 3; ++c) L.P[b][c] = gm == 1 ? take(nc * 4) : 0;
   L.pop = gm ? take(nc * 4 * (gm == 2 ? 18 : 6)) : 0;
   L.gidx = gm ? take(nc * 4) : 0;
+  L.glist = gm == 2 ? take(nc * 4) : 0;
+  for (int q = 0; q < 2; ++q) L.dmq[q] = gm == 2 ? take(nc * 4 * 3) : 0;
   for (int w = 0; w < 3; ++w) {
     const bool on = pml_t(p, w) > 0;
     L.prof[w] = on ? take(sizeof(float) * 6 * axis_n(p, w)) : 0;
@@ -477,6 +487,12 @@ int compute_layout(fdtd_plan* p, int64_t max_steps, Layout& L) {
   for (const Flux& f : p->flux)
     if (f.nf > 0) ndft += (size_t)((plane + FD_DFT_PTS - 1) / FD_DFT_PTS) * (size_t)((f.nf + FD_DFT_QB - 1) / FD_DFT_QB);
   L.dft = take(sizeof(fd_dft_tile) * std::max<size_t>(ndft, 1));
+  // density-matrix pass units: cells by FD_DM_CELLS, edge range by FD_DM_EDGES,
+  // one diagnostics unit per flux-plane xy tile plus one for the probes
+  const size_t ndm = gm == 2 ? (nc + FD_DM_CELLS - 1) / FD_DM_CELLS + (nc + FD_DM_EDGES - 1) / FD_DM_EDGES +
+                                   p->flux.size() * (size_t)p->nblk + 1
+                             : 0;
+  L.dmunits = take(sizeof(fd_dm_unit) * std::max<size_t>(ndm, 1));
   if (p->have_opal) {
     size_t ns = 1;
     for (int a = 0; a < 3; ++a) ns *= (size_t)(2 * p->opal.cells[a] + 1);
@@ -493,11 +509,97 @@ T* at(fdtd_plan* p, size_t off) {
   return reinterpret_cast<T*>(p->arena + off);
 }
 
+// Work units of the density-matrix passes (plans with that medium): the gain
+// ordinals in runs of FD_DM_CELLS, the cells whose edges can touch a gain cell
+// in runs of FD_DM_EDGES (the planes from the lowest gain plane to one past the
+// highest; every plane on a periodic z axis), one diagnostics unit per xy tile
+// of each flux plane and one for the probes; uploaded to the plan's arena,
+// with the cells and algorithmic bytes of one launch of each pass.
+int build_dm_units(fdtd_plan* p) {
+  for (auto& v : p->dmu) v.clear();
+  for (int q = 0; q < 4; ++q) {
+    p->dm_cells[q] = 0;
+    p->dm_bytes[q] = 0.0;
+  }
+  if (p->gm != 2) return FDTD_OK;
+  const fd_desc& d = p->hdesc;
+  const int ng = d.ngain;
+  for (int g0 = 0; g0 < ng; g0 += FD_DM_CELLS) p->dmu[0].push_back({p->ddesc, g0, std::min(FD_DM_CELLS, ng - g0), 0});
+  if (ng > 0) {
+    const int plane = d.plane, nz = p->g.nz;
+    int kmin = nz, kmax = -1;
+    for (int k = 0; k < nz; ++k)
+      for (int c = 0; c < plane; ++c)
+        if (p->mats[p->host_map[(size_t)k * plane + c]].gain) {
+          kmin = std::min(kmin, k);
+          kmax = std::max(kmax, k);
+          break;
+        }
+    const bool perz = p->g.bc[2] == FDTD_BC_PERIODIC;
+    const int k0 = perz ? 0 : kmin, k1 = perz ? nz : std::min(nz, kmax + 2);
+    const int64_t first = (int64_t)k0 * plane, last = (int64_t)k1 * plane;
+    for (int64_t o = first; o < last; o += FD_DM_EDGES)
+      p->dmu[1].push_back({p->ddesc, (int)o, (int)std::min<int64_t>(FD_DM_EDGES, last - o), 0});
+    // cells of the edge range whose own edges have a gain cell among their sharers
+    int64_t touched = 0;
+    const int nx = p->g.nx, ny = p->g.ny;
+    auto gain_at = [&](int i, int j, int k) {
+      const int n3[3] = {nx, ny, nz};
+      int q[3] = {i, j, k};
+      for (int a = 0; a < 3; ++a) {
+        if (q[a] >= 0 && q[a] < n3[a]) continue;
+        if (p->g.bc[a] != FDTD_BC_PERIODIC) return false;
+        q[a] = ((q[a] % n3[a]) + n3[a]) % n3[a];
+      }
+      return p->mats[p->host_map[((size_t)q[2] * ny + q[1]) * nx + q[0]]].gain != 0;
+    };
+    for (int k = k0; k < k1; ++k)
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+          bool any = false;
+          for (int u = 0; u < 2 && !any; ++u)
+            for (int v = 0; v < 2 && !any; ++v)
+              any = gain_at(i, j - u, k - v) || gain_at(i - v, j, k - u) || gain_at(i - u, j - v, k);
+          touched += any ? 1 : 0;
+        }
+    p->dm_cells[0] = p->dm_cells[1] = ng;
+    p->dm_cells[2] = last - first;
+    // predictor: state 72 + E^n and A of the cell's edges 24 + map, list and
+    // ordinal 9 + Q* 12; corrector: state 72 + 72, fields 24, neighbours' Q*
+    // 12, Q 12, map, list and ordinal 9; edges: the map of the range, and for a
+    // cell whose edges touch gain A in and E out 24 + Q 12 + neighbours' map and
+    // ordinals 5
+    p->dm_bytes[0] = 117.0 * ng;
+    p->dm_bytes[1] = 201.0 * ng;
+    p->dm_bytes[2] = 1.0 * (double)(last - first) + 41.0 * (double)touched;
+  }
+  for (int f = 0; f < (int)p->flux.size(); ++f)
+    for (int b = 0; b < p->nblk; ++b) p->dmu[2].push_back({p->ddesc, f, b, 0});
+  p->dmu[2].push_back({p->ddesc, -1, 0, 0});
+  p->dm_cells[3] = (int64_t)p->flux.size() * d.plane + (int64_t)p->probes.size();
+  // E^n, E^{n+1} (x, y) and H at two planes (x, y) per flux-plane point; a probe sample
+  p->dm_bytes[3] = 32.0 * (double)p->flux.size() * d.plane + 8.0 * (double)p->probes.size();
+  p->ddm = at<fd_dm_unit>(p, p->L.dmunits);
+  size_t off = 0;
+  for (int q = 0; q < 3; ++q) {
+    if (!p->dmu[q].empty())
+      HIPCHK(hipMemcpy(p->ddm + off, p->dmu[q].data(), sizeof(fd_dm_unit) * p->dmu[q].size(), hipMemcpyHostToDevice));
+    off += p->dmu[q].size();
+  }
+  return FDTD_OK;
+}
+
 // Enqueue one step (batch-relative index s) of the given tile sets.  With a
 // Fork (graph capture) the non-empty classes become parallel graph branches.
+// Density-matrix pass units of a plan or batch: cells, edges, diagnostics.
+struct DmLaunch {
+  const fd_dm_unit* u[3] = {nullptr, nullptr, nullptr};
+  int n[3] = {0, 0, 0};
+};
+
 int enqueue_step(fd_tile* const dtiles[FD_NCLASS], const std::vector<fd_tile>* tiles, const fd_xcd* part,
                  const int* pgrid, int tile_x, int block, int max_blocks, const fd_dft_tile* ddft, int ndft,
-                 int maxnf, bool dft_due, int s, int ntst, int gm, hipStream_t st, Fork* fk) {
+                 int maxnf, bool dft_due, int s, int ntst, const DmLaunch& dm, hipStream_t st, Fork* fk) {
   int used[FD_NCLASS], nused = 0;
   for (int c = 0; c < FD_NCLASS; ++c)
     if (!tiles[c].empty()) used[nused++] = c;
@@ -513,14 +615,26 @@ int enqueue_step(fd_tile* const dtiles[FD_NCLASS], const std::vector<fd_tile>* t
       on = fk->side[c];
       HIPCHK(hipStreamWaitEvent(on, fk->fork, 0));
     }
-    HIPCHK(fd_launch_step(c, dtiles[c], nt, tile_x, block, grid, s, pc, ntst, gm, on));
+    HIPCHK(fd_launch_step(c, dtiles[c], nt, tile_x, block, grid, s, pc, ntst, on));
     if (par && u > 0) HIPCHK(hipEventRecord(fk->join[c], on));
   }
   if (par)
     for (int u = 1; u < nused; ++u) HIPCHK(hipStreamWaitEvent(st, fk->join[used[u]], 0));
   (void)maxnf;
   if (dft_due && ndft > 0) HIPCHK(fd_launch_dft(ddft, ndft, s, st));
+  if (dm.n[0] > 0) HIPCHK(fd_launch_dm(dm.u[0], dm.n[0], dm.u[1], dm.n[1], dm.u[2], dm.n[2], block, s, st));
   return FDTD_OK;
+}
+
+DmLaunch plan_dm(const fdtd_plan* p) {
+  DmLaunch l;
+  size_t off = 0;
+  for (int q = 0; q < 3; ++q) {
+    l.u[q] = p->ddm ? p->ddm + off : nullptr;
+    l.n[q] = (int)p->dmu[q].size();
+    off += p->dmu[q].size();
+  }
+  return l;
 }
 
 bool plan_dft_due(const fdtd_plan* p, int64_t n) {
@@ -540,7 +654,7 @@ int plan_enqueue(fdtd_plan* p, int64_t n, hipStream_t st, Fork* fk) {
   for (int64_t s = 0; s < n; ++s) {
     const int r = enqueue_step(p->dtiles, p->tiles, p->part, p->pgrid, p->tune.tile_x, p->tune.block,
                                p->tune.max_blocks, p->ddft, (int)p->dft.size(), p->maxnf,
-                               plan_dft_due(p, p->step + s), (int)s, p->ntst, p->gm ? p->gm : 1, st, fk);
+                               plan_dft_due(p, p->step + s), (int)s, p->ntst, plan_dm(p), st, fk);
     if (r) return r;
   }
   HIPCHK(fd_launch_advance_one(p->ddesc, n, st));
@@ -847,6 +961,9 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
     }
   d.pop = p->has_gain ? at<float>(p, L.pop) : nullptr;
   d.gidx = p->has_gain ? at<uint32_t>(p, L.gidx) : nullptr;
+  d.glist = p->gm == 2 ? at<uint32_t>(p, L.glist) : nullptr;
+  for (int q = 0; q < 2; ++q) d.dmq[q] = p->gm == 2 ? at<float>(p, L.dmq[q]) : nullptr;
+  d.tile_x = p->tune.tile_x;
   d.key0 = p->g.seed;
   d.key1 = p->g.realization;
   std::vector<float> prof;
@@ -1005,6 +1122,15 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
     HIPCHK(hipMemcpyAsync(p->arena + L.gidx, p->gidx.data(), sizeof(uint32_t) * nc, hipMemcpyHostToDevice, st));
     HIPCHK(fd_launch_init_pop(at<uint8_t>(p, L.map), at<float>(p, L.ninit), at<uint32_t>(p, L.gidx), d.gainmask,
                               d.pop, d.ncell, st));
+    d.ngain = (int)g;
+    if (p->gm == 2) {
+      // the cell of each gain ordinal, for the density-matrix passes
+      std::vector<uint32_t> glist(g);
+      for (size_t o = 0; o < nc; ++o)
+        if (p->mats[p->host_map[o]].gain) glist[p->gidx[o]] = (uint32_t)o;
+      if (g) HIPCHK(hipMemcpyAsync(p->arena + L.glist, glist.data(), sizeof(uint32_t) * g, hipMemcpyHostToDevice, st));
+    }
+    HIPCHK(hipMemcpyAsync(p->ddesc, &d, sizeof d, hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
   }
 
@@ -1082,13 +1208,15 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
         long long ngain = 0;
         if (p->has_gain)
           for (int k = t.k0; k < t.k1; ++k) ngain += blk_gain[(size_t)k * p->nblk + t.blk];
-        const bool gain = ngain > 0;
+        // density-matrix plans step with the classes without gain: the matter
+        // has passes of its own after the step kernels
+        const bool gain = ngain > 0 && p->gm != 2;
         const int nxt_ = iend - t.i0, nyt_ = jend - t.j0, nzt_ = t.k1 - t.k0;
         const double slab_cells = (double)slab_count(0, t.i0, iend) * nyt_ * nzt_ +
                                   (double)nxt_ * slab_count(1, t.j0, jend) * nzt_ +
                                   (double)nxt_ * nyt_ * slab_count(2, t.k0, t.k1);
         // algorithmic bytes of the tile, plus the plane below it that it also stages
-        tcost.push_back(49.0 * nxt_ * nyt_ * (nzt_ + 1) + 32.0 * slab_cells + gain_cell_bytes(p->gm) * (double)ngain);
+        tcost.push_back(49.0 * nxt_ * nyt_ * (nzt_ + 1) + 32.0 * slab_cells + (gain ? 84.0 * (double)ngain : 0.0));
         tcls.push_back({pml, gain ? 1 : 0});
         all.push_back(t);
       }
@@ -1133,6 +1261,7 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
   p->ddft = at<fd_dft_tile>(p, L.dft);
   if (!p->dft.empty())
     HIPCHK(hipMemcpyAsync(p->ddft, p->dft.data(), sizeof(fd_dft_tile) * p->dft.size(), hipMemcpyHostToDevice, st));
+  if (int r = build_dm_units(p)) return r;
   HIPCHK(hipStreamSynchronize(st));
   p->step = 0;
   p->ntst = p->tune.stores == FDTD_STORES_NONTEMPORAL ? 1
@@ -1422,7 +1551,8 @@ int fdtd_class_cells(const fdtd_plan* p, int64_t* cells) {
   int64_t pts = 0;
   for (const Flux& f : p->flux)
     if (f.nf > 0) pts += plane;
-  cells[FD_NCLASS] = pts;
+  cells[FD_KERNEL_DFT] = pts;
+  for (int q = 0; q < 4; ++q) cells[FD_KERNEL_DM + q] = p->dm_cells[q];
   return FDTD_OK;
 }
 
@@ -1444,8 +1574,7 @@ int fdtd_class_bytes(const fdtd_plan* p, double* bytes) {
             double b = 49.0;
             b += 32.0 * ((in_slab(0, i) ? 1 : 0) + (in_slab(1, j) ? 1 : 0) + (in_slab(2, k) ? 1 : 0));
             const uint8_t m = p->host_map[((size_t)k * ny + j) * nx + i];
-            if (p->mats[m].gain) b += gain_cell_bytes(p->gm);
-            if (c >= FD_CLASS_GAIN) b += 4.0;  // the cell's gain ordinal
+            if (c >= FD_CLASS_GAIN) b += 4.0 + (p->mats[m].gain ? 84.0 : 0.0);  // ordinal and Lorentz state
             acc += b;
           }
     bytes[c] = acc;
@@ -1455,7 +1584,8 @@ int fdtd_class_bytes(const fdtd_plan* p, double* bytes) {
   double dft = 0.0;
   for (const Flux& f : p->flux)
     if (f.nf > 0) dft += (double)nx * ny * (40.0 + (128.0 * f.nf + 16.0 * FD_DFT_RING) / FD_DFT_RING);
-  bytes[FD_NCLASS] = dft;
+  bytes[FD_KERNEL_DFT] = dft;
+  for (int q = 0; q < 4; ++q) bytes[FD_KERNEL_DM + q] = p->dm_bytes[q];
   return FDTD_OK;
 }
 
@@ -1492,16 +1622,34 @@ int fdtd_time_kernels(fdtd_plan* p, int64_t n, void* stream, double* ms, int64_t
       const int grid = p->tune.max_blocks > 0 ? std::min(nt, p->tune.max_blocks) : p->pgrid[c];
       const fd_xcd* pc = p->tune.max_blocks > 0 ? nullptr : &p->part[c];
       const int r = record(c, [&](hipEvent_t a, hipEvent_t b) {
-        return fd_launch_step(c, p->dtiles[c], nt, p->tune.tile_x, p->tune.block, grid, (int)s, pc, p->ntst,
-                              p->gm ? p->gm : 1, st, a, b);
+        return fd_launch_step(c, p->dtiles[c], nt, p->tune.tile_x, p->tune.block, grid, (int)s, pc, p->ntst, st, a,
+                              b);
       });
       if (r) { cleanup(); return r; }
     }
     if (plan_dft_due(p, p->step + s) && !p->dft.empty()) {
-      const int r = record(FD_NCLASS, [&](hipEvent_t a, hipEvent_t b) {
+      const int r = record(FD_KERNEL_DFT, [&](hipEvent_t a, hipEvent_t b) {
         return fd_launch_dft(p->ddft, (int)p->dft.size(), (int)s, st, a, b);
       });
       if (r) { cleanup(); return r; }
+    }
+    const DmLaunch dm = plan_dm(p);
+    if (dm.n[0] > 0) {
+      hipEvent_t ev[8];
+      for (int q = 0; q < 4; ++q) {
+        Rec r{FD_KERNEL_DM + q, nullptr, nullptr};
+        if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) {
+          cleanup();
+          return fail(FDTD_EHIP, "time_kernels: hipEventCreate");
+        }
+        ev[2 * q] = r.a;
+        ev[2 * q + 1] = r.b;
+        if (q < 2 || dm.n[q - 1] > 0) recs.push_back(r);
+        else { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); ev[2 * q] = ev[2 * q + 1] = nullptr; }
+      }
+      const hipError_t e = fd_launch_dm(dm.u[0], dm.n[0], dm.u[1], dm.n[1], dm.u[2], dm.n[2], p->tune.block, (int)s,
+                                        st, ev);
+      if (e != hipSuccess) { cleanup(); return fail(FDTD_EHIP, "time_kernels: %s", hipGetErrorString(e)); }
     }
   }
   hipError_t e = fd_launch_advance_one(p->ddesc, n, st);
@@ -1511,7 +1659,7 @@ int fdtd_time_kernels(fdtd_plan* p, int64_t n, void* stream, double* ms, int64_t
     return fail(FDTD_EHIP, "time_kernels: %s", hipGetErrorString(e));
   }
   p->step += n;
-  for (int c = 0; c <= FD_NCLASS; ++c) {
+  for (int c = 0; c < FD_NKERNEL; ++c) {
     ms[c] = 0.0;
     launches[c] = 0;
   }
@@ -1652,11 +1800,16 @@ void batch_layout(fdtd_batch* b, fdtd_plan* const* plans, int32_t n, int gm) {
     b->maxnf = std::max(b->maxnf, p->maxnf);
   }
   for (int c = 0; c < FD_NCLASS; ++c) b->part[c] = xcd_partition(bcost[c], &b->pgrid[c]);
+  for (int q = 0; q < 3; ++q) {
+    b->dmu[q].clear();
+    for (fdtd_plan* p : b->plans) b->dmu[q].insert(b->dmu[q].end(), p->dmu[q].begin(), p->dmu[q].end());
+  }
 }
 
 // Device bytes of the batch's launch tables (tile lists, DFT units, descriptor
 // pointers) and their offsets.
-size_t batch_table_bytes(const fdtd_batch* b, size_t off_t[FD_NCLASS], size_t* off_d, size_t* off_p) {
+size_t batch_table_bytes(const fdtd_batch* b, size_t off_t[FD_NCLASS], size_t* off_d, size_t* off_p,
+                         size_t off_m[3]) {
   size_t bytes = 0;
   for (int c = 0; c < FD_NCLASS; ++c) {
     off_t[c] = bytes;
@@ -1664,6 +1817,10 @@ size_t batch_table_bytes(const fdtd_batch* b, size_t off_t[FD_NCLASS], size_t* o
   }
   *off_d = bytes;
   bytes = align256(bytes + sizeof(fd_dft_tile) * std::max<size_t>(b->dft.size(), 1));
+  for (int q = 0; q < 3; ++q) {
+    off_m[q] = bytes;
+    bytes = align256(bytes + sizeof(fd_dm_unit) * b->dmu[q].size());
+  }
   *off_p = bytes;
   return align256(bytes + sizeof(fd_desc*) * b->plans.size());
 }
@@ -1679,8 +1836,8 @@ void batch_drop_graphs(fdtd_batch* b) {
 // Writes the launch tables of b's members to b->dmem (b->dcap bytes, the
 // caller has checked they fit) and points the launch arguments at them.
 int batch_upload(fdtd_batch* b) {
-  size_t off_t[FD_NCLASS], off_d, off_p;
-  (void)batch_table_bytes(b, off_t, &off_d, &off_p);
+  size_t off_t[FD_NCLASS], off_d, off_p, off_m[3];
+  (void)batch_table_bytes(b, off_t, &off_d, &off_p, off_m);
   uint8_t* base = (uint8_t*)b->dmem;
   std::vector<fd_desc*> dl;
   for (fdtd_plan* p : b->plans) dl.push_back(p->ddesc);
@@ -1692,6 +1849,11 @@ int batch_upload(fdtd_batch* b) {
   b->ddft = (fd_dft_tile*)(base + off_d);
   if (!b->dft.empty())
     HIPCHK(hipMemcpy(b->ddft, b->dft.data(), sizeof(fd_dft_tile) * b->dft.size(), hipMemcpyHostToDevice));
+  for (int q = 0; q < 3; ++q) {
+    b->ddm[q] = (fd_dm_unit*)(base + off_m[q]);
+    if (!b->dmu[q].empty())
+      HIPCHK(hipMemcpy(b->ddm[q], b->dmu[q].data(), sizeof(fd_dm_unit) * b->dmu[q].size(), hipMemcpyHostToDevice));
+  }
   b->ddescs = (fd_desc**)(base + off_p);
   HIPCHK(hipMemcpy(b->ddescs, dl.data(), sizeof(fd_desc*) * dl.size(), hipMemcpyHostToDevice));
   return FDTD_OK;
@@ -1720,8 +1882,8 @@ int fdtd_batch_create(fdtd_plan* const* plans, int32_t n, const fdtd_tuning* t, 
   // grid gains.
   b->ntst = bt.stores == FDTD_STORES_NONTEMPORAL ? 1 : 0;
   batch_layout(b.get(), plans, n, gm);
-  size_t off_t[FD_NCLASS], off_d, off_p;
-  const size_t bytes = batch_table_bytes(b.get(), off_t, &off_d, &off_p);
+  size_t off_t[FD_NCLASS], off_d, off_p, off_m[3];
+  const size_t bytes = batch_table_bytes(b.get(), off_t, &off_d, &off_p, off_m);
   // Set-up allocation of the batch's launch tables (small; grown by
   // fdtd_batch_set_members only when a member list needs more; freed by destroy).
   HIPCHK(hipMalloc(&b->dmem, bytes));
@@ -1752,8 +1914,8 @@ int fdtd_batch_create_static(fdtd_plan* const* plans, int32_t n, const fdtd_tuni
   b->graph_steps = bt.graph_steps;
   b->ntst = bt.stores == FDTD_STORES_NONTEMPORAL ? 1 : 0;
   batch_layout(b.get(), plans, n, gm);
-  size_t off_t[FD_NCLASS], off_d, off_p;
-  const size_t bytes = batch_table_bytes(b.get(), off_t, &off_d, &off_p);
+  size_t off_t[FD_NCLASS], off_d, off_p, off_m[3];
+  const size_t bytes = batch_table_bytes(b.get(), off_t, &off_d, &off_p, off_m);
   if (bytes > FD_STATIC_TABLE_BYTES)
     return fail(FDTD_ENOMEM, "batch launch tables of %zu bytes exceed the static maximum of %zu", bytes,
                 (size_t)FD_STATIC_TABLE_BYTES);
@@ -1789,8 +1951,8 @@ int fdtd_batch_set_members(fdtd_batch* b, fdtd_plan* const* plans, int32_t n, vo
   HIPCHK(hipStreamSynchronize((hipStream_t)stream));
   fdtd_batch next;
   batch_layout(&next, plans, n, gm);
-  size_t off_t[FD_NCLASS], off_d, off_p;
-  const size_t bytes = batch_table_bytes(&next, off_t, &off_d, &off_p);
+  size_t off_t[FD_NCLASS], off_d, off_p, off_m[3];
+  const size_t bytes = batch_table_bytes(&next, off_t, &off_d, &off_p, off_m);
   if (bytes > b->dcap) {
     if (!b->owns_dmem) return fail(FDTD_ENOMEM, "member tables of %zu bytes exceed the %zu available", bytes, b->dcap);
     void* grown = nullptr;
@@ -1818,10 +1980,20 @@ static bool batch_dft_due(const fdtd_batch* b, int64_t s) {
   return false;
 }
 
+static DmLaunch batch_dm(const fdtd_batch* b) {
+  DmLaunch l;
+  for (int q = 0; q < 3; ++q) {
+    l.u[q] = b->ddm[q];
+    l.n[q] = (int)b->dmu[q].size();
+  }
+  return l;
+}
+
 static int batch_enqueue(fdtd_batch* b, int64_t n, hipStream_t st, Fork* fk) {
   for (int64_t s = 0; s < n; ++s) {
     const int r = enqueue_step(b->dtiles, b->tiles, b->part, b->pgrid, b->tile_x, b->block, b->max_blocks, b->ddft,
-                               (int)b->dft.size(), b->maxnf, batch_dft_due(b, s), (int)s, b->ntst, b->gm, st, fk);
+                               (int)b->dft.size(), b->maxnf, batch_dft_due(b, s), (int)s, b->ntst, batch_dm(b), st,
+                               fk);
     if (r) return r;
   }
   HIPCHK(fd_launch_advance(b->ddescs, (int)b->plans.size(), n, st));
@@ -1913,14 +2085,24 @@ int fdtd_batch_time_kernels(fdtd_batch* b, int64_t n, void* stream, double* ms, 
       const fd_xcd* pc = b->max_blocks > 0 ? nullptr : &b->part[c];
       hipEvent_t a, z;
       if (int r = pair(c, &a, &z)) { cleanup(); return r; }
-      const hipError_t e = fd_launch_step(c, b->dtiles[c], nt, b->tile_x, b->block, grid, (int)s, pc, b->ntst, b->gm,
-                                          st, a, z);
+      const hipError_t e = fd_launch_step(c, b->dtiles[c], nt, b->tile_x, b->block, grid, (int)s, pc, b->ntst, st,
+                                          a, z);
       if (e != hipSuccess) { cleanup(); return fail(FDTD_EHIP, "batch_time_kernels: %s", hipGetErrorString(e)); }
     }
     if (batch_dft_due(b, s) && !b->dft.empty()) {
       hipEvent_t a, z;
-      if (int r = pair(FD_NCLASS, &a, &z)) { cleanup(); return r; }
+      if (int r = pair(FD_KERNEL_DFT, &a, &z)) { cleanup(); return r; }
       const hipError_t e = fd_launch_dft(b->ddft, (int)b->dft.size(), (int)s, st, a, z);
+      if (e != hipSuccess) { cleanup(); return fail(FDTD_EHIP, "batch_time_kernels: %s", hipGetErrorString(e)); }
+    }
+    const DmLaunch dm = batch_dm(b);
+    if (dm.n[0] > 0) {
+      hipEvent_t ev[8] = {};
+      for (int q = 0; q < 4; ++q)
+        if (q < 2 || dm.n[q - 1] > 0)
+          if (int r = pair(FD_KERNEL_DM + q, &ev[2 * q], &ev[2 * q + 1])) { cleanup(); return r; }
+      const hipError_t e = fd_launch_dm(dm.u[0], dm.n[0], dm.u[1], dm.n[1], dm.u[2], dm.n[2], b->block, (int)s, st,
+                                        ev);
       if (e != hipSuccess) { cleanup(); return fail(FDTD_EHIP, "batch_time_kernels: %s", hipGetErrorString(e)); }
     }
   }
@@ -1931,7 +2113,7 @@ int fdtd_batch_time_kernels(fdtd_batch* b, int64_t n, void* stream, double* ms, 
     return fail(FDTD_EHIP, "batch_time_kernels: %s", hipGetErrorString(e));
   }
   for (fdtd_plan* p : b->plans) p->step += n;
-  for (int c = 0; c <= FD_NCLASS; ++c) {
+  for (int c = 0; c < FD_NKERNEL; ++c) {
     ms[c] = 0.0;
     launches[c] = 0;
   }

@@ -68,6 +68,13 @@ struct fd_desc {
   // Im rho_01..03, Re rho_12, rho_13, rho_23, Im rho_12, rho_13, rho_23.
   float* pop;
   const uint32_t* gidx;
+  // Density matrix (held at the cell centre): the cell of each gain ordinal, and
+  // per ordinal the polarization increment of the predictor (dmq[0]) and of the
+  // corrector (dmq[1]), 3 planes each, both including the noise current's dt J
+  const uint32_t* glist;
+  float* dmq[2];
+  int ngain;
+  int tile_x;  // xy tile width of the plan's step tiles (the T(t) partial slots)
   uint32_t key0, key1;
   // CPML
   int pml_lo[3], pml_hi[3], pml_t[3];
@@ -124,12 +131,26 @@ struct fd_dft_tile {
   int pad;
 };
 
+// Work unit of the density-matrix passes: cells [first, first + count) of one
+// plan (gain ordinals for the cell passes, flattened cell indices for the edge
+// pass); for the diagnostics pass first = flux plane (-1: probes), count = xy tile.
+struct fd_dm_unit {
+  const fd_desc* d;
+  int first, count;
+  int pad;
+};
+#define FD_DM_CELLS 256   // gain cells per unit of the cell passes (one per thread)
+#define FD_DM_EDGES 1024  // cells per unit of the edge pass (4 per thread)
+
 // Tile classes: kernels specialised on the CPML slabs a tile touches (none, z
 // only, any axis) and on gain cells being present.  class = cpml + 3 * gain.
 enum {
   FD_CLASS_PLAIN = 0, FD_CLASS_PMLZ = 1, FD_CLASS_PML = 2,
   FD_CLASS_GAIN = 3, FD_CLASS_PMLZ_GAIN = 4, FD_CLASS_PML_GAIN = 5, FD_NCLASS = 6
 };
+// Kernels of a step as the timing and byte counts list them: the six step
+// classes, the DFT, then the four density-matrix passes.
+enum { FD_KERNEL_DFT = FD_NCLASS, FD_KERNEL_DM = FD_NCLASS + 1, FD_NKERNEL = FD_NCLASS + 5 };
 
 // Launchers (kernels.hip).
 // A launch's tile list split into 8 contiguous parts of about equal cost, one
@@ -142,9 +163,10 @@ struct fd_xcd {
 // part == nullptr: grid-stride loop over the tiles with the plain XCD renumbering
 // start / stop (optional): events that take the kernel's own begin and end timestamps
 // nt: non-temporal field stores (the launch's working set exceeds the Infinity Cache)
-// gm: gain model of the gain classes (1 Lorentz, 2 density matrix)
+// Gain classes run the Lorentz medium; density-matrix plans step with the
+// classes without gain and add the fd_launch_dm passes.
 hipError_t fd_launch_step(int cls, const fd_tile* tiles, int ntiles, int tile_x, int block, int grid,
-                          int s, const fd_xcd* part, int nt, int gm, hipStream_t st, hipEvent_t start = nullptr,
+                          int s, const fd_xcd* part, int nt, hipStream_t st, hipEvent_t start = nullptr,
                           hipEvent_t stop = nullptr);
 hipError_t fd_launch_dft(const fd_dft_tile* tiles, int ntiles, int s, hipStream_t st, hipEvent_t start = nullptr,
                          hipEvent_t stop = nullptr);
@@ -157,6 +179,12 @@ hipError_t fd_launch_voxelize(const int64_t* sites, int ex, int ey, int ez, cons
                               const int* ncr, const int* origin, const int64_t* reach,
                               int res, int mat_bg, int mat_void, int mat_out,
                               int nx, int ny, int nz, uint8_t* map, hipStream_t st);
+// Density-matrix passes of one step (after the step kernels have left A, the
+// field before the polarization change, on every edge): predictor, corrector
+// (writes rho^{n+1}), edges (E^{n+1} = A - [Q]/eps), then probes and T(t).
+hipError_t fd_launch_dm(const fd_dm_unit* cells, int ncells, const fd_dm_unit* edges, int nedges,
+                        const fd_dm_unit* diag, int ndiag, int block, int s, hipStream_t st,
+                        hipEvent_t* ev = nullptr);
 hipError_t fd_launch_init_pop(const uint8_t* map, const float* n_init_by_mat, const uint32_t* gidx, unsigned gainmask,
                               float* pop, int ncell, hipStream_t st);
 

@@ -1,8 +1,8 @@
-// gfx950 kernels of libfdtd: one fused Yee step (H then E, CPML, the gain media
-// -- Lorentz ADE with four-level populations, or the density matrix of a ground
-// level and three degenerate upper levels -- noise, soft sources, probes,
-// transmitted power, energy), the running-DFT flux update, the integer
-// voxelizer and small helpers.
+// gfx950 kernels of libfdtd: one fused Yee step (H then E, CPML, the Lorentz
+// gain medium -- ADE with four-level populations and noise -- soft sources,
+// probes, transmitted power, energy), the passes of the density-matrix gain
+// medium (a ground level and three degenerate upper levels, held at the cell
+// centre), the running-DFT flux update, the integer voxelizer and small helpers.
 //
 // Method: C. Conti and A. Fratalocchi, arXiv:0802.3775 — Yee FDTD with absorbing
 // walls in a disordered inverted opal, pumped gain medium seeded by a stochastic
@@ -11,8 +11,9 @@
 //
 // Stepping scheme.  E, H, the H-side CPML memory and the Lorentz polarization
 // are double-buffered by step parity, so one step reads only buffer n&1 and
-// writes only the other one (the E-side CPML memory, the populations and the
-// density matrix are read and written only by their own cell's thread).  Every tile is therefore independent within a step, and a
+// writes only the other one (the E-side CPML memory and the populations are read
+// and written only by their own cell's thread).  Every tile is therefore
+// independent within a step, and a
 // workgroup can recompute the H^{n+1/2} values its E update needs at x-1, y-1 and
 // z-1 from the read-only inputs instead of waiting for the owner: one pass over
 // HBM per step (E, H, material index in; E, H out).
@@ -688,10 +689,9 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         }
       }
     }
-    // gain-cell inputs of plane k (Lorentz: populations, P^n, P^{n-1}; density
-    // matrix: its 18 floats), consumed in the E update; other lanes read element 0
+    // gain-cell inputs of plane k (populations, P^n, P^{n-1}), consumed in the E
+    // update; other lanes read element 0
     float gnh[3], gnl[3], gPn[3], gPm[3];
-    float gq[12];
     bool gk = false;
     if (GAIN) {
       gk = act && ((gmask >> S.m) & 1u);
@@ -702,15 +702,10 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         gnh[q] = pop[(size_t)q * ncs + ig];
         gnl[q] = pop[(size_t)(3 + q) * ncs + ig];
       }
-      if (GAIN == 1) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          gPn[q] = G((const float*)d->P[par][q])[ig];
-          gPm[q] = G((const float*)d->P[par ^ 1][q])[ig];
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < 12; ++q) gq[q] = pop[(size_t)(6 + q) * ncs + ig];
+      for (int q = 0; q < 3; ++q) {
+        gPn[q] = G((const float*)d->P[par][q])[ig];
+        gPm[q] = G((const float*)d->P[par ^ 1][q])[ig];
       }
     }
     // the loads two planes ahead go out after this plane's psi and gain inputs:
@@ -847,17 +842,6 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
           nl[q] = gnl[q];
         }
       }
-      // density matrix of the cell (populations p, their increments, coherences)
-      float dmp[3] = {0.0f, 0.0f, 0.0f}, dminc[3] = {0.0f, 0.0f, 0.0f};
-      Cz dmc[3], dmx[3];
-      if (GAIN == 2) {
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          dmp[q] = nh[q] + nl[q];
-          dmc[q] = {gq[q], gq[3 + q]};
-          dmx[q] = {gq[6 + q], gq[9 + q]};
-        }
-      }
       if (GAIN == 1 && g) {
         const float n1 = nh[0] + nl[0], n2 = nh[1] + nl[1];
         float F[3] = {0.0f, 0.0f, 0.0f};
@@ -888,13 +872,6 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         if (sc == 0) cx += v;
         else if (sc == 1) cy += v;
         else cz += v;
-      }
-      if (GAIN == 2 && g && mt.noise != 0.0f) {  // spontaneous-emission current on E
-        float gg[3];
-        normals3((uint32_t)n, (uint32_t)o, d->key0, d->key1, gg);
-        cx += mt.noise * sqrtf(fmaxf(dmp[0], 0.0f)) * gg[0];
-        cy += mt.noise * sqrtf(fmaxf(dmp[1], 0.0f)) * gg[1];
-        cz += mt.noise * sqrtf(fmaxf(dmp[2], 0.0f)) * gg[2];
       }
       // av: E^{n+1} without the polarization current; on: not a PEC-held component
       float av[3] = {0.0f, 0.0f, 0.0f};
@@ -949,30 +926,6 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         on[2] = true;
       }
       }
-      if (GAIN == 2 && g) {
-        // one predictor-corrector pass of the implicit midpoint coupling:
-        // rho^{n+1} = R C(E_mid) R rho^n with E_mid = (E^n + E^{n+1}) / 2
-        const float Pn[3] = {mt.bk2 * dmc[0].r, mt.bk2 * dmc[1].r, mt.bk2 * dmc[2].r};
-        dm_relax(mt, dmp, dminc, dmc, dmx);
-        float em[3];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) em[q] = 0.5f * (eo[q] + av[q]);
-        {
-          Cz cp[3] = {dmc[0], dmc[1], dmc[2]};
-          Cz xp[3] = {dmx[0], dmx[1], dmx[2]};
-          float pp[3] = {dmp[0], dmp[1], dmp[2]}, ip[3] = {0.0f, 0.0f, 0.0f};
-          dm_cayley<false>(mt, em, pp, ip, cp, xp);
-#pragma unroll
-          for (int q = 0; q < 3; ++q) {
-            const float es = on[q] ? av[q] - (mt.bk2 * (cp[q].r * mt.bf2) - Pn[q]) * mt.inv_eps : 0.0f;
-            em[q] = 0.5f * (eo[q] + es);
-          }
-        }
-        dm_cayley<true>(mt, em, dmp, dminc, dmc, dmx);
-        dm_relax(mt, dmp, dminc, dmc, dmx);
-#pragma unroll
-        for (int q = 0; q < 3; ++q) dP[q] = mt.bk2 * dmc[q].r - Pn[q];
-      }
       if (GAIN == 0) {
         // no polarization current: av is E^{n+1} (0 where a PEC wall holds it),
         // bit for bit what av - 0 / eps gives
@@ -987,21 +940,6 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       put(x.Eout[0], o, ex_n);
       put(x.Eout[1], o, ey_n);
       put(x.Eout[2], o, ez_n);
-      if (GAIN == 2 && g) {
-        const int nc = d->ncell;
-        const uint32_t q = S.gi;
-        gf* pop = G(d->pop);
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-          two_sum(nh[r], nl[r], dminc[r]);
-          pop[(size_t)r * nc + q] = nh[r];
-          pop[(size_t)(3 + r) * nc + q] = nl[r];
-          pop[(size_t)(6 + r) * nc + q] = dmc[r].r;
-          pop[(size_t)(9 + r) * nc + q] = dmc[r].i;
-          pop[(size_t)(12 + r) * nc + q] = dmx[r].r;
-          pop[(size_t)(15 + r) * nc + q] = dmx[r].i;
-        }
-      }
       if (GAIN == 1 && g) {
         const float en[3] = {ex_n, ey_n, ez_n};
         float u = 0.0f;
@@ -1095,10 +1033,9 @@ template <int TX, int PM, int GAIN, bool NT>
 __device__ __forceinline__ void step_body(const fd_tile* __restrict__ tiles, int ntiles, int s, const fd_xcd& part,
                                           int use_part, Lds<TX>& lds) {
   // z-only CPML launches specialise their interior tiles; the all-axes kernel
-  // and the density-matrix kernels keep one general march (two would not fit
-  // their register budget)
+  // keeps one general march (two would not fit its register budget)
   auto run = [&](const fd_tile& tl) {
-    if constexpr (PM == 4 && GAIN != 2) {
+    if constexpr (PM == 4) {
       if (!(tl.flags & FD_TILE_ZSLAB)) {
         run_tile<TX, PM, GAIN, false, NT>(tl, s, lds);
         return;
@@ -1134,16 +1071,6 @@ __global__ __launch_bounds__(FD_MAXBLOCK) __attribute__((amdgpu_waves_per_eu(4))
     const fd_tile* __restrict__ tiles, int ntiles, int s, fd_xcd part, int use_part) {
   __shared__ Lds<TX> lds;
   step_body<TX, 7, 0, NT>(tiles, ntiles, s, part, use_part, lds);
-}
-
-// Density-matrix gain: the register budget is capped at three waves per SIMD
-// (168 VGPRs); left alone the compiler takes a few more and drops to two waves,
-// which measured 20% slower on the lasing box.
-template <int TX, int PM>
-__global__ __launch_bounds__(FD_MAXBLOCK) __attribute__((amdgpu_waves_per_eu(3))) void step_kernel_dm(
-    const fd_tile* __restrict__ tiles, int ntiles, int s, fd_xcd part, int use_part) {
-  __shared__ Lds<TX> lds;
-  step_body<TX, PM, 2, false>(tiles, ntiles, s, part, use_part, lds);
 }
 
 // ------------------------------------------------------------- flux DFT
@@ -1431,17 +1358,274 @@ __global__ void init_pop_kernel(const uint8_t* __restrict__ map, const float* __
   }
 }
 
+// ------------------------------------- density matrix at the cell centres
+// A density-matrix gain cell holds rho at its centre (i+1/2, j+1/2, k+1/2), where
+// the paper solves the density-matrix equations.  The step kernels leave on
+// every edge A = E^n + dt/(eps dx) (curl H - dx J_src), the field before the
+// polarization change.  With <F> the average of the four edges of a component
+// around a centre and [Q] on an edge a quarter of the sum of Q over the (up to
+// four) gain cells sharing it -- the adjoint of <.>, so the field gives the
+// matter exactly the energy the matter takes -- the matter then makes one
+// predictor-corrector pass of the implicit midpoint coupling:
+//   predictor  rho* = S(rho^n; <(E^n + A)/2>),   Q* = P(rho*) - P(rho^n) + dt J
+//   corrector  E* = A - [Q*]/eps,  rho^{n+1} = S(rho^n; <(E^n + E*)/2>),
+//              Q = P(rho^{n+1}) - P(rho^n) + dt J
+//   edges      E^{n+1} = A - [Q]/eps
+// with S = R(dt/2) C(E) R(dt/2), P_c = 2 kappa Re rho_0c, J the
+// spontaneous-emission noise current at the centre and eps that of the edge's
+// own voxel.  Each pass reads what the previous one wrote for neighbouring
+// cells, so the passes are separate launches; a cell's rho is read and written
+// only by its own thread.
+
+// material m of the plan (a gain cell's own medium, an edge's permittivity)
+typedef __attribute__((address_space(1))) const fd_mat gmat_t;
+__device__ __forceinline__ fd_mat gmat(const cdesc* d, int m) {
+  fd_mat out;
+  const gf* src = (const gf*)((gmat_t*)d->mats + m);
+  float* dst = reinterpret_cast<float*>(&out);
+#pragma unroll
+  for (int q = 0; q < (int)(sizeof(fd_mat) / 4); ++q) dst[q] = src[q];
+  return out;
+}
+__device__ __forceinline__ float ginv_eps(const cdesc* d, int m) { return ((gmat_t*)d->mats)[m].inv_eps; }
+
+struct Ijk {
+  int i, j, k;
+};
+__device__ __forceinline__ Ijk ijk_of(const cdesc* d, uint32_t o) {
+  const uint32_t plane = (uint32_t)d->plane, nx = (uint32_t)d->nx;
+  const uint32_t k = o / plane, r = o - k * plane, j = r / nx;
+  return {(int)(r - j * nx), (int)j, (int)k};
+}
+
+// Flattened index of the cell at p shifted by (u, v) along the two axes
+// transverse to component c ((c+1) mod 3, (c+2) mod 3), after periodic wrap;
+// -1 beyond a PEC wall.
+__device__ __forceinline__ int shifted(const cdesc* d, int c, Ijk p, int u, int v) {
+  int q[3] = {p.i, p.j, p.k};
+  q[(c + 1) % 3] += u;
+  q[(c + 2) % 3] += v;
+  const int a = wrap(q[0], d->nx, d->per[0]), b = wrap(q[1], d->ny, d->per[1]), z = wrap(q[2], d->nz, d->per[2]);
+  return (a < 0 || b < 0 || z < 0) ? -1 : (z * d->ny + b) * d->nx + a;
+}
+
+// Component c of voxel p lies on a PEC wall (index 0 of a non-periodic
+// transverse axis) and is held at zero.
+__device__ __forceinline__ bool held_edge(const cdesc* d, int c, Ijk p) {
+  const int q[3] = {p.i, p.j, p.k};
+  const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+  return (!d->per[a1] && q[a1] == 0) || (!d->per[a2] && q[a2] == 0);
+}
+
+// [Q] of component c's edge of voxel p: a quarter of Q over the gain cells at
+// offsets {0, -1} along the transverse axes; *any: some such cell has gain.
+__device__ __forceinline__ float edge_share(const cdesc* d, const gf* Q, int c, Ijk p, bool* any) {
+  const gu8* map = (const gu8*)d->mat;
+  const __attribute__((address_space(1))) uint32_t* gidx = (const __attribute__((address_space(1))) uint32_t*)d->gidx;
+  const size_t ncs = (size_t)d->ncell;
+  float acc = 0.0f;
+  bool hit = false;
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int cc = shifted(d, c, p, -u, -v);
+      if (cc < 0 || !((d->gainmask >> map[cc]) & 1u)) continue;
+      acc += Q[(size_t)c * ncs + gidx[cc]];
+      hit = true;
+    }
+  *any = hit;
+  return 0.25f * acc;
+}
+
+// A gain cell's state (populations as (hi, lo) FP32 pairs, coherences), its
+// noise term dt J and P(rho^n).
+struct DmCell {
+  uint32_t g, o;
+  Ijk p;
+  fd_mat mt;
+  float nh[3], nl[3], pp[3], inc[3];
+  Cz c[3], x[3];
+  float Pn[3], dJ[3];
+};
+
+__device__ __forceinline__ void dm_load(const cdesc* d, uint32_t g, long long n, DmCell& z) {
+  const size_t ncs = (size_t)d->ncell;
+  const gf* pop = G((const float*)d->pop);
+  z.g = g;
+  z.o = ((const __attribute__((address_space(1))) uint32_t*)d->glist)[g];
+  z.p = ijk_of(d, z.o);
+  z.mt = gmat(d, ((const gu8*)d->mat)[z.o]);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    z.nh[q] = pop[(size_t)q * ncs + g];
+    z.nl[q] = pop[(size_t)(3 + q) * ncs + g];
+    z.pp[q] = z.nh[q] + z.nl[q];
+    z.inc[q] = 0.0f;
+    z.c[q] = {pop[(size_t)(6 + q) * ncs + g], pop[(size_t)(9 + q) * ncs + g]};
+    z.x[q] = {pop[(size_t)(12 + q) * ncs + g], pop[(size_t)(15 + q) * ncs + g]};
+    z.Pn[q] = z.mt.bk2 * z.c[q].r;
+    z.dJ[q] = 0.0f;
+  }
+  if (z.mt.noise != 0.0f) {
+    float gg[3];
+    normals3((uint32_t)n, z.o, d->key0, d->key1, gg);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) z.dJ[q] = z.mt.noise * sqrtf(fmaxf(z.pp[q], 0.0f)) * gg[q];
+  }
+}
+
+// <F> of component c around cell p's centre (edges beyond a PEC wall hold 0).
+__device__ __forceinline__ float centre_avg(const cdesc* d, const gf* F, int c, Ijk p) {
+  float acc = 0.0f;
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int e = shifted(d, c, p, u, v);
+      if (e >= 0) acc += F[e];
+    }
+  return 0.25f * acc;
+}
+
+__global__ __launch_bounds__(FD_DM_CELLS) void dm_predict_kernel(const fd_dm_unit* __restrict__ units, int s) {
+  const fd_dm_unit u = units[blockIdx.x];
+  if ((int)threadIdx.x >= u.count) return;
+  const cdesc* d = (const cdesc*)u.d;
+  const long long n = d->step + s;
+  const int par = (int)(n & 1);
+  DmCell z;
+  dm_load(d, (uint32_t)(u.first + (int)threadIdx.x), n, z);
+  float em[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+    em[q] = 0.5f * (centre_avg(d, G((const float*)d->E[par][q]), q, z.p) +
+                    centre_avg(d, G((const float*)d->E[par ^ 1][q]), q, z.p));
+  dm_relax(z.mt, z.pp, z.inc, z.c, z.x);
+  dm_cayley<false>(z.mt, em, z.pp, z.inc, z.c, z.x);
+  gf* Q = G(d->dmq[0]);
+  const size_t ncs = (size_t)d->ncell;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) Q[(size_t)q * ncs + z.g] = z.mt.bk2 * (z.c[q].r * z.mt.bf2) - z.Pn[q] + z.dJ[q];
+}
+
+__global__ __launch_bounds__(FD_DM_CELLS) void dm_correct_kernel(const fd_dm_unit* __restrict__ units, int s) {
+  const fd_dm_unit u = units[blockIdx.x];
+  if ((int)threadIdx.x >= u.count) return;
+  const cdesc* d = (const cdesc*)u.d;
+  const long long n = d->step + s;
+  const int par = (int)(n & 1);
+  DmCell z;
+  dm_load(d, (uint32_t)(u.first + (int)threadIdx.x), n, z);
+  const gf* Qs = G((const float*)d->dmq[0]);
+  const gu8* map = (const gu8*)d->mat;
+  float em[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const gf* A = G((const float*)d->E[par ^ 1][q]);
+    float acc = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int e = shifted(d, q, z.p, a, b);
+        if (e < 0) continue;
+        const Ijk pe = ijk_of(d, (uint32_t)e);
+        if (held_edge(d, q, pe)) continue;
+        bool any;
+        const float sh = edge_share(d, Qs, q, pe, &any);
+        acc += A[e] - sh * ginv_eps(d, map[e]);  // E* of the edge
+      }
+    em[q] = 0.5f * (centre_avg(d, G((const float*)d->E[par][q]), q, z.p) + 0.25f * acc);
+  }
+  dm_relax(z.mt, z.pp, z.inc, z.c, z.x);
+  dm_cayley<true>(z.mt, em, z.pp, z.inc, z.c, z.x);
+  dm_relax(z.mt, z.pp, z.inc, z.c, z.x);
+  const size_t ncs = (size_t)d->ncell;
+  gf* pop = G(d->pop);
+  gf* Q = G(d->dmq[1]);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    Q[(size_t)r * ncs + z.g] = z.mt.bk2 * z.c[r].r - z.Pn[r] + z.dJ[r];
+    two_sum(z.nh[r], z.nl[r], z.inc[r]);
+    pop[(size_t)r * ncs + z.g] = z.nh[r];
+    pop[(size_t)(3 + r) * ncs + z.g] = z.nl[r];
+    pop[(size_t)(6 + r) * ncs + z.g] = z.c[r].r;
+    pop[(size_t)(9 + r) * ncs + z.g] = z.c[r].i;
+    pop[(size_t)(12 + r) * ncs + z.g] = z.x[r].r;
+    pop[(size_t)(15 + r) * ncs + z.g] = z.x[r].i;
+  }
+}
+
+// E^{n+1} = A - [Q]/eps on the edges next to gain cells; a unit's cells are
+// dealt to the threads in strides of the block.
+__global__ __launch_bounds__(256) void dm_edges_kernel(const fd_dm_unit* __restrict__ units, int s) {
+  const fd_dm_unit u = units[blockIdx.x];
+  const cdesc* d = (const cdesc*)u.d;
+  const long long n = d->step + s;
+  const int par = (int)(n & 1);
+  const gf* Q = G((const float*)d->dmq[1]);
+  const gu8* map = (const gu8*)d->mat;
+  for (int t = (int)threadIdx.x; t < u.count; t += (int)blockDim.x) {
+    const uint32_t o = (uint32_t)(u.first + t);
+    const Ijk p = ijk_of(d, o);
+    const float ie = ginv_eps(d, map[o]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (held_edge(d, c, p)) continue;
+      bool any;
+      const float sh = edge_share(d, Q, c, p, &any);
+      if (!any) continue;
+      gf* E = G(d->E[par ^ 1][c]);
+      E[o] = E[o] - sh * ie;
+    }
+  }
+}
+
+// After the edge pass: probe samples of E components and the T(t) partial of
+// every xy tile of a flux plane, recomputed from the final E^{n+1} (the step
+// kernels recorded them from A).  Unit: first = flux plane (-1: the probes),
+// count = xy tile; the block has the plan's tile shape.
+__global__ __launch_bounds__(FD_MAXBLOCK) void dm_diag_kernel(const fd_dm_unit* __restrict__ units, int s) {
+  __shared__ double red[FD_MAXBLOCK / 64];
+  const fd_dm_unit u = units[blockIdx.x];
+  const cdesc* d = (const cdesc*)u.d;
+  const long long n = d->step + s;
+  const int par = (int)(n & 1);
+  const int t = (int)threadIdx.x;
+  if (u.first < 0) {
+    if (t < d->nprobe && d->probe_comp[t] < 3)
+      G(d->probe_ring)[(long long)t * d->max_steps + n] =
+          G((const float*)d->E[par ^ 1][d->probe_comp[t]])[(size_t)d->probe_k[t] * d->plane + d->probe_cell[t]];
+    return;
+  }
+  const int f = u.first, blk = u.count;
+  const int TX = d->tile_x, TY = (int)blockDim.x / TX;
+  const int ntx = (d->nx + TX - 1) / TX;
+  const int i = (blk % ntx) * TX + t % TX, j = (blk / ntx) * TY + t / TX;
+  double v = 0.0;
+  if (i < d->nx && j < d->ny) {
+    const int kf = d->flux_k[f], km = kf > 0 ? kf - 1 : d->nz - 1;
+    const size_t off = (size_t)j * d->nx + i;
+    const size_t o = (size_t)kf * d->plane + off, om = (size_t)km * d->plane + off;
+    const float sx = 0.5f * (G((const float*)d->E[par][0])[o] + G((const float*)d->E[par ^ 1][0])[o]);
+    const float sy = 0.5f * (G((const float*)d->E[par][1])[o] + G((const float*)d->E[par ^ 1][1])[o]);
+    const gf* hx = G((const float*)d->H[par ^ 1][0]);
+    const gf* hy = G((const float*)d->H[par ^ 1][1]);
+    const float hyc = 0.5f * (hy[om] + hy[o]), hxc = 0.5f * (hx[om] + hx[o]);
+    v = (double)(sx * hyc) - (double)(sy * hxc);
+  }
+  const double tot = block_sum(v, red);
+  if (t == 0) G(d->flux_T[f])[n * d->nblk + blk] = tot;
+}
+
 }  // namespace
 
 // start/stop (optional) take the kernel's own begin and end timestamps
 template <int TX, int PM, int GAIN>
 static void launch_one(const fd_tile* tiles, int ntiles, int block, int grid, int s, const fd_xcd& part, int use,
                        int nt, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
-  if constexpr (GAIN == 2) {  // density-matrix kernels keep ordinary stores
-    (void)nt;
-    hipExtLaunchKernelGGL(step_kernel_dm<TX, PM>, dim3(grid), dim3(block), 0, st, start, stop, 0, tiles, ntiles, s,
-                          part, use);
-  } else if constexpr (PM == 7 && GAIN == 0) {
+  if constexpr (PM == 7 && GAIN == 0) {
     if (nt)
       hipExtLaunchKernelGGL(step_kernel_ax<TX, true>, dim3(grid), dim3(block), 0, st, start, stop, 0, tiles, ntiles,
                             s, part, use);
@@ -1459,32 +1643,21 @@ static void launch_one(const fd_tile* tiles, int ntiles, int block, int grid, in
 
 template <int TX>
 static hipError_t launch_tx(int cls, const fd_tile* tiles, int ntiles, int block, int grid, int s,
-                            const fd_xcd& part, int use, int nt, int gm, hipStream_t st, hipEvent_t start,
-                            hipEvent_t stop) {
-  const bool dm = gm == 2;
+                            const fd_xcd& part, int use, int nt, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
   switch (cls) {
     case FD_CLASS_PLAIN: launch_one<TX, 0, 0>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
     case FD_CLASS_PMLZ: launch_one<TX, 4, 0>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
     case FD_CLASS_PML: launch_one<TX, 7, 0>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
-    case FD_CLASS_GAIN:
-      if (dm) launch_one<TX, 0, 2>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop);
-      else launch_one<TX, 0, 1>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop);
-      break;
-    case FD_CLASS_PMLZ_GAIN:
-      if (dm) launch_one<TX, 4, 2>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop);
-      else launch_one<TX, 4, 1>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop);
-      break;
-    case FD_CLASS_PML_GAIN:
-      if (dm) launch_one<TX, 7, 2>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop);
-      else launch_one<TX, 7, 1>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop);
-      break;
+    case FD_CLASS_GAIN: launch_one<TX, 0, 1>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
+    case FD_CLASS_PMLZ_GAIN: launch_one<TX, 4, 1>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
+    case FD_CLASS_PML_GAIN: launch_one<TX, 7, 1>(tiles, ntiles, block, grid, s, part, use, nt, st, start, stop); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t fd_launch_step(int cls, const fd_tile* tiles, int ntiles, int tile_x, int block, int grid, int s,
-                          const fd_xcd* part, int nt, int gm, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
+                          const fd_xcd* part, int nt, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
   if (ntiles <= 0) return hipSuccess;
   if (block < 64 || block > FD_MAXBLOCK || (block & 63) != 0 || grid <= 0 || block % tile_x != 0 ||
       2 * (tile_x + 2) + 2 * (block / tile_x) > block)
@@ -1504,9 +1677,9 @@ hipError_t fd_launch_step(int cls, const fd_tile* tiles, int ntiles, int tile_x,
     use = 1;
   }
   switch (tile_x) {
-    case 16: return launch_tx<16>(cls, tiles, ntiles, block, grid, s, pz, use, nt, gm, st, start, stop);
-    case 32: return launch_tx<32>(cls, tiles, ntiles, block, grid, s, pz, use, nt, gm, st, start, stop);
-    case 64: return launch_tx<64>(cls, tiles, ntiles, block, grid, s, pz, use, nt, gm, st, start, stop);
+    case 16: return launch_tx<16>(cls, tiles, ntiles, block, grid, s, pz, use, nt, st, start, stop);
+    case 32: return launch_tx<32>(cls, tiles, ntiles, block, grid, s, pz, use, nt, st, start, stop);
+    case 64: return launch_tx<64>(cls, tiles, ntiles, block, grid, s, pz, use, nt, st, start, stop);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1595,4 +1768,17 @@ hipError_t fd_static_tables(void** ptr, int* device) {
   *ptr = addr[dev];
   *device = dev;
   return hipSuccess;
+}
+
+hipError_t fd_launch_dm(const fd_dm_unit* cells, int ncells, const fd_dm_unit* edges, int nedges,
+                        const fd_dm_unit* diag, int ndiag, int block, int s, hipStream_t st, hipEvent_t* ev) {
+  if (ncells <= 0) return hipSuccess;
+  if (block < 64 || block > FD_MAXBLOCK || (block & 63) != 0) return hipErrorInvalidValue;
+  auto E = [&](int q) -> hipEvent_t { return ev ? ev[q] : nullptr; };
+  hipExtLaunchKernelGGL(dm_predict_kernel, dim3(ncells), dim3(FD_DM_CELLS), 0, st, E(0), E(1), 0, cells, s);
+  hipExtLaunchKernelGGL(dm_correct_kernel, dim3(ncells), dim3(FD_DM_CELLS), 0, st, E(2), E(3), 0, cells, s);
+  if (nedges > 0)
+    hipExtLaunchKernelGGL(dm_edges_kernel, dim3(nedges), dim3(256), 0, st, E(4), E(5), 0, edges, s);
+  if (ndiag > 0) hipExtLaunchKernelGGL(dm_diag_kernel, dim3(ndiag), dim3(block), 0, st, E(6), E(7), 0, diag, s);
+  return hipGetLastError();
 }

@@ -309,22 +309,22 @@ class Plan:
         return ms.value
 
     CLASSES = ("step_plain", "step_cpml_z", "step_cpml", "step_gain", "step_cpml_z_gain",
-               "step_cpml_gain", "dft")
+               "step_cpml_gain", "dft", "dm_predict", "dm_correct", "dm_edges", "dm_diag")
 
     def class_cells(self):
-        out = np.zeros(7, dtype=np.int64)
+        out = np.zeros(len(self.CLASSES), dtype=np.int64)
         _check(lib().fdtd_class_cells(self.h, _ptr(out, C.c_int64)))
         return out
 
     def class_bytes(self):
-        out = np.zeros(7, dtype=np.float64)
+        out = np.zeros(len(self.CLASSES), dtype=np.float64)
         _check(lib().fdtd_class_bytes(self.h, _ptr(out, C.c_double)))
         return out
 
     def time_kernels(self, n, stream=None):
         """Per kernel class: (total ms, launches) over n eager steps."""
-        ms = np.zeros(7, dtype=np.float64)
-        cnt = np.zeros(7, dtype=np.int64)
+        ms = np.zeros(len(Plan.CLASSES), dtype=np.float64)
+        cnt = np.zeros(len(Plan.CLASSES), dtype=np.int64)
         _check(lib().fdtd_time_kernels(self.h, int(n), _stream(stream), _ptr(ms, C.c_double),
                                        _ptr(cnt, C.c_int64)))
         return ms, cnt
@@ -437,8 +437,8 @@ class Batch:
 
     def time_kernels(self, n, stream=None):
         """Per kernel class: (total ms, launches) over n eager batch steps."""
-        ms = np.zeros(7, dtype=np.float64)
-        cnt = np.zeros(7, dtype=np.int64)
+        ms = np.zeros(len(Plan.CLASSES), dtype=np.float64)
+        cnt = np.zeros(len(Plan.CLASSES), dtype=np.int64)
         _check(lib().fdtd_batch_time_kernels(self.h, int(n), _stream(stream), _ptr(ms, C.c_double),
                                              _ptr(cnt, C.c_int64)))
         return ms, cnt

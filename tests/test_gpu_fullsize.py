@@ -54,8 +54,10 @@ def _tuned(cfg, **extra):
     return t
 
 
-def _run_checkpoints(name, tol_fields, tuning_extra=None):
-    """Step the GPU through the fixture's checkpoints; returns (plan, fixture)."""
+def _run_checkpoints(name, tol_fields, tuning_extra=None, fields=True):
+    """Step the GPU through the fixture's checkpoints; returns (plan, fixture).
+    fields=False: the run ends empty (the pulse has left through the CPML and the
+    oracle's field norm is rounding residue), so only the diagnostics compare."""
     import torch
     from paper_0802_3775_amd import fdtd as F
     build, _ = FX.RUNS[name]
@@ -69,6 +71,9 @@ def _run_checkpoints(name, tol_fields, tuning_extra=None):
         plan.step(int(cp) - done)
         done = int(cp)
         torch.cuda.synchronize()
+        if not fields:
+            _say("  step", cp, "oracle field norms", fx["norm_%d" % cp], "(not compared)")
+            continue
         err = _sampled_rel(plan.fields(), fx["f_%d" % cp], fx["idx"])
         _say("  step", cp, "sampled field rel L2", err)
         assert err <= tol_fields, (name, cp, err)
@@ -109,8 +114,10 @@ def test_slab_full_size_full_length_with_transmission():
         assert rel_l2(S, fx["S%d" % f]) <= 1e-3
         spec.append(S)
     plan.close()
-    empty, efx = _run_checkpoints("slab_empty_full", 1e-4)
+    empty, efx = _run_checkpoints("slab_empty_full", 1e-4, fields=False)
+    assert max(efx["norm_20000"]) < 1e-5 * max(fx["norm_20000"])
     Se = empty.flux(0)[1]
+    assert rel_l2(empty.flux(0)[0], efx["T0"]) <= 1e-3
     assert rel_l2(Se, efx["S0"]) <= 1e-3
     tr_g, tr_o = spec[0] / Se, fx["S0"] / efx["S0"]
     _say("transmission", rel_l2(tr_g, tr_o))

@@ -206,3 +206,98 @@ def test_inverted_cell_gives_energy_to_the_field_and_ground_cell_takes_it():
     # the field amplitude along x is bounded by energy exchange: the inverted atom
     # has lost upper population, the ground one gained some
     assert p_inv < 1.0 - 1e-6 and p_gnd > 1e-6
+
+
+def _rotation_box(N=12, M=6, src=None, steps=0):
+    """Periodic N x N x M box of uniform permittivity 1 (so only the matter can
+    break a symmetry) with density-matrix cells forming a plus sign around cell
+    (c, c, kc) that a 90-degree turn about that cell's centre maps onto itself."""
+    c, kc = N // 2, M // 2
+    dye = material(eps=1.0, t1=1e3, t2=1e3, n_init=(0.4, 0.2, 0.2, 0.2))
+    mp = np.zeros((M, N, N), np.uint8)
+    for di, dj in ((0, 0), (1, 0), (-1, 0), (0, 1), (0, -1)):
+        mp[kc, c + dj, c + di] = 1
+    grid = {"n": (N, N, M), "periodic": (1, 1, 1), "pml_lo": (0, 0, 0), "pml_hi": (0, 0, 0), "res": 16,
+            "courant": 0.5, "a_meters": A_M, "seed": 3, "realization": 0}
+    cfg = {"name": "rot", "grid": grid, "materials": [{"eps": 1.0}, dye], "map": mp, "sources": [src],
+           "probes": [], "flux": [], "energy_interval": 0, "steps": steps}
+    return cfg, c, kc
+
+
+def test_density_matrix_sits_at_the_cell_centre_rotation_isotropy():
+    """The density-matrix equations are solved in the middle of the Yee cell
+    (section "Sample and numerical approach"): a gain cell couples to the
+    average of the four edges of each field component around its centre and
+    hands its polarization change back to them.  Turning the whole setup by 90
+    degrees about z through a gain cell's centre, (x, y) -> (2c+1-y, x), maps
+    the Yee lattice onto itself (Ex edges onto Ey edges), so the run of the
+    turned source must give the turned density matrix: upper levels 1, 2, 3
+    transform as the vector (x, y, z) -> (-y, x, z).  Coupling each cell to the
+    three edges at its lower corner instead breaks this at first order."""
+    steps = 300
+    wave = {"f0": 0.78, "width_kind": "fwhm_power", "width": 0.3, "delay": 5.0, "amp": 40.0}
+    cfg_a, c_, kc_ = _rotation_box()
+    # source A: Ex of cell (c+2, c+1); its image is Ey of cell (2c+1-(c+1), c+2) = (c, c+2)
+    cfg_a["sources"] = [dict(wave, kind="dipole", comp=0, i=c_ + 2, j=c_ + 1, k=kc_)]
+    cfg_b, _, _ = _rotation_box()
+    cfg_b["sources"] = [dict(wave, kind="dipole", comp=1, i=c_, j=c_ + 2, k=kc_)]
+    runs = []
+    for cfg in (cfg_a, cfg_b):
+        sim = O.OracleSim(cfg, max_steps=steps)
+        sim.step(steps)
+        runs.append((sim.density(), sim.fields()))
+    (da, fa), (db, fb) = runs
+    scale = np.abs(da[3:9]).max()
+    assert scale > 1e-3  # the pulse reached the matter
+    for di, dj in ((0, 0), (1, 0), (-1, 0), (0, 1), (0, -1)):
+        i, j = c_ + di, c_ + dj
+        ib, jb = 2 * c_ + 1 - j - 1, i   # the turned cell: centre (i+1/2, j+1/2) -> (2c+1-j-1/2, i+1/2)
+        a = da[:, kc_, j, i]
+        b = db[:, kc_, jb, ib]
+        # populations rho_11, rho_22, rho_33 -> (rho_22, rho_11, rho_33)
+        assert np.allclose([b[0], b[1], b[2]], [a[1], a[0], a[2]], rtol=0, atol=1e-10 * scale)
+        # ground-upper coherences (rho_01, rho_02, rho_03) -> (-rho_02, rho_01, rho_03), Re (3..5) and Im (6..8)
+        for o in (3, 6):
+            assert np.allclose([b[o], b[o + 1], b[o + 2]], [-a[o + 1], a[o], a[o + 2]], rtol=0, atol=1e-10 * scale)
+    # and the fields: E'_y at the image of an Ex edge equals E_x there
+    ex_a = fa[0, kc_]            # Ex(i, j) at (i+1/2, j) -> Ey(2c+1-j, i)
+    ey_b = fb[1, kc_]
+    N = ex_a.shape[0]
+    for j in range(N):
+        for i in range(N):
+            assert abs(ey_b[i, (2 * c_ + 1 - j) % N] - ex_a[j, i]) <= 1e-10 * np.abs(ex_a).max()
+
+
+def test_density_matrix_cells_conserve_field_plus_matter_energy_in_a_box():
+    """Periodic 6^3 box filled with the dye (no relaxation, pump or noise) from
+    random fields: the discrete field energy W^n (eps |E^n|^2 + H^{n-1/2} .
+    H^{n+1/2}) / 2 plus the matter energy kappa w0 sum_k rho_kk of every cell,
+    times dx^3, is constant to O(dt^2) -- the centre average and the hand-back
+    to the edges are adjoint, so the exchange between field and matter balances
+    cell by cell."""
+    drift = []
+    for res in (16, 32):
+        m = material(t1=1e3, t2=1e3, n_init=(0.6, 0.3, 0.1, 0.0))
+        n = (6, 6, 6)
+        rng = np.random.default_rng(11)
+        cfg = {"name": "dm_energy", "grid": {"n": n, "periodic": (1, 1, 1), "pml_lo": (0, 0, 0), "pml_hi": (0, 0, 0),
+                                             "res": res, "courant": 0.5, "a_meters": A_M, "seed": 1,
+                                             "realization": 0},
+               "materials": [m], "map": np.zeros(n, np.uint8), "sources": [], "probes": [], "flux": [],
+               "energy_interval": 1, "steps": 0}
+        dt, dx = 0.5 / res, 1.0 / res
+        steps = int(round(4.0 / dt))
+        sim = O.OracleSim(cfg, max_steps=steps + 1)
+        for c in range(3):
+            sim.set_field(c, 0.3 * rng.standard_normal(n))
+        w0, _, kappa, *_ = O.bloch_constants(m, dt, dx, A_M)
+        tot = []
+        for _ in range(steps):
+            pops = sim.populations()
+            matter = kappa * w0 * pops[1:].sum() * dx ** 3
+            sim.step(1)
+            tot.append(sim.energy()[-1] + matter)
+        tot = np.array(tot)
+        drift.append(np.max(np.abs(tot - tot[0])) / tot[0])
+    assert drift[0] < 5e-3
+    assert 3.0 < drift[0] / drift[1] < 5.0, drift
