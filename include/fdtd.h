@@ -339,11 +339,11 @@ int fdtd_class_cells(const fdtd_plan* p, int64_t* cells /* FDTD_NKERNEL */);
    the DFT entry is the average bytes of one call: the plane sample (24 bytes
    read, 16 written per point) and, once per 32 samples, the 4 complex FP64
    accumulators read + written per plane point and frequency plus the sample
-   ring read; per density-matrix gain cell 117 (predictor: 18 state floats, the
-   cell's share of E^n and A, map, list and ordinal, Q*) and 201 (corrector: the
-   state read and written, fields, neighbours' Q*, Q), 1 per cell of the edge
-   range + 41 per cell whose edges touch gain (A in, E out, Q, neighbours' map
-   and ordinals), 32 per flux-plane point + 8 per probe for the diagnostics. */
+   ring read; per density-matrix gain cell 113 (predictor: 18 state floats, the
+   cell's share of E^n and A, map and list, Q*) and 197 (corrector: the state
+   read and written, fields, neighbours' Q*, Q), 12 per cell of the edge range
+   (Q) + 25 per cell whose edges touch gain (A in, E out, map), 32 per
+   flux-plane point + 8 per probe for the diagnostics. */
 int fdtd_class_bytes(const fdtd_plan* p, double* bytes /* FDTD_NKERNEL */);
 /* Advance n steps without graphs, launching every kernel with a pair of hipEvents
    bound to the launch (hipExtLaunchKernelGGL start/stop: the kernel's own begin

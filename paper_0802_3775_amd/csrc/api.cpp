@@ -564,14 +564,13 @@ int build_dm_units(fdtd_plan* p) {
         }
     p->dm_cells[0] = p->dm_cells[1] = ng;
     p->dm_cells[2] = last - first;
-    // predictor: state 72 + E^n and A of the cell's edges 24 + map, list and
-    // ordinal 9 + Q* 12; corrector: state 72 + 72, fields 24, neighbours' Q*
-    // 12, Q 12, map, list and ordinal 9; edges: the map of the range, and for a
-    // cell whose edges touch gain A in and E out 24 + Q 12 + neighbours' map and
-    // ordinals 5
-    p->dm_bytes[0] = 117.0 * ng;
-    p->dm_bytes[1] = 201.0 * ng;
-    p->dm_bytes[2] = 1.0 * (double)(last - first) + 41.0 * (double)touched;
+    // predictor: state 72 + E^n and A of the cell's edges 24 + map and list 5
+    // + Q* 12; corrector: state 72 + 72, fields 24, neighbours' Q* 12, Q 12,
+    // map and list 5; edges: Q of the range 12, and for a cell whose edges touch
+    // gain A in and E out 24 + its map 1
+    p->dm_bytes[0] = 113.0 * ng;
+    p->dm_bytes[1] = 197.0 * ng;
+    p->dm_bytes[2] = 12.0 * (double)(last - first) + 25.0 * (double)touched;
   }
   for (int f = 0; f < (int)p->flux.size(); ++f)
     for (int b = 0; b < p->nblk; ++b) p->dmu[2].push_back({p->ddesc, f, b, 0});

@@ -69,8 +69,9 @@ struct fd_desc {
   float* pop;
   const uint32_t* gidx;
   // Density matrix (held at the cell centre): the cell of each gain ordinal, and
-  // per ordinal the polarization increment of the predictor (dmq[0]) and of the
+  // per cell the polarization increment of the predictor (dmq[0]) and of the
   // corrector (dmq[1]), 3 planes each, both including the noise current's dt J
+  // (cells without gain keep the arena's zeros)
   const uint32_t* glist;
   float* dmq[2];
   int ngain;

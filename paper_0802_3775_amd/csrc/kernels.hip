@@ -1398,44 +1398,38 @@ __device__ __forceinline__ Ijk ijk_of(const cdesc* d, uint32_t o) {
   return {(int)(r - j * nx), (int)j, (int)k};
 }
 
-// Flattened index of the cell at p shifted by (u, v) along the two axes
-// transverse to component c ((c+1) mod 3, (c+2) mod 3), after periodic wrap;
-// -1 beyond a PEC wall.
-__device__ __forceinline__ int shifted(const cdesc* d, int c, Ijk p, int u, int v) {
-  int q[3] = {p.i, p.j, p.k};
-  q[(c + 1) % 3] += u;
-  q[(c + 2) % 3] += v;
-  const int a = wrap(q[0], d->nx, d->per[0]), b = wrap(q[1], d->ny, d->per[1]), z = wrap(q[2], d->nz, d->per[2]);
-  return (a < 0 || b < 0 || z < 0) ? -1 : (z * d->ny + b) * d->nx + a;
+// Coordinates of cell p's neighbours along each axis at offsets -1, 0, +1
+// (periodic wrap; -1 beyond a PEC wall), so a cell's neighbourhood is indexed
+// without divisions.
+struct Nbr {
+  int c[3][3];  // [axis][offset + 1]
+};
+__device__ __forceinline__ int wrap1(int i, int n, int per) {
+  if (i >= 0 && i < n) return i;
+  if (!per) return -1;
+  return i < 0 ? i + n : i - n;
 }
-
-// Component c of voxel p lies on a PEC wall (index 0 of a non-periodic
+__device__ __forceinline__ Nbr neighbours(const cdesc* d, Ijk p) {
+  Nbr b;
+  const int q[3] = {p.i, p.j, p.k}, n[3] = {d->nx, d->ny, d->nz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int o = 0; o < 3; ++o) b.c[a][o] = wrap1(q[a] + o - 1, n[a], d->per[a]);
+  return b;
+}
+// The cell at offsets u, v in {-1, 0, 1} along the two axes transverse to
+// component c ((c+1) mod 3, (c+2) mod 3), or -1 beyond a PEC wall; *held: the
+// cell's component-c edge lies on a PEC wall (index 0 of a non-periodic
 // transverse axis) and is held at zero.
-__device__ __forceinline__ bool held_edge(const cdesc* d, int c, Ijk p) {
-  const int q[3] = {p.i, p.j, p.k};
+__device__ __forceinline__ int nb_cell(const cdesc* d, const Nbr& b, int c, int u, int v, bool* held) {
   const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
-  return (!d->per[a1] && q[a1] == 0) || (!d->per[a2] && q[a2] == 0);
-}
-
-// [Q] of component c's edge of voxel p: a quarter of Q over the gain cells at
-// offsets {0, -1} along the transverse axes; *any: some such cell has gain.
-__device__ __forceinline__ float edge_share(const cdesc* d, const gf* Q, int c, Ijk p, bool* any) {
-  const gu8* map = (const gu8*)d->mat;
-  const __attribute__((address_space(1))) uint32_t* gidx = (const __attribute__((address_space(1))) uint32_t*)d->gidx;
-  const size_t ncs = (size_t)d->ncell;
-  float acc = 0.0f;
-  bool hit = false;
-#pragma unroll
-  for (int u = 0; u < 2; ++u)
-#pragma unroll
-    for (int v = 0; v < 2; ++v) {
-      const int cc = shifted(d, c, p, -u, -v);
-      if (cc < 0 || !((d->gainmask >> map[cc]) & 1u)) continue;
-      acc += Q[(size_t)c * ncs + gidx[cc]];
-      hit = true;
-    }
-  *any = hit;
-  return 0.25f * acc;
+  int o[3] = {1, 1, 1};
+  o[a1] += u;
+  o[a2] += v;
+  const int x = b.c[0][o[0]], y = b.c[1][o[1]], z = b.c[2][o[2]];
+  *held = (!d->per[a1] && b.c[a1][o[a1]] == 0) || (!d->per[a2] && b.c[a2][o[a2]] == 0);
+  return (x < 0 || y < 0 || z < 0) ? -1 : (z * d->ny + y) * d->nx + x;
 }
 
 // A gain cell's state (populations as (hi, lo) FP32 pairs, coherences), its
@@ -1475,19 +1469,6 @@ __device__ __forceinline__ void dm_load(const cdesc* d, uint32_t g, long long n,
   }
 }
 
-// <F> of component c around cell p's centre (edges beyond a PEC wall hold 0).
-__device__ __forceinline__ float centre_avg(const cdesc* d, const gf* F, int c, Ijk p) {
-  float acc = 0.0f;
-#pragma unroll
-  for (int u = 0; u < 2; ++u)
-#pragma unroll
-    for (int v = 0; v < 2; ++v) {
-      const int e = shifted(d, c, p, u, v);
-      if (e >= 0) acc += F[e];
-    }
-  return 0.25f * acc;
-}
-
 __global__ __launch_bounds__(FD_DM_CELLS) void dm_predict_kernel(const fd_dm_unit* __restrict__ units, int s) {
   const fd_dm_unit u = units[blockIdx.x];
   if ((int)threadIdx.x >= u.count) return;
@@ -1496,17 +1477,30 @@ __global__ __launch_bounds__(FD_DM_CELLS) void dm_predict_kernel(const fd_dm_uni
   const int par = (int)(n & 1);
   DmCell z;
   dm_load(d, (uint32_t)(u.first + (int)threadIdx.x), n, z);
+  const Nbr b = neighbours(d, z.p);
   float em[3];
 #pragma unroll
-  for (int q = 0; q < 3; ++q)
-    em[q] = 0.5f * (centre_avg(d, G((const float*)d->E[par][q]), q, z.p) +
-                    centre_avg(d, G((const float*)d->E[par ^ 1][q]), q, z.p));
+  for (int q = 0; q < 3; ++q) {
+    // <(E^n + A)/2>: the cell's four component-q edges sit at offsets {0, 1}
+    const gf* En = G((const float*)d->E[par][q]);
+    const gf* A = G((const float*)d->E[par ^ 1][q]);
+    float acc = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        bool held;
+        const int e = nb_cell(d, b, q, a, c, &held);
+        if (e >= 0) acc += En[e] + A[e];
+      }
+    em[q] = 0.125f * acc;
+  }
   dm_relax(z.mt, z.pp, z.inc, z.c, z.x);
   dm_cayley<false>(z.mt, em, z.pp, z.inc, z.c, z.x);
   gf* Q = G(d->dmq[0]);
   const size_t ncs = (size_t)d->ncell;
 #pragma unroll
-  for (int q = 0; q < 3; ++q) Q[(size_t)q * ncs + z.g] = z.mt.bk2 * (z.c[q].r * z.mt.bf2) - z.Pn[q] + z.dJ[q];
+  for (int q = 0; q < 3; ++q) Q[(size_t)q * ncs + z.o] = z.mt.bk2 * (z.c[q].r * z.mt.bf2) - z.Pn[q] + z.dJ[q];
 }
 
 __global__ __launch_bounds__(FD_DM_CELLS) void dm_correct_kernel(const fd_dm_unit* __restrict__ units, int s) {
@@ -1517,36 +1511,57 @@ __global__ __launch_bounds__(FD_DM_CELLS) void dm_correct_kernel(const fd_dm_uni
   const int par = (int)(n & 1);
   DmCell z;
   dm_load(d, (uint32_t)(u.first + (int)threadIdx.x), n, z);
+  const Nbr b = neighbours(d, z.p);
   const gf* Qs = G((const float*)d->dmq[0]);
   const gu8* map = (const gu8*)d->mat;
+  const size_t ncs = (size_t)d->ncell;
   float em[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
+    // Q* of the 3 x 3 cells around the centre across component q (0 off the
+    // grid; cells without gain hold 0), and the voxels of the cell's four edges
+    float qn[3][3];
+    int me[2][2], ee[2][2];
+    bool he[2][2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        bool held;
+        const int e = nb_cell(d, b, q, a - 1, c - 1, &held);
+        qn[a][c] = e >= 0 ? Qs[(size_t)q * ncs + e] : 0.0f;
+        if (a >= 1 && c >= 1) {
+          me[a - 1][c - 1] = e >= 0 ? map[e] : 0;
+          ee[a - 1][c - 1] = e;
+          he[a - 1][c - 1] = held;
+        }
+      }
+    // <E^n + E*> with E* = A - [Q*]/eps on the edges (0 beyond or on a PEC wall);
+    // the edge at offsets (a, c) is shared by the cells at (a - 1 .. a, c - 1 .. c)
+    const gf* En = G((const float*)d->E[par][q]);
     const gf* A = G((const float*)d->E[par ^ 1][q]);
     float acc = 0.0f;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int e = shifted(d, q, z.p, a, b);
+      for (int c = 0; c < 2; ++c) {
+        const int e = ee[a][c];
         if (e < 0) continue;
-        const Ijk pe = ijk_of(d, (uint32_t)e);
-        if (held_edge(d, q, pe)) continue;
-        bool any;
-        const float sh = edge_share(d, Qs, q, pe, &any);
-        acc += A[e] - sh * ginv_eps(d, map[e]);  // E* of the edge
+        acc += En[e];
+        if (he[a][c]) continue;
+        const float sh = 0.25f * ((qn[a][c] + qn[a + 1][c]) + (qn[a][c + 1] + qn[a + 1][c + 1]));
+        acc += A[e] - sh * ginv_eps(d, me[a][c]);
       }
-    em[q] = 0.5f * (centre_avg(d, G((const float*)d->E[par][q]), q, z.p) + 0.25f * acc);
+    em[q] = 0.125f * acc;
   }
   dm_relax(z.mt, z.pp, z.inc, z.c, z.x);
   dm_cayley<true>(z.mt, em, z.pp, z.inc, z.c, z.x);
   dm_relax(z.mt, z.pp, z.inc, z.c, z.x);
-  const size_t ncs = (size_t)d->ncell;
   gf* pop = G(d->pop);
   gf* Q = G(d->dmq[1]);
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    Q[(size_t)r * ncs + z.g] = z.mt.bk2 * z.c[r].r - z.Pn[r] + z.dJ[r];
+    Q[(size_t)r * ncs + z.o] = z.mt.bk2 * z.c[r].r - z.Pn[r] + z.dJ[r];
     two_sum(z.nh[r], z.nl[r], z.inc[r]);
     pop[(size_t)r * ncs + z.g] = z.nh[r];
     pop[(size_t)(3 + r) * ncs + z.g] = z.nl[r];
@@ -1566,18 +1581,31 @@ __global__ __launch_bounds__(256) void dm_edges_kernel(const fd_dm_unit* __restr
   const int par = (int)(n & 1);
   const gf* Q = G((const float*)d->dmq[1]);
   const gu8* map = (const gu8*)d->mat;
+  const size_t ncs = (size_t)d->ncell;
   for (int t = (int)threadIdx.x; t < u.count; t += (int)blockDim.x) {
     const uint32_t o = (uint32_t)(u.first + t);
-    const Ijk p = ijk_of(d, o);
-    const float ie = ginv_eps(d, map[o]);
+    const Nbr b = neighbours(d, ijk_of(d, o));
+    float ie = -1.0f;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      if (held_edge(d, c, p)) continue;
-      bool any;
-      const float sh = edge_share(d, Q, c, p, &any);
-      if (!any) continue;
+      bool held;
+      (void)nb_cell(d, b, c, 0, 0, &held);
+      if (held) continue;
+      // the cells sharing the edge: offsets {0, -1} along the transverse axes
+      // (cells without gain hold Q = 0, so an edge with no gain neighbour keeps A)
+      float acc = 0.0f;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          bool h2;
+          const int cc = nb_cell(d, b, c, -a, -v, &h2);
+          if (cc >= 0) acc += Q[(size_t)c * ncs + cc];
+        }
+      if (acc == 0.0f) continue;
+      if (ie < 0.0f) ie = ginv_eps(d, map[o]);
       gf* E = G(d->E[par ^ 1][c]);
-      E[o] = E[o] - sh * ie;
+      E[o] = E[o] - 0.25f * acc * ie;
     }
   }
 }
