@@ -169,9 +169,13 @@ typedef struct {
    stream order.  stores: FDTD_STORES_AUTO (non-temporal field stores for a plan
    whose step state exceeds four times the 256 MB Infinity Cache, ordinary ones
    otherwise and in batches), FDTD_STORES_ORDINARY or FDTD_STORES_NONTEMPORAL.
-   Results do not depend on any of these. */
+   cache_mb (batches only; >= 0): members are stepped in groups of consecutive
+   members whose step state together is at most cache_mb MB, each group for all
+   the steps of a call (or of a captured graph) before the next, so that a group
+   that fits the Infinity Cache is read from there; 0 steps every member every
+   step.  Results do not depend on any of these. */
 typedef struct {
-  int32_t block, zchunk, graph_steps, max_blocks, tile_x, merge, parallel, stores;
+  int32_t block, zchunk, graph_steps, max_blocks, tile_x, merge, parallel, stores, cache_mb;
 } fdtd_tuning;
 
 /* Message of the last failed call on this thread; library version string. */
@@ -278,9 +282,9 @@ int fdtd_read_energy(fdtd_plan* p, double* host, int64_t* n, void* stream);
    realizations of the disorder): bound plans that step together, one launch
    per tile class per step over all plans' tiles (uneven sizes, each plan's own
    step count).  t (may be NULL: the first member's tuning) gives the batch's
-   launch settings (graph_steps, max_blocks, parallel, stores); its block and
-   tile_x must equal every member's (their tiles were laid out at bind; zchunk
-   and merge of t are not used).  Stepping a batch advances every member;
+   launch settings (graph_steps, max_blocks, parallel, stores, cache_mb); its
+   block and tile_x must equal every member's (their tiles were laid out at
+   bind; zchunk and merge of t are not used).  Stepping a batch advances every member;
    members must stay alive.  Creation allocates the batch's launch tables on the
    device (hipMalloc; freed by destroy). */
 int fdtd_batch_create(fdtd_plan* const* plans, int32_t n, const fdtd_tuning* t, fdtd_batch** out);
@@ -350,8 +354,10 @@ int fdtd_class_bytes(const fdtd_plan* p, double* bytes /* FDTD_NKERNEL */);
    and end timestamps); ms[c] = summed milliseconds and launches[c] = number of
    launches of kernel c (FDTD_NKERNEL entries each, as above). */
 int fdtd_time_kernels(fdtd_plan* p, int64_t n, void* stream, double* ms, int64_t* launches);
-/* The same for a batch: the launches of its tile classes over all members (the
-   class bytes of a batch launch are the sum of its members' fdtd_class_bytes). */
+/* The same for a batch, member group after member group: ms[c] sums kernel c's
+   launches over all groups, and launches[c] counts the steps in which it ran, so
+   ms[c] / launches[c] is its time per batch step over all members (whose bytes
+   are the sum of the members' fdtd_class_bytes). */
 int fdtd_batch_time_kernels(fdtd_batch* b, int64_t n, void* stream, double* ms, int64_t* launches);
 
 #ifdef __cplusplus

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <memory>
 #include <mutex>
 #include <numeric>
@@ -177,6 +178,19 @@ struct fdtd_plan {
   std::map<int64_t, GraphEntry> graphs;
 };
 
+// Members [m0, m1) of a batch, stepped together: their sub-ranges of the
+// batch's class tile lists, DFT units and density-matrix units (all of which
+// list the members in order), with the group's own XCD partitions.
+struct BGroup {
+  int m0 = 0, m1 = 0;
+  int t0[FD_NCLASS] = {}, nt[FD_NCLASS] = {};
+  fd_xcd part[FD_NCLASS] = {};
+  int pgrid[FD_NCLASS] = {};
+  int d0 = 0, nd = 0;
+  int u0[3] = {}, nu[3] = {};
+  int maxnf = 0;
+};
+
 struct fdtd_batch {
   std::vector<fdtd_plan*> plans;
   int block = 256;
@@ -185,9 +199,9 @@ struct fdtd_batch {
   int max_blocks = 0;
   int graph_steps = 0;
   std::vector<fd_tile> tiles[FD_NCLASS];
-  fd_xcd part[FD_NCLASS] = {};
-  int pgrid[FD_NCLASS] = {};
   int ntst = 0;
+  int cache_mb = 0;  // member groups of at most this much step state (0: one group)
+  std::vector<BGroup> groups;
   int gm = 1;  // gain model shared by the members with gain
   std::vector<fd_dft_tile> dft;
   int maxnf = 0;
@@ -596,17 +610,17 @@ struct DmLaunch {
   int n[3] = {0, 0, 0};
 };
 
-int enqueue_step(fd_tile* const dtiles[FD_NCLASS], const std::vector<fd_tile>* tiles, const fd_xcd* part,
+int enqueue_step(fd_tile* const dtiles[FD_NCLASS], const int* ntiles, const fd_xcd* part,
                  const int* pgrid, int tile_x, int block, int max_blocks, const fd_dft_tile* ddft, int ndft,
                  int maxnf, bool dft_due, int s, int ntst, const DmLaunch& dm, hipStream_t st, Fork* fk) {
   int used[FD_NCLASS], nused = 0;
   for (int c = 0; c < FD_NCLASS; ++c)
-    if (!tiles[c].empty()) used[nused++] = c;
+    if (ntiles[c] > 0) used[nused++] = c;
   const bool par = fk && nused > 1;
   if (par) HIPCHK(hipEventRecord(fk->fork, st));
   for (int u = 0; u < nused; ++u) {
     const int c = used[u];
-    const int nt = (int)tiles[c].size();
+    const int nt = ntiles[c];
     const int grid = max_blocks > 0 ? std::min(nt, max_blocks) : pgrid[c];
     const fd_xcd* pc = max_blocks > 0 ? nullptr : &part[c];
     hipStream_t on = st;
@@ -650,8 +664,10 @@ int64_t plan_phase_key(const fdtd_plan* p, int64_t n0) {
 }
 
 int plan_enqueue(fdtd_plan* p, int64_t n, hipStream_t st, Fork* fk) {
+  int nt[FD_NCLASS];
+  for (int c = 0; c < FD_NCLASS; ++c) nt[c] = (int)p->tiles[c].size();
   for (int64_t s = 0; s < n; ++s) {
-    const int r = enqueue_step(p->dtiles, p->tiles, p->part, p->pgrid, p->tune.tile_x, p->tune.block,
+    const int r = enqueue_step(p->dtiles, nt, p->part, p->pgrid, p->tune.tile_x, p->tune.block,
                                p->tune.max_blocks, p->ddft, (int)p->dft.size(), p->maxnf,
                                plan_dft_due(p, p->step + s), (int)s, p->ntst, plan_dm(p), st, fk);
     if (r) return r;
@@ -877,6 +893,7 @@ int fdtd_set_tuning(fdtd_plan* p, const fdtd_tuning* t) {
                 "exceeds block", t->tile_x, t->block);
   if (t->merge < 0 || t->merge > 2 || t->parallel < 0 || t->parallel > 1) return fail(FDTD_EINVAL, "bad merge/parallel");
   if (t->stores < FDTD_STORES_AUTO || t->stores > FDTD_STORES_NONTEMPORAL) return fail(FDTD_EINVAL, "bad stores mode");
+  if (t->cache_mb < 0) return fail(FDTD_EINVAL, "cache_mb must be >= 0");
   p->tune = *t;
   return FDTD_OK;
 }
@@ -1763,7 +1780,7 @@ int batch_check(fdtd_plan* const* plans, int32_t n, const fdtd_tuning& bt, int* 
   if (!plans || n < 1) return fail(FDTD_EINVAL, "need at least one plan");
   for (int q = 0; q < n; ++q)
     if (!plans[q] || !plans[q]->bound) return fail(FDTD_ESTATE, "batch member %d not bound", q);
-  if (bt.graph_steps < 0 || bt.max_blocks < 0 || bt.parallel < 0 || bt.parallel > 1 ||
+  if (bt.graph_steps < 0 || bt.max_blocks < 0 || bt.parallel < 0 || bt.parallel > 1 || bt.cache_mb < 0 ||
       bt.stores < FDTD_STORES_AUTO || bt.stores > FDTD_STORES_NONTEMPORAL)
     return fail(FDTD_EINVAL, "bad batch tuning");
   for (int q = 0; q < n; ++q) {
@@ -1781,28 +1798,58 @@ int batch_check(fdtd_plan* const* plans, int32_t n, const fdtd_tuning& bt, int* 
   return FDTD_OK;
 }
 
-// Host side of a batch: members' tile lists concatenated per class, their XCD
-// partitions and the DFT work units.
+// Host side of a batch: members' tile lists concatenated per class, the DFT
+// and density-matrix work units, and the member groups: consecutive members
+// whose step state together stays within cache_mb MB (a member larger than
+// that is a group of its own; cache_mb = 0: one group), each with the XCD
+// partitions of its own tiles.
 void batch_layout(fdtd_batch* b, fdtd_plan* const* plans, int32_t n, int gm) {
   b->plans.assign(plans, plans + n);
   b->gm = gm ? gm : 1;
   b->maxnf = 0;
   b->dft.clear();
-  std::vector<double> bcost[FD_NCLASS];
+  b->groups.clear();
   for (int c = 0; c < FD_NCLASS; ++c) b->tiles[c].clear();
-  for (fdtd_plan* p : b->plans) {
+  for (int q = 0; q < 3; ++q) b->dmu[q].clear();
+  const size_t cap = (size_t)b->cache_mb << 20;
+  size_t held = 0;
+  std::vector<double> gcost[FD_NCLASS];
+  auto close_group = [&]() {
+    BGroup& g = b->groups.back();
+    for (int c = 0; c < FD_NCLASS; ++c) {
+      g.nt[c] = (int)b->tiles[c].size() - g.t0[c];
+      g.part[c] = xcd_partition(gcost[c], &g.pgrid[c]);
+      gcost[c].clear();
+    }
+    g.nd = (int)b->dft.size() - g.d0;
+    for (int q = 0; q < 3; ++q) g.nu[q] = (int)b->dmu[q].size() - g.u0[q];
+  };
+  for (int m = 0; m < n; ++m) {
+    fdtd_plan* p = b->plans[m];
+    const size_t bytes = step_state_bytes(p);
+    if (b->groups.empty() || (cap > 0 && held > 0 && held + bytes > cap)) {
+      if (!b->groups.empty()) close_group();
+      BGroup g;
+      g.m0 = m;
+      for (int c = 0; c < FD_NCLASS; ++c) g.t0[c] = (int)b->tiles[c].size();
+      g.d0 = (int)b->dft.size();
+      for (int q = 0; q < 3; ++q) g.u0[q] = (int)b->dmu[q].size();
+      b->groups.push_back(g);
+      held = 0;
+    }
+    BGroup& g = b->groups.back();
+    g.m1 = m + 1;
+    g.maxnf = std::max(g.maxnf, p->maxnf);
+    held += bytes;
     for (int c = 0; c < FD_NCLASS; ++c) {
       b->tiles[c].insert(b->tiles[c].end(), p->tiles[c].begin(), p->tiles[c].end());
-      bcost[c].insert(bcost[c].end(), p->tcost[c].begin(), p->tcost[c].end());
+      gcost[c].insert(gcost[c].end(), p->tcost[c].begin(), p->tcost[c].end());
     }
     b->dft.insert(b->dft.end(), p->dft.begin(), p->dft.end());
     b->maxnf = std::max(b->maxnf, p->maxnf);
+    for (int q = 0; q < 3; ++q) b->dmu[q].insert(b->dmu[q].end(), p->dmu[q].begin(), p->dmu[q].end());
   }
-  for (int c = 0; c < FD_NCLASS; ++c) b->part[c] = xcd_partition(bcost[c], &b->pgrid[c]);
-  for (int q = 0; q < 3; ++q) {
-    b->dmu[q].clear();
-    for (fdtd_plan* p : b->plans) b->dmu[q].insert(b->dmu[q].end(), p->dmu[q].begin(), p->dmu[q].end());
-  }
+  close_group();
 }
 
 // Device bytes of the batch's launch tables (tile lists, DFT units, descriptor
@@ -1876,6 +1923,7 @@ int fdtd_batch_create(fdtd_plan* const* plans, int32_t n, const fdtd_tuning* t, 
   b->parallel = bt.parallel;
   b->max_blocks = bt.max_blocks;
   b->graph_steps = bt.graph_steps;
+  b->cache_mb = bt.cache_mb;
   // Batches keep ordinary stores unless asked: over a 64-member ensemble of
   // 1.9 GB the non-temporal form measured about 10% slower, while a single 2 GB
   // grid gains.
@@ -1911,6 +1959,7 @@ int fdtd_batch_create_static(fdtd_plan* const* plans, int32_t n, const fdtd_tuni
   b->parallel = bt.parallel;
   b->max_blocks = bt.max_blocks;
   b->graph_steps = bt.graph_steps;
+  b->cache_mb = bt.cache_mb;
   b->ntst = bt.stores == FDTD_STORES_NONTEMPORAL ? 1 : 0;
   batch_layout(b.get(), plans, n, gm);
   size_t off_t[FD_NCLASS], off_d, off_p, off_m[3];
@@ -1944,11 +1993,13 @@ int fdtd_batch_set_members(fdtd_batch* b, fdtd_plan* const* plans, int32_t n, vo
   bt.max_blocks = b->max_blocks;
   bt.parallel = b->parallel;
   bt.stores = b->ntst ? FDTD_STORES_NONTEMPORAL : FDTD_STORES_ORDINARY;
+  bt.cache_mb = b->cache_mb;
   int gm = 0;
   if (int r = batch_check(plans, n, bt, &gm)) return r;
   // the launches already queued read the current tables: wait for them
   HIPCHK(hipStreamSynchronize((hipStream_t)stream));
   fdtd_batch next;
+  next.cache_mb = b->cache_mb;
   batch_layout(&next, plans, n, gm);
   size_t off_t[FD_NCLASS], off_d, off_p, off_m[3];
   const size_t bytes = batch_table_bytes(&next, off_t, &off_d, &off_p, off_m);
@@ -1973,27 +2024,34 @@ void fdtd_batch_destroy(fdtd_batch* b) {
   delete b;
 }
 
-static bool batch_dft_due(const fdtd_batch* b, int64_t s) {
-  for (const fdtd_plan* p : b->plans)
-    if (plan_dft_due(p, p->step + s)) return true;
+static bool group_dft_due(const fdtd_batch* b, const BGroup& g, int64_t s) {
+  for (int m = g.m0; m < g.m1; ++m)
+    if (plan_dft_due(b->plans[m], b->plans[m]->step + s)) return true;
   return false;
 }
 
-static DmLaunch batch_dm(const fdtd_batch* b) {
+static DmLaunch group_dm(const fdtd_batch* b, const BGroup& g) {
   DmLaunch l;
   for (int q = 0; q < 3; ++q) {
-    l.u[q] = b->ddm[q];
-    l.n[q] = (int)b->dmu[q].size();
+    l.u[q] = b->ddm[q] + g.u0[q];
+    l.n[q] = g.nu[q];
   }
   return l;
 }
 
+// n steps of every member, group after group (a group's state stays in the
+// Infinity Cache over its n steps when it fits there); members are independent,
+// so the order changes no result.
 static int batch_enqueue(fdtd_batch* b, int64_t n, hipStream_t st, Fork* fk) {
-  for (int64_t s = 0; s < n; ++s) {
-    const int r = enqueue_step(b->dtiles, b->tiles, b->part, b->pgrid, b->tile_x, b->block, b->max_blocks, b->ddft,
-                               (int)b->dft.size(), b->maxnf, batch_dft_due(b, s), (int)s, b->ntst, batch_dm(b), st,
-                               fk);
-    if (r) return r;
+  for (const BGroup& g : b->groups) {
+    fd_tile* dt[FD_NCLASS];
+    for (int c = 0; c < FD_NCLASS; ++c) dt[c] = b->dtiles[c] + g.t0[c];
+    const DmLaunch dm = group_dm(b, g);
+    for (int64_t s = 0; s < n; ++s) {
+      const int r = enqueue_step(dt, g.nt, g.part, g.pgrid, b->tile_x, b->block, b->max_blocks, b->ddft + g.d0, g.nd,
+                                 g.maxnf, group_dft_due(b, g, s), (int)s, b->ntst, dm, st, fk);
+      if (r) return r;
+    }
   }
   HIPCHK(fd_launch_advance(b->ddescs, (int)b->plans.size(), n, st));
   return FDTD_OK;
@@ -2060,6 +2118,8 @@ int fdtd_batch_time_kernels(fdtd_batch* b, int64_t n, void* stream, double* ms, 
   hipStream_t st = (hipStream_t)stream;
   std::vector<std::array<hipEvent_t, 2>> ev;
   std::vector<int> cls;
+  std::set<std::pair<int, int64_t>> stepped;  // (kernel, step) pairs launched
+  int64_t cur = 0;
   auto cleanup = [&]() {
     for (auto& e : ev) {
       (void)hipEventDestroy(e[0]);
@@ -2072,29 +2132,32 @@ int fdtd_batch_time_kernels(fdtd_batch* b, int64_t n, void* stream, double* ms, 
     HIPCHK(hipEventCreate(&e[1]));
     ev.push_back(e);
     cls.push_back(c);
+    stepped.insert({c, cur});
     *a = e[0];
     *z = e[1];
     return FDTD_OK;
   };
+  for (const BGroup& g : b->groups)
   for (int64_t s = 0; s < n; ++s) {
+    cur = s;
     for (int c = 0; c < FD_NCLASS; ++c) {
-      const int nt = (int)b->tiles[c].size();
+      const int nt = g.nt[c];
       if (nt == 0) continue;
-      const int grid = b->max_blocks > 0 ? std::min(nt, b->max_blocks) : b->pgrid[c];
-      const fd_xcd* pc = b->max_blocks > 0 ? nullptr : &b->part[c];
+      const int grid = b->max_blocks > 0 ? std::min(nt, b->max_blocks) : g.pgrid[c];
+      const fd_xcd* pc = b->max_blocks > 0 ? nullptr : &g.part[c];
       hipEvent_t a, z;
       if (int r = pair(c, &a, &z)) { cleanup(); return r; }
-      const hipError_t e = fd_launch_step(c, b->dtiles[c], nt, b->tile_x, b->block, grid, (int)s, pc, b->ntst, st,
-                                          a, z);
+      const hipError_t e = fd_launch_step(c, b->dtiles[c] + g.t0[c], nt, b->tile_x, b->block, grid, (int)s, pc,
+                                          b->ntst, st, a, z);
       if (e != hipSuccess) { cleanup(); return fail(FDTD_EHIP, "batch_time_kernels: %s", hipGetErrorString(e)); }
     }
-    if (batch_dft_due(b, s) && !b->dft.empty()) {
+    if (group_dft_due(b, g, s) && g.nd > 0) {
       hipEvent_t a, z;
       if (int r = pair(FD_KERNEL_DFT, &a, &z)) { cleanup(); return r; }
-      const hipError_t e = fd_launch_dft(b->ddft, (int)b->dft.size(), (int)s, st, a, z);
+      const hipError_t e = fd_launch_dft(b->ddft + g.d0, g.nd, (int)s, st, a, z);
       if (e != hipSuccess) { cleanup(); return fail(FDTD_EHIP, "batch_time_kernels: %s", hipGetErrorString(e)); }
     }
-    const DmLaunch dm = batch_dm(b);
+    const DmLaunch dm = group_dm(b, g);
     if (dm.n[0] > 0) {
       hipEvent_t ev[8] = {};
       for (int q = 0; q < 4; ++q)
@@ -2120,8 +2183,8 @@ int fdtd_batch_time_kernels(fdtd_batch* b, int64_t n, void* stream, double* ms, 
     float f = 0.0f;
     (void)hipEventElapsedTime(&f, ev[q][0], ev[q][1]);
     ms[cls[q]] += f;
-    launches[cls[q]] += 1;
   }
+  for (const auto& cs : stepped) launches[cs.first] += 1;
   cleanup();
   return FDTD_OK;
 }

@@ -59,11 +59,11 @@ class OpalDesc(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("zchunk", C.c_int32), ("graph_steps", C.c_int32),
                 ("max_blocks", C.c_int32), ("tile_x", C.c_int32), ("merge", C.c_int32),
-                ("parallel", C.c_int32), ("stores", C.c_int32)]
+                ("parallel", C.c_int32), ("stores", C.c_int32), ("cache_mb", C.c_int32)]
 
 
 STORES = {"auto": 0, "ordinary": 1, "nontemporal": 2}
-TUNING_KEYS = ("block", "zchunk", "graph_steps", "max_blocks", "tile_x", "merge", "parallel", "stores")
+TUNING_KEYS = ("block", "zchunk", "graph_steps", "max_blocks", "tile_x", "merge", "parallel", "stores", "cache_mb")
 
 
 def make_tuning(t):
@@ -188,7 +188,7 @@ def _material(m):
 
 def default_tuning(cfg=None):
     return {"block": 256, "zchunk": 4, "graph_steps": 64, "max_blocks": 0, "tile_x": 32, "merge": 1,
-            "parallel": 0, "stores": 0}
+            "parallel": 0, "stores": 0, "cache_mb": 0}
 
 
 class Plan:

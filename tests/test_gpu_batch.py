@@ -40,7 +40,11 @@ def _same(a, b):
         assert np.array_equal(a[k], b[k]), k
 
 
-def test_batch_equals_plain_bitwise():
+@pytest.mark.parametrize("cache_mb", [0, 1, 2])
+def test_batch_equals_plain_bitwise(cache_mb):
+    """cache_mb 0: every member every step; 1 and 2: member groups of at most
+    that many MB of step state (one member each, or the small ones together),
+    each group stepped through a call or graph before the next."""
     import torch
     from paper_0802_3775_amd import fdtd as F
     steps = 120
@@ -52,7 +56,8 @@ def test_batch_equals_plain_bitwise():
         alone.append(_state(p))
         p.close()
     plans = [F.Plan(cfg, max_steps=steps, tuning=tune) for cfg in _cfgs(steps)]
-    b = F.Batch(plans)
+    print("member cells", [p.ncell for p in plans], "cache_mb", cache_mb, flush=True)
+    b = F.Batch(plans, tuning={"cache_mb": cache_mb})
     b.step(37)   # remainder path (no graph)
     b.step(83)   # graph path
     torch.cuda.synchronize()
@@ -116,8 +121,9 @@ def test_ensemble_batch_members_match_the_oracle():
     """The batched ensemble at its full size (64 uneven realizations, delta ~
     U[0, 0.12] a, 4^3-6^3 cells at 16-24 cells/a, slab layout with z-CPML and
     two 100-frequency flux planes each; about 1.9 GB of step state), stepped 300
-    steps as one batch; the largest and the smallest member, started from random
-    fields, against the oracle's runs of the same realizations."""
+    steps as one batch in member groups of at most 128 MB; the largest and the
+    smallest member, started from random fields, against the oracle's runs of the
+    same realizations."""
     import torch
     from gpu_common import field_rel_l2, pec_clean, rel_l2, run_oracle
     from paper_0802_3775_amd import fdtd as F
@@ -128,7 +134,7 @@ def test_ensemble_batch_members_match_the_oracle():
     for q in picks:  # random initial fields: every cell, the CPML and the wrap are busy from step 0
         cfgs[q]["init_fields"] = pec_clean(W.random_fields(cfgs[q]["grid"]["n"], seed=100 + q),
                                            cfgs[q]["grid"]["periodic"])
-    tune = {"block": 256, "tile_x": 32, "zchunk": 8, "graph_steps": 50}
+    tune = {"block": 256, "tile_x": 32, "zchunk": 8, "graph_steps": 50, "cache_mb": 128}
     plans = [F.Plan(c, max_steps=steps, tuning=tune) for c in cfgs]
     b = F.Batch(plans)
     b.step(steps)
