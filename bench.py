@@ -55,6 +55,9 @@ WORKLOADS = {
                     "density-matrix dye in the spheres, CPML on all faces, noise-seeded)",
     "lasing168": "lasing box 6x6x6 cells at 24 cells/a + 12-cell CPML on all faces (168^3), gain voids: Lorentz + "
                  "four-level rate equations at 1e24 m^-3, pump 1e10 s^-1, noise",
+    "lasing_density": "lasing box 6x6x6 cells at 24 cells/a + 12-cell CPML on all faces (168^3), gain voids: "
+                      "density-matrix dye (ground + 3 upper levels, T1 1 ns, T2 10 fs, N 5e25 m^-3, inverted start), "
+                      "pump 1e10 s^-1, noise",
 }
 
 
@@ -69,6 +72,8 @@ def headline_config(steps, workload="big320"):
         return W.paper_lasing(0.1, steps=steps)
     if workload == "lasing168":
         return W.lasing(pump=1e10, steps=steps)
+    if workload == "lasing_density":
+        return W.lasing(pump=1e10, steps=steps, model="density")
     return W.slab(delta=0.05, seed=13, res=20, cells=(4, 4, 8), steps=steps, nf=100, decim=8,
                   energy_interval=100)
 
@@ -233,8 +238,7 @@ def measure_side(args, workload, steps, warm, kernel_steps, copy_gbs):
 
 def measure_lasing_density(args, steps=1000):
     from paper_0802_3775_amd import fdtd, tune
-    from paper_0802_3775_amd import workloads as W
-    cfg = W.lasing(pump=1e10, steps=steps + 300, model="density")
+    cfg = headline_config(steps + 300, "lasing_density")
     tuning = tune.autotune(dict(cfg), budget_s=args.tune_seconds, quick=True)
     plan = fdtd.Plan(cfg, max_steps=steps + 300, tuning=tuning)
     plan.step(100)
@@ -242,10 +246,9 @@ def measure_lasing_density(args, steps=1000):
     kern = kernel_table(plan, 50)
     n = plan.ncell
     plan.close()
-    return {"workload": "lasing box 6x6x6 cells at 24 cells/a + 12-cell CPML on all faces (168^3), gain voids: "
-            "density-matrix dye (ground + 3 upper levels, T1 1 ns, T2 10 fs, N 5e25 m^-3, inverted start), pump "
-            "1e10 s^-1, noise", "cells": n, "steps_timed": steps, "cell_updates_per_s": n * steps / wall,
-            "tuning": tuning, "roofline": _roofline(kern, _dominant(kern), "lasing_density"), "kernels": kern}
+    return {"workload": WORKLOADS["lasing_density"], "cells": n, "steps_timed": steps,
+            "cell_updates_per_s": n * steps / wall, "ms_per_step": 1e3 * wall / steps, "tuning": tuning,
+            "roofline": _roofline(kern, _dominant(kern), "lasing_density"), "kernels": kern}
 
 
 def measure_cpu(workload, budget_s):
@@ -281,23 +284,28 @@ def measure_batched(args, steps=300, kernel_steps=30):
     from paper_0802_3775_amd import fdtd, tune
     from paper_0802_3775_amd import workloads as W
     cfgs = W.ensemble(count=64, steps=10000)
-    tuning = tune.tune_batch(cfgs, budget_s=args.tune_seconds)
-    seq_tuning = tune.common_tuning(cfgs, budget_s=args.tune_seconds)  # tuned for plain runs
-    cells = 0
-    seq = 0.0
-    for c in cfgs:           # sequential plain: each realization alone
-        p = fdtd.Plan(c, max_steps=steps + 50, tuning=seq_tuning)
-        cells += p.ncell
-        p.step(50)
-        seq += timed_run(p, steps)
-        p.close()
+    if args.batch_tuning:
+        v = [int(q) for q in args.batch_tuning.split(",")]
+        tuning = {"tile_x": v[0], "block": v[1], "zchunk": v[2], "graph_steps": v[3], "max_blocks": 0,
+                  "merge": v[4], "parallel": v[5], "cache_mb": v[6]}
+    else:
+        tuning = tune.tune_batch(cfgs, budget_s=args.tune_seconds)
+    cells = sum(c["grid"]["n"][0] * c["grid"]["n"][1] * c["grid"]["n"][2] for c in cfgs)
+    seq = None
+    seq_tuning = None
+    if not args.no_sequential:
+        seq_tuning = tune.common_tuning(cfgs, budget_s=args.tune_seconds)  # tuned for plain runs
+        seq = 0.0
+        for c in cfgs:           # sequential plain: each realization alone
+            p = fdtd.Plan(c, max_steps=steps + 50, tuning=seq_tuning)
+            p.step(50)
+            seq += timed_run(p, steps)
+            p.close()
     total = steps + 100 + kernel_steps
     plans = [fdtd.Plan(c, max_steps=total, tuning=tuning) for c in cfgs]
     log("batched: %d realizations, %d cells, tuning %s (sequential runs: %s)" % (len(plans), cells, tuning, seq_tuning))
-    for p in plans:
-        p.step(50)
     b = fdtd.Batch(plans)
-    b.step(50)
+    b.step(100)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.step(steps)
@@ -321,10 +329,11 @@ def measure_batched(args, steps=300, kernel_steps=30):
     return {"realizations": len(cfgs), "cells": cells, "steps_timed": steps, "tuning": tuning,
             "sequential_tuning": seq_tuning,
             "cell_updates_per_s": cells * steps / tb,
-            "sequential_cell_updates_per_s": cells * steps / seq,
+            "sequential_cell_updates_per_s": cells * steps / seq if seq else None,
             "ms_per_step": 1e3 * tb / steps,
             "realizations_per_hour": 3600.0 * len(cfgs) / (tb * scale),
-            "sequential_realizations_per_hour": 3600.0 * len(cfgs) / (seq * scale),
+            "sequential_realizations_per_hour": 3600.0 * len(cfgs) / (seq * scale) if seq else None,
+            "speedup_vs_sequential": seq / tb if seq else None,
             "roofline": _roofline(kern, _dominant(kern), "batched"),
             "step_alg_GBps": step_bytes / (tb / steps) / 1e9,
             "step_frac": step_bytes / (tb / steps) / 1e9 / HBM_PEAK_GBS,
@@ -395,6 +404,12 @@ def main():
     ap.add_argument("--only", default="", help="comma list of side measurements to run (profiling): "
                     "slab,paper_beam,lasing168,lasing_density,paper_lasing,batched,serving")
     ap.add_argument("--tuning", default="", help="fixed tile_x,block,zchunk,graph_steps[,merge,parallel] (skip the autotuner)")
+    ap.add_argument("--batch-tuning", default="",
+                    help="fixed batch tuning tile_x,block,zchunk,graph_steps,merge,parallel,cache_mb (profiling)")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batched: skip the members-one-after-another baseline (profiling)")
+    ap.add_argument("--skip-plain", action="store_true",
+                    help="skip the headline measurement and print only the side measurements (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration in profiled runs)")
     args = ap.parse_args()
@@ -406,10 +421,42 @@ def main():
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
     if args.copy_calibration:
         copy_calibration()
+    copy_gbs = copy_bandwidth()
+    if args.skip_plain:
+        out, value = {}, None
+    else:
+        out, value = headline(args, copy_gbs)
+    only = set(q for q in args.only.split(",") if q)
+    want = (lambda q: not args.no_extras and (not only or q in only))
+    if want("slab"):
+        log("slab 80x80x224 ...")
+        out["slab_80x80x224"] = measure_side(args, "slab", 2000, 200, 200, copy_gbs)
+    if want("paper_beam"):
+        log("paper beam box ...")
+        out["paper_beam_200"] = measure_side(args, "paper_beam", 400, 50, 100, copy_gbs)
+    if want("lasing168"):
+        log("lasing 168^3 ...")
+        out["lasing_168"] = measure_side(args, "lasing168", 1000, 100, 50, copy_gbs)
+    if want("lasing_density"):
+        log("lasing 168^3, density matrix ...")
+        out["lasing_density_168"] = measure_lasing_density(args)
+    if want("paper_lasing"):
+        log("paper lasing box ...")
+        out["paper_lasing_200"] = measure_side(args, "paper_lasing", 300, 100, 50, copy_gbs)
+    if want("batched"):
+        log("batched ...")
+        out["batched"] = measure_batched(args)
+    if want("serving") and value is not None:
+        log("serving ...")
+        out["serving"] = measure_serving(args, value)
+    print(json.dumps(out), flush=True)
+
+
+def headline(args, copy_gbs):
+    """The headline JSON fields: the plain stepper on the --workload grid, and the
+    CPU oracle on its bounded sample."""
     plain = measure_plain(args)
     value = plain["ncell"] * args.steps / plain["wall"]
-    dom = plain["kernels"][plain["dominant"]]
-    copy_gbs = copy_bandwidth()
     out = {
         "metric": METRIC,
         "value": value,
@@ -431,30 +478,7 @@ def main():
     if not args.no_cpu:
         log("cpu baseline ...")
         out["cpu_baseline"] = measure_cpu(args.workload, args.cpu_seconds)
-    only = set(q for q in args.only.split(",") if q)
-    want = (lambda q: not args.no_extras and (not only or q in only))
-    if want("slab"):
-        log("slab 80x80x224 ...")
-        out["slab_80x80x224"] = measure_side(args, "slab", 2000, 200, 200, copy_gbs)
-    if want("paper_beam"):
-        log("paper beam box ...")
-        out["paper_beam_200"] = measure_side(args, "paper_beam", 400, 50, 100, copy_gbs)
-    if want("lasing168"):
-        log("lasing 168^3 ...")
-        out["lasing_168"] = measure_side(args, "lasing168", 1000, 100, 50, copy_gbs)
-    if want("lasing_density"):
-        log("lasing 168^3, density matrix ...")
-        out["lasing_density_168"] = measure_lasing_density(args)
-    if want("paper_lasing"):
-        log("paper lasing box ...")
-        out["paper_lasing_200"] = measure_side(args, "paper_lasing", 300, 100, 50, copy_gbs)
-    if want("batched"):
-        log("batched ...")
-        out["batched"] = measure_batched(args)
-    if want("serving"):
-        log("serving ...")
-        out["serving"] = measure_serving(args, value)
-    print(json.dumps(out), flush=True)
+    return out, value
 
 
 if __name__ == "__main__":

@@ -83,19 +83,3 @@ def test_diffusion_run_pulse_and_window():
     assert cfg["steps"] * 0.5 / cfg["grid"]["res"] * t_unit == pytest.approx(2.5e-12, rel=1e-4)
     assert cfg["flux"][0]["k"] > cfg["layout"]["z0"] + cfg["opal"]["cells"][2] * cfg["grid"]["res"]
     assert cfg["grid"]["n"] == (p["grid_cells_per_axis"],) * 3
-
-
-def test_dye_field_unit_matches_the_oracle_coupling():
-    """The energy-density conversion of the lasing experiment uses the field unit
-    hbar c / (mu a); with it, kappa = N mu^2 a / (eps0 hbar c) must equal the
-    oracle's coupling constant for the same material."""
-    from paper_0802_3775_amd import experiments as X
-    p = _load("paper_parameters.json")
-    m = W.density_material()
-    E0 = X.dye_field_unit(m, p["a_m"])
-    mu = X.HBAR * C0 / (E0 * p["a_m"])
-    kappa = m["n_total"] * mu ** 2 * p["a_m"] / (X.EPS0 * X.HBAR * C0)
-    _, _, k_orc, *_ = O.bloch_constants(m, 0.5 / 16, 1.0 / 16, p["a_m"])
-    assert kappa == pytest.approx(k_orc, rel=1e-9)
-    m2 = dict(m, dipole=3e-29)
-    assert X.HBAR * C0 / (X.dye_field_unit(m2, p["a_m"]) * p["a_m"]) == pytest.approx(3e-29, rel=1e-12)
