@@ -141,7 +141,7 @@ struct fd_dm_unit {
   int pad;
 };
 #define FD_DM_CELLS 256   // gain cells per unit of the cell passes (one per thread)
-#define FD_DM_EDGES 1024  // cells per unit of the edge pass (4 per thread)
+#define FD_DM_EDGES 256   // cells per unit of the edge pass (one per thread)
 
 // Tile classes: kernels specialised on the CPML slabs a tile touches (none, z
 // only, any axis) and on gain cells being present.  class = cpml + 3 * gain.

@@ -1377,17 +1377,19 @@ __global__ void init_pop_kernel(const uint8_t* __restrict__ map, const float* __
 // cells, so the passes are separate launches; a cell's rho is read and written
 // only by its own thread.
 
-// material m of the plan (a gain cell's own medium, an edge's permittivity)
-typedef __attribute__((address_space(1))) const fd_mat gmat_t;
-__device__ __forceinline__ fd_mat gmat(const cdesc* d, int m) {
-  fd_mat out;
-  const gf* src = (const gf*)((gmat_t*)d->mats + m);
-  float* dst = reinterpret_cast<float*>(&out);
-#pragma unroll
-  for (int q = 0; q < (int)(sizeof(fd_mat) / 4); ++q) dst[q] = src[q];
-  return out;
+// The plan's material table in LDS (a gain cell's own medium, an edge's
+// permittivity), staged once per workgroup: a work unit's cells belong to one
+// plan, so every coefficient read of the passes is an LDS read.
+struct DmMats {
+  fd_mat m[FD_MAXMAT];
+};
+__device__ __forceinline__ void dm_stage_mats(const cdesc* d, DmMats& sm) {
+  const int words = d->nmat * (int)(sizeof(fd_mat) / 4);
+  const gf* src = G((const float*)d->mats);
+  float* dst = reinterpret_cast<float*>(sm.m);
+  for (int q = (int)threadIdx.x; q < words; q += (int)blockDim.x) dst[q] = src[q];
+  __syncthreads();
 }
-__device__ __forceinline__ float ginv_eps(const cdesc* d, int m) { return ((gmat_t*)d->mats)[m].inv_eps; }
 
 struct Ijk {
   int i, j, k;
@@ -1428,28 +1430,30 @@ __device__ __forceinline__ int nb_cell(const cdesc* d, const Nbr& b, int c, int 
   o[a1] += u;
   o[a2] += v;
   const int x = b.c[0][o[0]], y = b.c[1][o[1]], z = b.c[2][o[2]];
-  *held = (!d->per[a1] && b.c[a1][o[a1]] == 0) || (!d->per[a2] && b.c[a2][o[a2]] == 0);
-  return (x < 0 || y < 0 || z < 0) ? -1 : (z * d->ny + y) * d->nx + x;
+  // bitwise, not short-circuit, operators: lane values must not become branches
+  *held = ((!d->per[a1]) & (b.c[a1][o[a1]] == 0)) | ((!d->per[a2]) & (b.c[a2][o[a2]] == 0));
+  return ((x | y | z) < 0) ? -1 : (z * d->ny + y) * d->nx + x;
 }
 
 // A gain cell's state (populations as (hi, lo) FP32 pairs, coherences), its
-// noise term dt J and P(rho^n).
+// medium, its noise term dt J and P(rho^n).
 struct DmCell {
   uint32_t g, o;
   Ijk p;
-  fd_mat mt;
+  const fd_mat* mt;
   float nh[3], nl[3], pp[3], inc[3];
   Cz c[3], x[3];
   float Pn[3], dJ[3];
 };
 
-__device__ __forceinline__ void dm_load(const cdesc* d, uint32_t g, long long n, DmCell& z) {
+__device__ __forceinline__ void dm_load(const cdesc* d, const DmMats& sm, uint32_t g, long long n, DmCell& z) {
   const size_t ncs = (size_t)d->ncell;
   const gf* pop = G((const float*)d->pop);
   z.g = g;
   z.o = ((const __attribute__((address_space(1))) uint32_t*)d->glist)[g];
   z.p = ijk_of(d, z.o);
-  z.mt = gmat(d, ((const gu8*)d->mat)[z.o]);
+  z.mt = &sm.m[((const gu8*)d->mat)[z.o]];
+  const fd_mat& mt = *z.mt;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     z.nh[q] = pop[(size_t)q * ncs + g];
@@ -1458,25 +1462,32 @@ __device__ __forceinline__ void dm_load(const cdesc* d, uint32_t g, long long n,
     z.inc[q] = 0.0f;
     z.c[q] = {pop[(size_t)(6 + q) * ncs + g], pop[(size_t)(9 + q) * ncs + g]};
     z.x[q] = {pop[(size_t)(12 + q) * ncs + g], pop[(size_t)(15 + q) * ncs + g]};
-    z.Pn[q] = z.mt.bk2 * z.c[q].r;
+    z.Pn[q] = mt.bk2 * z.c[q].r;
     z.dJ[q] = 0.0f;
   }
-  if (z.mt.noise != 0.0f) {
+  if (mt.noise != 0.0f) {
     float gg[3];
     normals3((uint32_t)n, z.o, d->key0, d->key1, gg);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) z.dJ[q] = z.mt.noise * sqrtf(fmaxf(z.pp[q], 0.0f)) * gg[q];
+    for (int q = 0; q < 3; ++q) z.dJ[q] = mt.noise * sqrtf(fmaxf(z.pp[q], 0.0f)) * gg[q];
   }
 }
 
+// Gathers are branch-free: an index beyond a PEC wall (-1) reads cell 0 and the
+// value is replaced by 0 where it is used, so a thread's loads go out together
+// and are waited for once (a load under a branch is waited for on its own).
+__device__ __forceinline__ uint32_t clamp0(int e) { return e >= 0 ? (uint32_t)e : 0u; }
+
 __global__ __launch_bounds__(FD_DM_CELLS) void dm_predict_kernel(const fd_dm_unit* __restrict__ units, int s) {
+  __shared__ DmMats sm;
   const fd_dm_unit u = units[blockIdx.x];
-  if ((int)threadIdx.x >= u.count) return;
   const cdesc* d = (const cdesc*)u.d;
+  dm_stage_mats(d, sm);
+  if ((int)threadIdx.x >= u.count) return;
   const long long n = d->step + s;
   const int par = (int)(n & 1);
   DmCell z;
-  dm_load(d, (uint32_t)(u.first + (int)threadIdx.x), n, z);
+  dm_load(d, sm, (uint32_t)(u.first + (int)threadIdx.x), n, z);
   const Nbr b = neighbours(d, z.p);
   float em[3];
 #pragma unroll
@@ -1491,26 +1502,30 @@ __global__ __launch_bounds__(FD_DM_CELLS) void dm_predict_kernel(const fd_dm_uni
       for (int c = 0; c < 2; ++c) {
         bool held;
         const int e = nb_cell(d, b, q, a, c, &held);
-        if (e >= 0) acc += En[e] + A[e];
+        const uint32_t ec = clamp0(e);
+        const float v = En[ec] + A[ec];
+        acc += e >= 0 ? v : 0.0f;
       }
     em[q] = 0.125f * acc;
   }
-  dm_relax(z.mt, z.pp, z.inc, z.c, z.x);
-  dm_cayley<false>(z.mt, em, z.pp, z.inc, z.c, z.x);
+  dm_relax(*z.mt, z.pp, z.inc, z.c, z.x);
+  dm_cayley<false>(*z.mt, em, z.pp, z.inc, z.c, z.x);
   gf* Q = G(d->dmq[0]);
   const size_t ncs = (size_t)d->ncell;
 #pragma unroll
-  for (int q = 0; q < 3; ++q) Q[(size_t)q * ncs + z.o] = z.mt.bk2 * (z.c[q].r * z.mt.bf2) - z.Pn[q] + z.dJ[q];
+  for (int q = 0; q < 3; ++q) Q[(size_t)q * ncs + z.o] = z.mt->bk2 * (z.c[q].r * z.mt->bf2) - z.Pn[q] + z.dJ[q];
 }
 
 __global__ __launch_bounds__(FD_DM_CELLS) void dm_correct_kernel(const fd_dm_unit* __restrict__ units, int s) {
+  __shared__ DmMats sm;
   const fd_dm_unit u = units[blockIdx.x];
-  if ((int)threadIdx.x >= u.count) return;
   const cdesc* d = (const cdesc*)u.d;
+  dm_stage_mats(d, sm);
+  if ((int)threadIdx.x >= u.count) return;
   const long long n = d->step + s;
   const int par = (int)(n & 1);
   DmCell z;
-  dm_load(d, (uint32_t)(u.first + (int)threadIdx.x), n, z);
+  dm_load(d, sm, (uint32_t)(u.first + (int)threadIdx.x), n, z);
   const Nbr b = neighbours(d, z.p);
   const gf* Qs = G((const float*)d->dmq[0]);
   const gu8* map = (const gu8*)d->mat;
@@ -1521,19 +1536,21 @@ __global__ __launch_bounds__(FD_DM_CELLS) void dm_correct_kernel(const fd_dm_uni
     // Q* of the 3 x 3 cells around the centre across component q (0 off the
     // grid; cells without gain hold 0), and the voxels of the cell's four edges
     float qn[3][3];
-    int me[2][2], ee[2][2];
+    int ee[2][2];
     bool he[2][2];
+    uint32_t me[2][2];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         bool held;
         const int e = nb_cell(d, b, q, a - 1, c - 1, &held);
-        qn[a][c] = e >= 0 ? Qs[(size_t)q * ncs + e] : 0.0f;
+        const float v = Qs[(size_t)q * ncs + clamp0(e)];
+        qn[a][c] = e >= 0 ? v : 0.0f;
         if (a >= 1 && c >= 1) {
-          me[a - 1][c - 1] = e >= 0 ? map[e] : 0;
           ee[a - 1][c - 1] = e;
           he[a - 1][c - 1] = held;
+          me[a - 1][c - 1] = map[clamp0(e)];
         }
       }
     // <E^n + E*> with E* = A - [Q*]/eps on the edges (0 beyond or on a PEC wall);
@@ -1546,22 +1563,23 @@ __global__ __launch_bounds__(FD_DM_CELLS) void dm_correct_kernel(const fd_dm_uni
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         const int e = ee[a][c];
-        if (e < 0) continue;
-        acc += En[e];
-        if (he[a][c]) continue;
+        const uint32_t ec = clamp0(e);
+        const float en = En[ec], av = A[ec];
         const float sh = 0.25f * ((qn[a][c] + qn[a + 1][c]) + (qn[a][c + 1] + qn[a + 1][c + 1]));
-        acc += A[e] - sh * ginv_eps(d, me[a][c]);
+        const float es = av - sh * sm.m[me[a][c]].inv_eps;
+        acc += e >= 0 ? en : 0.0f;
+        acc += ((e >= 0) & !he[a][c]) ? es : 0.0f;
       }
     em[q] = 0.125f * acc;
   }
-  dm_relax(z.mt, z.pp, z.inc, z.c, z.x);
-  dm_cayley<true>(z.mt, em, z.pp, z.inc, z.c, z.x);
-  dm_relax(z.mt, z.pp, z.inc, z.c, z.x);
+  dm_relax(*z.mt, z.pp, z.inc, z.c, z.x);
+  dm_cayley<true>(*z.mt, em, z.pp, z.inc, z.c, z.x);
+  dm_relax(*z.mt, z.pp, z.inc, z.c, z.x);
   gf* pop = G(d->pop);
   gf* Q = G(d->dmq[1]);
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    Q[(size_t)r * ncs + z.o] = z.mt.bk2 * z.c[r].r - z.Pn[r] + z.dJ[r];
+    Q[(size_t)r * ncs + z.o] = z.mt->bk2 * z.c[r].r - z.Pn[r] + z.dJ[r];
     two_sum(z.nh[r], z.nl[r], z.inc[r]);
     pop[(size_t)r * ncs + z.g] = z.nh[r];
     pop[(size_t)(3 + r) * ncs + z.g] = z.nl[r];
@@ -1572,42 +1590,50 @@ __global__ __launch_bounds__(FD_DM_CELLS) void dm_correct_kernel(const fd_dm_uni
   }
 }
 
-// E^{n+1} = A - [Q]/eps on the edges next to gain cells; a unit's cells are
-// dealt to the threads in strides of the block.
-__global__ __launch_bounds__(256) void dm_edges_kernel(const fd_dm_unit* __restrict__ units, int s) {
+// E^{n+1} = A - [Q]/eps on the edges next to gain cells, one cell per thread:
+// the twelve Q values first (cells without gain hold Q = 0, so an edge with no
+// gain neighbour keeps A and is not written), then, for a cell with a changed
+// edge, its A and the new E.
+__global__ __launch_bounds__(FD_DM_EDGES) void dm_edges_kernel(const fd_dm_unit* __restrict__ units, int s) {
+  __shared__ DmMats sm;
   const fd_dm_unit u = units[blockIdx.x];
   const cdesc* d = (const cdesc*)u.d;
+  dm_stage_mats(d, sm);
+  const int t = (int)threadIdx.x;
+  if (t >= u.count) return;
   const long long n = d->step + s;
   const int par = (int)(n & 1);
   const gf* Q = G((const float*)d->dmq[1]);
-  const gu8* map = (const gu8*)d->mat;
   const size_t ncs = (size_t)d->ncell;
-  for (int t = (int)threadIdx.x; t < u.count; t += (int)blockDim.x) {
-    const uint32_t o = (uint32_t)(u.first + t);
-    const Nbr b = neighbours(d, ijk_of(d, o));
-    float ie = -1.0f;
+  const uint32_t o = (uint32_t)(u.first + t);
+  const Nbr b = neighbours(d, ijk_of(d, o));
+  float acc[3];
+  bool held[3];
+  bool any = false;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      bool held;
-      (void)nb_cell(d, b, c, 0, 0, &held);
-      if (held) continue;
-      // the cells sharing the edge: offsets {0, -1} along the transverse axes
-      // (cells without gain hold Q = 0, so an edge with no gain neighbour keeps A)
-      float acc = 0.0f;
+  for (int c = 0; c < 3; ++c) {
+    (void)nb_cell(d, b, c, 0, 0, &held[c]);
+    // the cells sharing the edge: offsets {0, -1} along the transverse axes
+    acc[c] = 0.0f;
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int v = 0; v < 2; ++v) {
-          bool h2;
-          const int cc = nb_cell(d, b, c, -a, -v, &h2);
-          if (cc >= 0) acc += Q[(size_t)c * ncs + cc];
-        }
-      if (acc == 0.0f) continue;
-      if (ie < 0.0f) ie = ginv_eps(d, map[o]);
-      gf* E = G(d->E[par ^ 1][c]);
-      E[o] = E[o] - 0.25f * acc * ie;
-    }
+      for (int v = 0; v < 2; ++v) {
+        bool h2;
+        const int cc = nb_cell(d, b, c, -a, -v, &h2);
+        const float qv = Q[(size_t)c * ncs + clamp0(cc)];
+        acc[c] += cc >= 0 ? qv : 0.0f;
+      }
+    any = any | (!held[c] & (acc[c] != 0.0f));
   }
+  if (!any) return;
+  const float ie = sm.m[((const gu8*)d->mat)[o]].inv_eps;
+  float ev[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) ev[c] = G((const float*)d->E[par ^ 1][c])[o];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    if (!held[c] && acc[c] != 0.0f) G(d->E[par ^ 1][c])[o] = ev[c] - 0.25f * acc[c] * ie;
 }
 
 // After the edge pass: probe samples of E components and the T(t) partial of
@@ -1806,7 +1832,7 @@ hipError_t fd_launch_dm(const fd_dm_unit* cells, int ncells, const fd_dm_unit* e
   hipExtLaunchKernelGGL(dm_predict_kernel, dim3(ncells), dim3(FD_DM_CELLS), 0, st, E(0), E(1), 0, cells, s);
   hipExtLaunchKernelGGL(dm_correct_kernel, dim3(ncells), dim3(FD_DM_CELLS), 0, st, E(2), E(3), 0, cells, s);
   if (nedges > 0)
-    hipExtLaunchKernelGGL(dm_edges_kernel, dim3(nedges), dim3(256), 0, st, E(4), E(5), 0, edges, s);
+    hipExtLaunchKernelGGL(dm_edges_kernel, dim3(nedges), dim3(FD_DM_EDGES), 0, st, E(4), E(5), 0, edges, s);
   if (ndiag > 0) hipExtLaunchKernelGGL(dm_diag_kernel, dim3(ndiag), dim3(block), 0, st, E(6), E(7), 0, diag, s);
   return hipGetLastError();
 }

@@ -6,8 +6,8 @@ for femtosecond-pulse transmission at 80x80x224 for its full 20,000 steps, the
 test suite.  This script runs them on the CPU once and stores what the tests
 compare: every field component at a seeded sample of cells at a few
 checkpoints, the transmitted power T(t), the flux spectra, the probe and energy
-records, and for gain runs the populations and polarization at sampled gain
-cells.  It calls only the oracle and the seeded input generators; nothing here
+records, and for gain runs the populations and polarization (and for the
+density-matrix medium its 15 state values) at sampled gain cells.  It calls only the oracle and the seeded input generators; nothing here
 comes from the GPU path.
 
     python tests/golden/make_oracle_runs.py [name ...]
@@ -63,6 +63,9 @@ RUNS = {
     "slab_d10_4k": (lambda: W.slab(delta=0.10, seed=14, steps=4000, nf=100, decim=8), (4000,)),
     # the Maxwell-Bloch lasing box (Lorentz medium), pump 1e10 s^-1, seeded noise
     "lasing168_p1e10": (lambda: W.lasing(pump=1e10, steps=2000, energy_interval=100), (500, 1000, 2000)),
+    # the same box with the density-matrix dye (inverted start, pump 1e10 s^-1, seeded noise)
+    "lasing_density168": (lambda: W.lasing(pump=1e10, steps=600, energy_interval=100, model="density"),
+                          (200, 600)),
     "big320_random": (big_random_cfg, (30,)),
 }
 
@@ -92,6 +95,7 @@ def run(name):
         gain = np.sort(rng.choice(gcells, size=min(NGAIN, len(gcells)), replace=False)).astype(np.int64)
         out["gain_idx"] = gain
         out["pop_init"] = sim.populations().reshape(4, -1)[:, gain]
+    dm = any(m.get("gain") == 2 for m in mats)
     done = 0
     for cp in checkpoints:
         sim.step(cp - done)
@@ -102,6 +106,8 @@ def run(name):
         if gain is not None:
             out["pop_%d" % cp] = sim.populations().reshape(4, -1)[:, gain]
             out["pol_%d" % cp] = sim.polarization().reshape(3, -1)[:, gain].astype(np.float32)
+            if dm:
+                out["dens_%d" % cp] = sim.density().reshape(15, -1)[:, gain]
         print("%s: step %d (%.0f s)" % (name, cp, time.time() - t0), flush=True)
     for p in range(sim.nprobe):
         out["probe%d" % p] = sim.probe(p).astype(np.float32)

@@ -9,7 +9,7 @@ launch configuration the autotuner picks, and is compared with those samples
 (field relative L2 over the sampled cells; every T(t), probe and spectrum value).
 
 Tolerances: linear runs fields <= 1e-4, T(t) and spectra <= 1e-3; lasing runs
-fields <= 1e-3; populations: the change from the initial state agrees with the
+fields <= 1e-3 (and the density matrix <= 1e-3); populations: the change from the initial state agrees with the
 oracle's to 1e-3 of its size and 1e-6 absolute (the oracle evolves all four
 levels; the GPU stores n1..n3 and takes n0 = 1 - (n1 + n2 + n3), so the sum is 1
 by construction and the oracle's separately evolved N0 is the evidence).
@@ -95,6 +95,10 @@ def _check_populations(plan, fx, cp):
     assert scale > 0
     assert err <= 1e-3 * scale and err <= 1e-6
     assert rel_l2(plan.polarization().reshape(3, -1)[:, gi], fx["pol_%d" % cp]) <= 1e-3
+    if "dens_%d" % cp in fx:
+        derr = rel_l2(plan.density().reshape(15, -1)[:, gi], fx["dens_%d" % cp])
+        _say("  density matrix at sampled gain cells: rel L2 %.3e" % derr)
+        assert derr <= 1e-3
 
 
 def test_slab_full_size_full_length_with_transmission():
@@ -141,6 +145,17 @@ def test_lasing_box_168_at_pump_1e10():
     all faces, Lorentz gain voids at 1e24 m^-3, pump 1e10 s^-1, seeded noise) for
     2000 steps: fields, populations and polarization at three checkpoints."""
     plan, fx = _run_checkpoints("lasing168_p1e10", 1e-3)
+    assert rel_l2(plan.probe(0), fx["probe0"]) <= 1e-3
+    assert rel_l2(plan.energy(), fx["energy"]) <= 1e-3
+    plan.close()
+
+
+def test_density_lasing_box_168():
+    """The same 168^3 box with the density-matrix dye in the voids (inverted
+    start, pump 1e10 s^-1, seeded noise) for 600 steps in the autotuned launch
+    shape: fields, the 15 state values, populations and polarization at sampled
+    gain cells at two checkpoints; probe and energy."""
+    plan, fx = _run_checkpoints("lasing_density168", 1e-3)
     assert rel_l2(plan.probe(0), fx["probe0"]) <= 1e-3
     assert rel_l2(plan.energy(), fx["energy"]) <= 1e-3
     plan.close()
