@@ -133,7 +133,13 @@ fd_xcd xcd_partition(const std::vector<double>& cost, int* grid) {
 struct fdtd_plan {
   fdtd_grid_desc g{};
   double dx = 0, dt = 0;
-  int64_t ncell = 0;
+  int64_t ncell = 0;   // cells of the grid
+  // Device layout: rows of px >= nx cells (nx rounded up to 32 cells, 128 bytes,
+  // so that every row of every per-cell array starts on a cache line), nstore =
+  // px ny nz cells per array; the padding cells are never written.  Host-side
+  // arrays (material map, fields read and written) are dense.
+  int px = 0;
+  int64_t nstore = 0;
   std::vector<fdtd_material> mats;
   bool have_opal = false;
   fdtd_opal_desc opal{};
@@ -365,13 +371,30 @@ double source_sigma_t(const fdtd_source_desc& s) {
 }
 
 int axis_n(const fdtd_plan* p, int w) { return w == 0 ? p->g.nx : (w == 1 ? p->g.ny : p->g.nz); }
+// Row pitch of the device arrays: x extents above 32 cells are padded to a
+// multiple of 32 (128-byte rows).  With unpadded rows of, say, 200 cells a
+// 32-wide tile row straddles two cache lines in three rows of four; padded, the
+// all-axes CPML kernel on a 200^3 box measured 106 -> 77 us.
+int row_pitch(int nx) { return nx <= 32 ? nx : (nx + 31) / 32 * 32; }
+// Device (padded) index of host (dense) cell o.
+size_t pitched(const fdtd_plan* p, size_t o) { return (o / (size_t)p->g.nx) * (size_t)p->px + o % (size_t)p->g.nx; }
+// Copies between a dense host array of ncell elements of elem bytes and the
+// padded device array at dev (one row of nx elements per (j, k)).
+hipError_t copy_rows_to_device(const fdtd_plan* p, void* dev, const void* host, size_t elem, hipStream_t st) {
+  const size_t w = elem * (size_t)p->g.nx;
+  return hipMemcpy2DAsync(dev, elem * (size_t)p->px, host, w, w, (size_t)p->g.ny * p->g.nz, hipMemcpyHostToDevice, st);
+}
+hipError_t copy_rows_to_host(const fdtd_plan* p, void* host, const void* dev, size_t elem, hipStream_t st) {
+  const size_t w = elem * (size_t)p->g.nx;
+  return hipMemcpy2DAsync(host, w, dev, elem * (size_t)p->px, w, (size_t)p->g.ny * p->g.nz, hipMemcpyDeviceToHost, st);
+}
 int pml_t(const fdtd_plan* p, int w) {
   return p->g.bc[w] == FDTD_BC_PEC ? p->g.pml_lo[w] + p->g.pml_hi[w] : 0;
 }
 size_t psi_elems(const fdtd_plan* p, int w) {
   const size_t t = (size_t)pml_t(p, w);
   const size_t nx = p->g.nx, ny = p->g.ny, nz = p->g.nz;
-  if (w == 2) return t * nx * ny;
+  if (w == 2) return t * (size_t)p->px * ny;  // z slabs are whole (padded) planes
   if (w == 0) return nz * ny * t;
   return nz * t * nx;
 }
@@ -393,6 +416,7 @@ int gain_model_of(const std::vector<fdtd_material>& mats) {
 constexpr size_t kInfinityCacheBytes = (size_t)256 << 20;
 constexpr size_t kNonTemporalBytes = 4 * kInfinityCacheBytes;
 size_t step_state_bytes(const fdtd_plan* p) {
+  // (the cells a step touches: row padding is never read or written)
   size_t b = (size_t)p->ncell * 49;
   for (int w = 0; w < 3; ++w) b += 6 * 4 * psi_elems(p, w);
   if (p->has_gain) b += (size_t)p->ncell * (p->gm == 2 ? 144 : 48);
@@ -436,7 +460,7 @@ int compute_layout(fdtd_plan* p, int64_t max_steps, Layout& L) {
     off = align256(off + bytes);
     return at;
   };
-  const size_t nc = (size_t)p->ncell;
+  const size_t nc = (size_t)p->nstore;
   const int gm = gain_model_of(p->mats);
   L.desc = take(sizeof(fd_desc));
   L.mats = take(sizeof(fd_mat) * FD_MAXMAT);
@@ -469,14 +493,14 @@ int compute_layout(fdtd_plan* p, int64_t max_steps, Layout& L) {
       len = std::min<int64_t>(std::max<int64_t>(len, 1), std::max<int64_t>(max_steps, 1));
       p->src_len[q] = (int)len;
       L.src[q] = take(sizeof(float) * (size_t)len);
-      L.srcprof[q] = s.kind == FDTD_SRC_BEAM ? take(sizeof(float) * (size_t)p->g.nx * p->g.ny) : 0;
+      L.srcprof[q] = s.kind == FDTD_SRC_BEAM ? take(sizeof(float) * (size_t)p->px * p->g.ny) : 0;
     } else {
       p->src_len[q] = 0;
       L.src[q] = 0;
       L.srcprof[q] = 0;
     }
   }
-  const int plane = p->g.nx * p->g.ny;
+  const int plane = p->px * p->g.ny;  // flux-plane points, padded rows
   const int TX = p->tune.tile_x, TY = p->tune.block / p->tune.tile_x;
   p->nblk = ((p->g.nx + TX - 1) / TX) * ((p->g.ny + TY - 1) / TY);
   const auto chunks = z_chunks(p, std::max(1, p->tune.zchunk));
@@ -540,11 +564,12 @@ int build_dm_units(fdtd_plan* p) {
   const int ng = d.ngain;
   for (int g0 = 0; g0 < ng; g0 += FD_DM_CELLS) p->dmu[0].push_back({p->ddesc, g0, std::min(FD_DM_CELLS, ng - g0), 0});
   if (ng > 0) {
-    const int plane = d.plane, nz = p->g.nz;
+    const int plane = d.plane, nz = p->g.nz;  // padded plane of the device cell index
+    const int hplane = p->g.nx * p->g.ny;     // dense plane of the host map
     int kmin = nz, kmax = -1;
     for (int k = 0; k < nz; ++k)
-      for (int c = 0; c < plane; ++c)
-        if (p->mats[p->host_map[(size_t)k * plane + c]].gain) {
+      for (int c = 0; c < hplane; ++c)
+        if (p->mats[p->host_map[(size_t)k * hplane + c]].gain) {
           kmin = std::min(kmin, k);
           kmax = std::max(kmax, k);
           break;
@@ -577,21 +602,22 @@ int build_dm_units(fdtd_plan* p) {
           touched += any ? 1 : 0;
         }
     p->dm_cells[0] = p->dm_cells[1] = ng;
-    p->dm_cells[2] = last - first;
+    p->dm_cells[2] = (int64_t)(k1 - k0) * hplane;  // the range's cells (its padding is skipped)
     // predictor: state 72 + E^n and A of the cell's edges 24 + map and list 5
     // + Q* 12; corrector: state 72 + 72, fields 24, neighbours' Q* 12, Q 12,
     // map and list 5; edges: Q of the range 12, and for a cell whose edges touch
     // gain A in and E out 24 + its map 1
     p->dm_bytes[0] = 113.0 * ng;
     p->dm_bytes[1] = 197.0 * ng;
-    p->dm_bytes[2] = 12.0 * (double)(last - first) + 25.0 * (double)touched;
+    p->dm_bytes[2] = 12.0 * (double)p->dm_cells[2] + 25.0 * (double)touched;
   }
   for (int f = 0; f < (int)p->flux.size(); ++f)
     for (int b = 0; b < p->nblk; ++b) p->dmu[2].push_back({p->ddesc, f, b, 0});
   p->dmu[2].push_back({p->ddesc, -1, 0, 0});
-  p->dm_cells[3] = (int64_t)p->flux.size() * d.plane + (int64_t)p->probes.size();
+  const int64_t fpts = (int64_t)p->g.nx * p->g.ny;  // a flux plane's points (its padding is skipped)
+  p->dm_cells[3] = (int64_t)p->flux.size() * fpts + (int64_t)p->probes.size();
   // E^n, E^{n+1} (x, y) and H at two planes (x, y) per flux-plane point; a probe sample
-  p->dm_bytes[3] = 32.0 * (double)p->flux.size() * d.plane + 8.0 * (double)p->probes.size();
+  p->dm_bytes[3] = 32.0 * (double)p->flux.size() * (double)fpts + 8.0 * (double)p->probes.size();
   p->ddm = at<fd_dm_unit>(p, p->L.dmunits);
   size_t off = 0;
   for (int q = 0; q < 3; ++q) {
@@ -712,6 +738,12 @@ int fdtd_plan_create(const fdtd_grid_desc* g, fdtd_plan** out) {
   p->dx = 1.0 / g->res;
   p->dt = g->courant * p->dx;
   p->ncell = ncell;
+  p->px = row_pitch(g->nx);
+  p->nstore = (int64_t)p->px * g->ny * g->nz;
+  if (p->nstore > (int64_t)1 << 30) {
+    delete p;
+    return fail(FDTD_EUNSUPPORTED, "more than 2^30 cells with rows padded to %d", row_pitch(g->nx));
+  }
   fdtd_material vac{};
   vac.eps = 1.0;
   p->mats.push_back(vac);
@@ -954,9 +986,10 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
   fd_desc& d = p->hdesc;
   std::memset(&d, 0, sizeof d);
   d.nx = p->g.nx; d.ny = p->g.ny; d.nz = p->g.nz;
-  d.plane = p->g.nx * p->g.ny;
+  d.px = p->px;
+  d.plane = p->px * p->g.ny;
   for (int w = 0; w < 3; ++w) d.per[w] = p->g.bc[w] == FDTD_BC_PERIODIC ? 1 : 0;
-  d.ncell = (int)p->ncell;
+  d.ncell = (int)p->nstore;
   d.ch = (float)(p->dt / p->dx);
   d.nmat = (int)p->mats.size();
   d.has_gain = p->has_gain ? 1 : 0;
@@ -1019,19 +1052,19 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
     d.src_kind[q] = s.kind;
     d.src_comp[q] = s.comp;
     d.src_k[q] = s.k;
-    d.src_cell[q] = s.kind == FDTD_SRC_DIPOLE ? s.j * p->g.nx + s.i : -1;
+    d.src_cell[q] = s.kind == FDTD_SRC_DIPOLE ? s.j * p->px + s.i : -1;
     d.src_len[q] = p->src_len[q];
     d.src_tab[q] = at<float>(p, L.src[q]);
     d.src_prof[q] = nullptr;
     if (s.kind == FDTD_SRC_BEAM) {
       // TEM00 waist profile at the driven component's Yee position (FP64, stored FP32)
-      std::vector<float> prof((size_t)p->g.nx * p->g.ny);
+      std::vector<float> prof((size_t)p->px * p->g.ny, 0.0f);
       for (int j = 0; j < p->g.ny; ++j)
         for (int i = 0; i < p->g.nx; ++i) {
           const double x = ((double)i + (s.comp == 0 ? 0.5 : 0.0)) * p->dx;
           const double y = ((double)j + (s.comp == 1 ? 0.5 : 0.0)) * p->dx;
           const double rx = x - s.x0, ry = y - s.y0;
-          prof[(size_t)j * p->g.nx + i] = (float)std::exp(-(rx * rx + ry * ry) / (s.waist * s.waist));
+          prof[(size_t)j * p->px + i] = (float)std::exp(-(rx * rx + ry * ry) / (s.waist * s.waist));
         }
       HIPCHK(hipMemcpyAsync(p->arena + L.srcprof[q], prof.data(), sizeof(float) * prof.size(),
                             hipMemcpyHostToDevice, st));
@@ -1043,7 +1076,7 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
   d.nprobe = (int)p->probes.size();
   for (int q = 0; q < d.nprobe; ++q) {
     d.probe_comp[q] = p->probes[q][0];
-    d.probe_cell[q] = p->probes[q][2] * p->g.nx + p->probes[q][1];
+    d.probe_cell[q] = p->probes[q][2] * p->px + p->probes[q][1];
     d.probe_k[q] = p->probes[q][3];
   }
   d.probe_ring = at<float>(p, L.probe);
@@ -1119,31 +1152,34 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
     }
     HIPCHK(hipMemcpyAsync(p->arena + L.sites, sites.data(), sizeof(int64_t) * sites.size(), hipMemcpyHostToDevice, st));
     HIPCHK(fd_launch_voxelize(at<int64_t>(p, L.sites), ext[0], ext[1], ext[2], per, ncr, o.origin, reach, p->g.res,
-                              o.mat_bg, o.mat_void, o.mat_out, p->g.nx, p->g.ny, p->g.nz, at<uint8_t>(p, L.map), st));
+                              o.mat_bg, o.mat_void, o.mat_out, p->g.nx, p->g.ny, p->g.nz, p->px,
+                              at<uint8_t>(p, L.map), st));
     p->host_map.resize((size_t)p->ncell);
-    HIPCHK(hipMemcpyAsync(p->host_map.data(), p->arena + L.map, (size_t)p->ncell, hipMemcpyDeviceToHost, st));
+    HIPCHK(copy_rows_to_host(p, p->host_map.data(), p->arena + L.map, 1, st));
     HIPCHK(hipStreamSynchronize(st));
   } else {
-    HIPCHK(hipMemcpyAsync(p->arena + L.map, p->host_map.data(), (size_t)p->ncell, hipMemcpyHostToDevice, st));
+    HIPCHK(copy_rows_to_device(p, p->arena + L.map, p->host_map.data(), 1, st));
     HIPCHK(hipStreamSynchronize(st));
   }
   if (p->has_gain) {
     // gain ordinals (gain cells numbered in cell order) and the initial
     // populations at them; the rest of the state starts at zero with the arena
+    // (the order of cells is the same in the dense and the padded layout)
     const size_t nc = (size_t)p->ncell;
     p->gidx.assign(nc, 0u);
     uint32_t g = 0;
     for (size_t o = 0; o < nc; ++o)
       if (p->mats[p->host_map[o]].gain) p->gidx[o] = g++;
-    HIPCHK(hipMemcpyAsync(p->arena + L.gidx, p->gidx.data(), sizeof(uint32_t) * nc, hipMemcpyHostToDevice, st));
+    HIPCHK(copy_rows_to_device(p, p->arena + L.gidx, p->gidx.data(), sizeof(uint32_t), st));
     HIPCHK(fd_launch_init_pop(at<uint8_t>(p, L.map), at<float>(p, L.ninit), at<uint32_t>(p, L.gidx), d.gainmask,
-                              d.pop, d.ncell, st));
+                              d.pop, d.ncell, d.nx, d.px, st));
+    HIPCHK(hipStreamSynchronize(st));
     d.ngain = (int)g;
     if (p->gm == 2) {
-      // the cell of each gain ordinal, for the density-matrix passes
+      // the (padded) cell of each gain ordinal, for the density-matrix passes
       std::vector<uint32_t> glist(g);
       for (size_t o = 0; o < nc; ++o)
-        if (p->mats[p->host_map[o]].gain) glist[p->gidx[o]] = (uint32_t)o;
+        if (p->mats[p->host_map[o]].gain) glist[p->gidx[o]] = (uint32_t)pitched(p, o);
       if (g) HIPCHK(hipMemcpyAsync(p->arena + L.glist, glist.data(), sizeof(uint32_t) * g, hipMemcpyHostToDevice, st));
     }
     HIPCHK(hipMemcpyAsync(p->ddesc, &d, sizeof d, hipMemcpyHostToDevice, st));
@@ -1151,7 +1187,7 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
   }
 
   // tiles, classified by CPML and gain presence
-  const int plane = d.plane;
+  const int plane = p->g.nx * p->g.ny;  // dense plane of the host map
   const int TX = p->tune.tile_x, TY = p->tune.block / p->tune.tile_x;
   const int ntx = (p->g.nx + TX - 1) / TX, nty = (p->g.ny + TY - 1) / TY;
   const auto chunks = z_chunks(p, std::max(1, p->tune.zchunk));
@@ -1198,13 +1234,13 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
         for (int q = 0; q < d.nsrc; ++q) {
           if (d.src_k[q] < t.k0 || d.src_k[q] >= t.k1) continue;
           if (d.src_kind[q] == FDTD_SRC_DIPOLE) {
-            const int si = d.src_cell[q] % p->g.nx, sj = d.src_cell[q] / p->g.nx;
+            const int si = d.src_cell[q] % p->px, sj = d.src_cell[q] / p->px;
             if (si < t.i0 || si >= t.i0 + TX || sj < t.j0 || sj >= t.j0 + TY) continue;
           }
           t.srcmask |= 1u << q;
         }
         for (int q = 0; q < d.nprobe; ++q) {
-          const int pi = d.probe_cell[q] % p->g.nx, pj = d.probe_cell[q] / p->g.nx;
+          const int pi = d.probe_cell[q] % p->px, pj = d.probe_cell[q] / p->px;
           if (d.probe_k[q] >= t.k0 && d.probe_k[q] < t.k1 && pi >= t.i0 && pi < t.i0 + TX && pj >= t.j0 &&
               pj < t.j0 + TY)
             t.pmask |= 1u << q;
@@ -1264,7 +1300,7 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
   p->dft.clear();
   for (int f = 0; f < d.nflux; ++f) {
     if (p->flux[f].nf == 0) continue;
-    for (int p0 = 0; p0 < plane; p0 += FD_DFT_PTS)
+    for (int p0 = 0; p0 < d.plane; p0 += FD_DFT_PTS)  // the padded plane's points
       for (int q0 = 0; q0 < p->flux[f].nf; q0 += FD_DFT_QB) {
         fd_dft_tile t{};
         t.d = p->ddesc;
@@ -1291,7 +1327,7 @@ int fdtd_get_material_map(fdtd_plan* p, uint8_t* host_map, void* stream) {
   if (!p || !host_map) return fail(FDTD_EINVAL, "null argument");
   if (!p->bound) return fail(FDTD_ESTATE, "plan not bound");
   hipStream_t st = (hipStream_t)stream;
-  HIPCHK(hipMemcpyAsync(host_map, p->arena + p->L.map, (size_t)p->ncell, hipMemcpyDeviceToHost, st));
+  HIPCHK(copy_rows_to_host(p, host_map, p->arena + p->L.map, 1, st));
   HIPCHK(hipStreamSynchronize(st));
   return FDTD_OK;
 }
@@ -1357,7 +1393,7 @@ int fdtd_read_field(fdtd_plan* p, int32_t comp, float* host, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   const int par = (int)(p->step & 1);
   const size_t off = comp < 3 ? p->L.E[par][comp] : p->L.H[par][comp - 3];
-  HIPCHK(hipMemcpyAsync(host, p->arena + off, sizeof(float) * (size_t)p->ncell, hipMemcpyDeviceToHost, st));
+  HIPCHK(copy_rows_to_host(p, host, p->arena + off, sizeof(float), st));
   HIPCHK(hipStreamSynchronize(st));
   return FDTD_OK;
 }
@@ -1369,7 +1405,7 @@ int fdtd_write_field(fdtd_plan* p, int32_t comp, const float* host, void* stream
   hipStream_t st = (hipStream_t)stream;
   const int par = (int)(p->step & 1);
   const size_t off = comp < 3 ? p->L.E[par][comp] : p->L.H[par][comp - 3];
-  HIPCHK(hipMemcpyAsync(p->arena + off, host, sizeof(float) * (size_t)p->ncell, hipMemcpyHostToDevice, st));
+  HIPCHK(copy_rows_to_device(p, p->arena + off, host, sizeof(float), st));
   HIPCHK(hipStreamSynchronize(st));
   return FDTD_OK;
 }
@@ -1405,7 +1441,7 @@ int fdtd_read_flux(fdtd_plan* p, int32_t id, double* T, double* spec, int64_t* n
   }
   const Flux& fl = p->flux[id];
   if (spec && fl.nf > 0) {
-    const size_t plane = (size_t)p->g.nx * p->g.ny;
+    const size_t plane = (size_t)p->px * p->g.ny;  // padded points (their sums stay 0)
     std::vector<double> acc(2 * 4 * (size_t)fl.nf * plane);
     // samples taken at steps 0, decim, ... < step; complete rings are already in
     // the sums, the rest is added into a copy
@@ -1440,8 +1476,8 @@ int fdtd_read_populations(fdtd_plan* p, float* host, void* stream) {
   if (!p->bound) return fail(FDTD_ESTATE, "plan not bound");
   if (!p->has_gain) return fail(FDTD_ESTATE, "no gain material");
   hipStream_t st = (hipStream_t)stream;
-  const size_t nc = (size_t)p->ncell;
-  std::vector<float> pop(6 * nc);
+  const size_t nc = (size_t)p->ncell, ns = (size_t)p->nstore;  // host and device plane strides
+  std::vector<float> pop(6 * ns);
   HIPCHK(hipMemcpyAsync(pop.data(), p->arena + p->L.pop, sizeof(float) * pop.size(), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   for (size_t o = 0; o < nc; ++o) {
@@ -1451,7 +1487,7 @@ int fdtd_read_populations(fdtd_plan* p, float* host, void* stream) {
     }
     const size_t q = p->gidx[o];  // state index of the cell
     double lv[3];
-    for (int l = 0; l < 3; ++l) lv[l] = (double)pop[l * nc + q] + (double)pop[(3 + l) * nc + q];
+    for (int l = 0; l < 3; ++l) lv[l] = (double)pop[l * ns + q] + (double)pop[(3 + l) * ns + q];
     host[0 * nc + o] = (float)(1.0 - (lv[0] + lv[1] + lv[2]));
     for (int l = 0; l < 3; ++l) host[(1 + l) * nc + o] = (float)lv[l];
   }
@@ -1463,10 +1499,10 @@ int fdtd_read_polarization(fdtd_plan* p, float* host, void* stream) {
   if (!p->bound) return fail(FDTD_ESTATE, "plan not bound");
   if (!p->has_gain) return fail(FDTD_ESTATE, "no gain material");
   hipStream_t st = (hipStream_t)stream;
-  const size_t nc = (size_t)p->ncell;
+  const size_t nc = (size_t)p->ncell, ns = (size_t)p->nstore;
   if (p->gm == 2) {  // P_c = 2 kappa Re rho_0c of each gain cell's material
-    std::vector<float> re(3 * nc);
-    HIPCHK(hipMemcpyAsync(re.data(), p->arena + p->L.pop + sizeof(float) * 6 * nc, sizeof(float) * re.size(),
+    std::vector<float> re(3 * ns);
+    HIPCHK(hipMemcpyAsync(re.data(), p->arena + p->L.pop + sizeof(float) * 6 * ns, sizeof(float) * re.size(),
                           hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     std::vector<float> k2(p->mats.size(), 0.0f);
@@ -1475,7 +1511,7 @@ int fdtd_read_polarization(fdtd_plan* p, float* host, void* stream) {
       if (p->mats[m].gain && build_material(p, p->mats[m], mt) == FDTD_OK) k2[m] = mt.bk2;
     }
     for (int c = 0; c < 3; ++c)
-      for (size_t o = 0; o < nc; ++o) host[c * nc + o] = k2[p->host_map[o]] * re[c * nc + p->gidx[o]];
+      for (size_t o = 0; o < nc; ++o) host[c * nc + o] = k2[p->host_map[o]] * re[c * ns + p->gidx[o]];
     return FDTD_OK;
   }
   const int par = (int)(p->step & 1);
@@ -1495,15 +1531,16 @@ int fdtd_read_density(fdtd_plan* p, float* host, void* stream) {
   if (p->gm != 2) return fail(FDTD_ESTATE, "no density-matrix gain material");
   hipStream_t st = (hipStream_t)stream;
   const size_t nc = (size_t)p->ncell;
-  std::vector<float> st18(18 * nc);
+  const size_t ns = (size_t)p->nstore;
+  std::vector<float> st18(18 * ns);
   HIPCHK(hipMemcpyAsync(st18.data(), p->arena + p->L.pop, sizeof(float) * st18.size(), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   for (size_t o = 0; o < nc; ++o) {
     const bool g = p->mats[p->host_map[o]].gain != 0;
     const size_t q = p->gidx[o];
     for (int l = 0; l < 3; ++l)
-      host[l * nc + o] = g ? (float)((double)st18[l * nc + q] + (double)st18[(3 + l) * nc + q]) : 0.0f;
-    for (int l = 3; l < 15; ++l) host[l * nc + o] = g ? st18[(3 + l) * nc + q] : 0.0f;
+      host[l * nc + o] = g ? (float)((double)st18[l * ns + q] + (double)st18[(3 + l) * ns + q]) : 0.0f;
+    for (int l = 3; l < 15; ++l) host[l * nc + o] = g ? st18[(3 + l) * ns + q] : 0.0f;
   }
   return FDTD_OK;
 }
@@ -1702,6 +1739,8 @@ fdtd_plan* clone_description(const fdtd_plan* p, const fdtd_tuning& t) {
   c->dx = p->dx;
   c->dt = p->dt;
   c->ncell = p->ncell;
+  c->px = p->px;
+  c->nstore = p->nstore;
   c->mats = p->mats;
   c->have_opal = p->have_opal;
   c->opal = p->opal;

@@ -44,9 +44,11 @@ struct fd_mat {
 
 // One realization on the device (lives in its plan's arena).
 struct fd_desc {
-  int nx, ny, nz, plane;
+  int nx, ny, nz, plane;       // extents; plane = px * ny
+  int px;                      // row pitch: cells from (i, j, k) to (i, j+1, k), nx rounded up to 32
+
   int per[3];                  // periodic axis flags
-  int ncell;
+  int ncell;                   // cells per array (px ny nz), the stride of per-cell planes
   float ch;                    // dt / dx
   int nmat;
   int has_gain;
@@ -179,7 +181,7 @@ hipError_t fd_launch_fill(void* p, size_t bytes, hipStream_t st);
 hipError_t fd_launch_voxelize(const int64_t* sites, int ex, int ey, int ez, const int* per,
                               const int* ncr, const int* origin, const int64_t* reach,
                               int res, int mat_bg, int mat_void, int mat_out,
-                              int nx, int ny, int nz, uint8_t* map, hipStream_t st);
+                              int nx, int ny, int nz, int px, uint8_t* map, hipStream_t st);
 // Density-matrix passes of one step (after the step kernels have left A, the
 // field before the polarization change, on every edge): predictor, corrector
 // (writes rho^{n+1}), edges (E^{n+1} = A - [Q]/eps), then probes and T(t).
@@ -187,7 +189,7 @@ hipError_t fd_launch_dm(const fd_dm_unit* cells, int ncells, const fd_dm_unit* e
                         const fd_dm_unit* diag, int ndiag, int block, int s, hipStream_t st,
                         hipEvent_t* ev = nullptr);
 hipError_t fd_launch_init_pop(const uint8_t* map, const float* n_init_by_mat, const uint32_t* gidx, unsigned gainmask,
-                              float* pop, int ncell, hipStream_t st);
+                              float* pop, int ncell, int nx, int px, hipStream_t st);
 
 // Device address of this GPU's static launch-table array (FD_STATIC_TABLE_BYTES,
 // 256-byte aligned), looked up once per device with that device current.

@@ -104,6 +104,7 @@ struct R32 {
 
 struct Ctx {
   int nx, ny, nz, plane;
+  int rx;  // row pitch of the per-cell arrays
   int px, py, pz;
   float ch;
   R32<const float> Ein[3];
@@ -119,7 +120,7 @@ struct Ctx {
 };
 
 __device__ __forceinline__ void make_ctx(Ctx& x, const cdesc* d, int par, bool pml) {
-  x.nx = d->nx; x.ny = d->ny; x.nz = d->nz; x.plane = d->plane;
+  x.nx = d->nx; x.ny = d->ny; x.nz = d->nz; x.plane = d->plane; x.rx = d->px;
   x.px = d->per[0]; x.py = d->per[1]; x.pz = d->per[2];
   x.ch = d->ch;
 #pragma unroll
@@ -169,7 +170,7 @@ __device__ __forceinline__ int slab(const Ctx& x, int w, int p) {
 
 // psi array offset for axis w, slab index sp, at (i, j, k)
 __device__ __forceinline__ int psi_off(const Ctx& x, int w, int sp, int i, int j, int k) {
-  if (w == 2) return sp * x.plane + j * x.nx + i;
+  if (w == 2) return sp * x.plane + j * x.rx + i;
   if (w == 0) return (k * x.ny + j) * x.t[0] + sp;
   return (k * x.t[1] + sp) * x.nx + i;
 }
@@ -203,7 +204,7 @@ __device__ __forceinline__ float stretch(const Ctx& x, int c, int w, int p, int 
 
 // The same for a z difference when the old psi and the plane's grading
 // (pz = 1/kappa, b, c) have already been loaded: z slabs are whole planes, so
-// the slab index sz of plane k is uniform over a tile.  off2d: j*nx + i of the
+// the slab index sz of plane k is uniform over a tile.  off2d: j*px + i of the
 // cell.  Bit-identical to stretch<HSIDE, PM>(.., 2, k, ..).
 template <bool HSIDE>
 __device__ __forceinline__ float stretch_z(const Ctx& x, int c, const float* pz, int sz, int off2d, float d,
@@ -423,7 +424,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   };
   const int i = i0 + tx, j = j0 + ty;
   const bool act = i < x.nx && j < x.ny;
-  const int c = j * x.nx + i;
+  const int c = j * x.rx + i;
   // the cell's column / row lies on the PEC wall x = 0 / y = 0 (its tangential
   // E components are held at zero there)
   const bool pec_i = !x.px && i == 0, pec_j = !x.py && j == 0;
@@ -432,7 +433,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   int own_off;
   {
     const int gi = wrap(i, x.nx, x.px), gj = wrap(j, x.ny, x.py);
-    own_off = (gi >= 0 && gj >= 0) ? gj * x.nx + gi : -1;
+    own_off = (gi >= 0 && gj >= 0) ? gj * x.rx + gi : -1;
   }
   const int own_slot = (ty + 1) * W + tx + 1;
   // The E staging area has a one-cell ring around the TX x TY tile: ring cell q
@@ -448,7 +449,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
     else { lx = TX + 1; ly = 1 + q - 2 * (TX + 2) - TY; }
     const int gi = wrap(i0 - 1 + lx, x.nx, x.px), gj = wrap(j0 - 1 + ly, x.ny, x.py);
     slot = ly * W + lx;
-    off = (gi >= 0 && gj >= 0) ? gj * x.nx + gi : -1;
+    off = (gi >= 0 && gj >= 0) ? gj * x.rx + gi : -1;
   };
   int r_slot = -1, r_off = -1;
   if (t < nring) ring_cell(t, r_slot, r_off);
@@ -460,7 +461,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   const int hgi = wrap(lh ? i0 - 1 : i0 + hr, x.nx, x.px);
   const int hgj = wrap(lh ? j0 + hr : j0 - 1, x.ny, x.py);
   const bool hact = (lh || bh) && hgi >= 0 && hgj >= 0 && (lh ? (j0 + hr < x.ny) : (i0 + hr < x.nx));
-  const int h_off = hact ? hgj * x.nx + hgi : 0;
+  const int h_off = hact ? hgj * x.rx + hgi : 0;
 
   // ---- sources, probes and flux planes that touch the tile (set on the host);
   // srcmine: the sources that drive this thread's column
@@ -595,8 +596,8 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   {
     const int zm = pro ? km * x.plane : 0;
     const uint32_t om = pro ? zm + c : 0;
-    const uint32_t ojp = (pro && jp >= 0) ? zm + jp * x.nx + i : 0;
-    const uint32_t oip = (pro && ip >= 0) ? zm + j * x.nx + ip : 0;
+    const uint32_t ojp = (pro && jp >= 0) ? zm + jp * x.rx + i : 0;
+    const uint32_t oip = (pro && ip >= 0) ? zm + j * x.rx + ip : 0;
     pEz = x.Ein[2][om];
     pEzj = x.Ein[2][ojp];
     pEzi = x.Ein[2][oip];
@@ -847,7 +848,9 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
         float F[3] = {0.0f, 0.0f, 0.0f};
         if (mt.noise != 0.0f) {
           float gg[3];
-          normals3((uint32_t)n, (uint32_t)o, d->key0, d->key1, gg);
+          // the counter takes the dense cell index (k ny + j) nx + i
+          normals3((uint32_t)n, ((uint32_t)k * (uint32_t)x.ny + (uint32_t)j) * (uint32_t)x.nx + (uint32_t)i,
+                   d->key0, d->key1, gg);
           const float amp = mt.noise * sqrtf(fmaxf(n2, 0.0f));
 #pragma unroll
           for (int q = 0; q < 3; ++q) F[q] = amp * gg[q];
@@ -1276,7 +1279,7 @@ __device__ __forceinline__ long long floordiv_ll(long long a, long long b) {
 
 __global__ void voxelize_kernel(const int64_t* __restrict__ sites, int ex, int ey, int ez, int3 per,
                                 int3 ncr, int3 org, longlong3 reach, int res, int mat_bg, int mat_void,
-                                int mat_out, int nx, int ny, int nz, uint8_t* __restrict__ map) {
+                                int mat_out, int nx, int ny, int nz, int px, uint8_t* __restrict__ map) {
   const long long ncell = (long long)nx * ny * nz;
   const long long stride = (long long)gridDim.x * blockDim.x;
   const long long H16 = 65536;
@@ -1289,8 +1292,9 @@ __global__ void voxelize_kernel(const int64_t* __restrict__ sites, int ex, int e
     bool in_crystal = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) in_crystal = in_crystal && rel[a] >= 0 && rel[a] < nc[a];
+    const long long vo = ((long long)k * ny + j) * px + i;  // padded rows
     if (!in_crystal) {
-      map[v] = (uint8_t)mat_out;
+      map[vo] = (uint8_t)mat_out;
       continue;
     }
     const int pr[3] = {per.x, per.y, per.z};
@@ -1340,16 +1344,18 @@ __global__ void voxelize_kernel(const int64_t* __restrict__ sites, int ex, int e
         }
       }
     }
-    map[v] = (uint8_t)(hit ? mat_void : mat_bg);
+    map[vo] = (uint8_t)(hit ? mat_void : mat_bg);
   }
 }
 
 // Initial upper-level populations of the gain cells at their gain ordinals (the
 // low parts and every other state variable start at zero with the arena).
 __global__ void init_pop_kernel(const uint8_t* __restrict__ map, const float* __restrict__ ninit,
-                                const uint32_t* __restrict__ gidx, unsigned gainmask, float* pop, int ncell) {
+                                const uint32_t* __restrict__ gidx, unsigned gainmask, float* pop, int ncell,
+                                int nx, int px) {
   const int stride = gridDim.x * blockDim.x;
   for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < ncell; o += stride) {
+    if (o % px >= nx) continue;  // row padding
     const int m = map[o];
     if (!((gainmask >> m) & 1u)) continue;
     const uint32_t g = gidx[o];
@@ -1395,9 +1401,9 @@ struct Ijk {
   int i, j, k;
 };
 __device__ __forceinline__ Ijk ijk_of(const cdesc* d, uint32_t o) {
-  const uint32_t plane = (uint32_t)d->plane, nx = (uint32_t)d->nx;
-  const uint32_t k = o / plane, r = o - k * plane, j = r / nx;
-  return {(int)(r - j * nx), (int)j, (int)k};
+  const uint32_t plane = (uint32_t)d->plane, px = (uint32_t)d->px;
+  const uint32_t k = o / plane, r = o - k * plane, j = r / px;
+  return {(int)(r - j * px), (int)j, (int)k};
 }
 
 // Coordinates of cell p's neighbours along each axis at offsets -1, 0, +1
@@ -1432,7 +1438,7 @@ __device__ __forceinline__ int nb_cell(const cdesc* d, const Nbr& b, int c, int 
   const int x = b.c[0][o[0]], y = b.c[1][o[1]], z = b.c[2][o[2]];
   // bitwise, not short-circuit, operators: lane values must not become branches
   *held = ((!d->per[a1]) & (b.c[a1][o[a1]] == 0)) | ((!d->per[a2]) & (b.c[a2][o[a2]] == 0));
-  return ((x | y | z) < 0) ? -1 : (z * d->ny + y) * d->nx + x;
+  return ((x | y | z) < 0) ? -1 : (z * d->ny + y) * d->px + x;
 }
 
 // A gain cell's state (populations as (hi, lo) FP32 pairs, coherences), its
@@ -1467,7 +1473,9 @@ __device__ __forceinline__ void dm_load(const cdesc* d, const DmMats& sm, uint32
   }
   if (mt.noise != 0.0f) {
     float gg[3];
-    normals3((uint32_t)n, z.o, d->key0, d->key1, gg);
+    // the counter takes the dense cell index (k ny + j) nx + i
+    normals3((uint32_t)n, ((uint32_t)z.p.k * (uint32_t)d->ny + (uint32_t)z.p.j) * (uint32_t)d->nx + (uint32_t)z.p.i,
+             d->key0, d->key1, gg);
 #pragma unroll
     for (int q = 0; q < 3; ++q) z.dJ[q] = mt.noise * sqrtf(fmaxf(z.pp[q], 0.0f)) * gg[q];
   }
@@ -1606,7 +1614,9 @@ __global__ __launch_bounds__(FD_DM_EDGES) void dm_edges_kernel(const fd_dm_unit*
   const gf* Q = G((const float*)d->dmq[1]);
   const size_t ncs = (size_t)d->ncell;
   const uint32_t o = (uint32_t)(u.first + t);
-  const Nbr b = neighbours(d, ijk_of(d, o));
+  const Ijk pc = ijk_of(d, o);
+  if (pc.i >= d->nx) return;  // row padding
+  const Nbr b = neighbours(d, pc);
   float acc[3];
   bool held[3];
   bool any = false;
@@ -1660,7 +1670,7 @@ __global__ __launch_bounds__(FD_MAXBLOCK) void dm_diag_kernel(const fd_dm_unit* 
   double v = 0.0;
   if (i < d->nx && j < d->ny) {
     const int kf = d->flux_k[f], km = kf > 0 ? kf - 1 : d->nz - 1;
-    const size_t off = (size_t)j * d->nx + i;
+    const size_t off = (size_t)j * d->px + i;
     const size_t o = (size_t)kf * d->plane + off, om = (size_t)km * d->plane + off;
     const float sx = 0.5f * (G((const float*)d->E[par][0])[o] + G((const float*)d->E[par ^ 1][0])[o]);
     const float sy = 0.5f * (G((const float*)d->E[par][1])[o] + G((const float*)d->E[par ^ 1][1])[o]);
@@ -1778,22 +1788,23 @@ hipError_t fd_launch_fill(void* p, size_t bytes, hipStream_t st) {
 
 hipError_t fd_launch_voxelize(const int64_t* sites, int ex, int ey, int ez, const int* per, const int* ncr,
                               const int* origin, const int64_t* reach, int res, int mat_bg,
-                              int mat_void, int mat_out, int nx, int ny, int nz, uint8_t* map, hipStream_t st) {
+                              int mat_void, int mat_out, int nx, int ny, int nz, int px, uint8_t* map,
+                              hipStream_t st) {
   const long long ncell = (long long)nx * ny * nz;
   long long blocks = (ncell + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   voxelize_kernel<<<(unsigned)blocks, 256, 0, st>>>(
       sites, ex, ey, ez, make_int3(per[0], per[1], per[2]), make_int3(ncr[0], ncr[1], ncr[2]),
       make_int3(origin[0], origin[1], origin[2]), make_longlong3(reach[0], reach[1], reach[2]), res, mat_bg,
-      mat_void, mat_out, nx, ny, nz, map);
+      mat_void, mat_out, nx, ny, nz, px, map);
   return hipGetLastError();
 }
 
 hipError_t fd_launch_init_pop(const uint8_t* map, const float* n_init_by_mat, const uint32_t* gidx, unsigned gainmask,
-                              float* pop, int ncell, hipStream_t st) {
+                              float* pop, int ncell, int nx, int px, hipStream_t st) {
   int blocks = (ncell + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  init_pop_kernel<<<blocks, 256, 0, st>>>(map, n_init_by_mat, gidx, gainmask, pop, ncell);
+  init_pop_kernel<<<blocks, 256, 0, st>>>(map, n_init_by_mat, gidx, gainmask, pop, ncell, nx, px);
   return hipGetLastError();
 }
 

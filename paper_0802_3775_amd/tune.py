@@ -15,7 +15,7 @@ import json
 import os
 import time
 
-CACHE_VERSION = 6
+CACHE_VERSION = 7
 
 
 def _cache_path():
@@ -38,10 +38,12 @@ def shape_key(cfg):
 
 def candidates(cfg, quick=False):
     nx, ny, nz = cfg["grid"]["n"]
-    tiles = [(16, 256), (32, 256), (64, 256), (16, 128), (32, 128)]
+    # the usual winners first (the search stops at its time budget): wide tiles
+    # and the chunk lengths that won on grids of 1-42 M cells
+    tiles = [(64, 256), (32, 256), (16, 256), (32, 128), (16, 128)]
     if quick:
-        tiles = [(16, 256), (32, 256), (64, 256)]
-    chunks = [1, 2, 4, 8, 16, 32, 48, 64]
+        tiles = [(64, 256), (32, 256), (16, 256)]
+    chunks = [8, 16, 48, 4, 32, 64, 2, 1]
     out = []
     for (tx, b), z in itertools.product(tiles, chunks):
         if tx > 16 and tx > 2 * nx:
@@ -95,8 +97,9 @@ def autotune(cfg, budget_s=20.0, quick=False, use_cache=True, graph_steps=(50, 2
     if key in cache:
         return dict(cache[key]["tuning"])
     ncell = cfg["grid"]["n"][0] * cfg["grid"]["n"][1] * cfg["grid"]["n"][2]
-    # steps per trial: about 2e8 cell-updates, at least 8
-    steps = int(max(8, min(200, 2e8 / max(ncell, 1))))
+    # steps per trial: about 2e8 cell-updates, at least 20 (fewer left the
+    # choice between shapes within a few percent of each other to noise)
+    steps = int(max(20, min(200, 2e8 / max(ncell, 1))))
     t_end = time.perf_counter() + budget_s
     best, best_ms = None, float("inf")
     results = []
@@ -173,7 +176,7 @@ def tune_batch(cfgs, budget_s=20.0, sample=8, use_cache=True, verbose=False):
     a sample of members spread over the size range is stepped as a Batch for
     every candidate tile shape (members share tile_x and block, and a tile wider
     than a member's grid wastes lanes, so the largest member's own best is not
-    the batch's), then for each class grouping and graph length."""
+    the batch's), then for member-group sizes and class groupings."""
     members = sorted(cfgs, key=_cells)
     if len(members) > sample:
         idx = [round(q * (len(members) - 1) / (sample - 1)) for q in range(sample)]
@@ -184,37 +187,32 @@ def tune_batch(cfgs, budget_s=20.0, sample=8, use_cache=True, verbose=False):
         return dict(cache[key]["tuning"])
     total = sum(_cells(c) for c in members)
     steps = int(max(8, min(100, 2e8 / max(total, 1))))
-    t_end = time.perf_counter() + budget_s
+    t0 = time.perf_counter()
     best, best_ms = None, float("inf")
+
+    def trial(tune):
+        nonlocal best, best_ms
+        ms = _time_batch(members, tune, steps, 4)
+        if verbose:
+            print("batch tune %s: %.2f us/step" % (tune, ms * 1e3), flush=True)
+        if ms < best_ms:
+            best, best_ms = tune, ms
+
+    # tile shapes within 60% of the budget, then member groups that fit the
+    # 256 MB Infinity Cache (the sample's state already exceeds it; above it a
+    # group streams from HBM) whatever the time, then the class grouping
     for cand in candidates(members[-1]):
-        if time.perf_counter() > t_end and best is not None:
+        if time.perf_counter() - t0 > 0.6 * budget_s and best is not None:
             break
-        tune = dict(cand, graph_steps=50)
-        ms = _time_batch(members, tune, steps, 4)
-        if verbose:
-            print("batch tune %s: %.2f us/step" % (tune, ms * 1e3), flush=True)
-        if ms < best_ms:
-            best, best_ms = tune, ms
-    for merge, par in ((0, 0), (2, 0)):
-        if time.perf_counter() > t_end:
-            break
-        tune = dict(best, merge=merge, parallel=par)
-        ms = _time_batch(members, tune, steps, 4)
-        if verbose:
-            print("batch tune %s: %.2f us/step" % (tune, ms * 1e3), flush=True)
-        if ms < best_ms:
-            best, best_ms = tune, ms
-    # member groups that fit the 256 MB Infinity Cache (timed on the sample,
-    # whose state already exceeds the cache); above it a group streams from HBM
+        trial(dict(cand, graph_steps=50))
+    base = dict(best)
     for mb in (192, 224, 256):
-        if time.perf_counter() > t_end:
+        trial(dict(base, cache_mb=mb))
+    base = dict(best)
+    for merge, par in ((0, 0), (2, 0)):
+        if time.perf_counter() - t0 > budget_s:
             break
-        tune = dict(best, cache_mb=mb)
-        ms = _time_batch(members, tune, steps, 4)
-        if verbose:
-            print("batch tune %s: %.2f us/step" % (tune, ms * 1e3), flush=True)
-        if ms < best_ms:
-            best, best_ms = tune, ms
+        trial(dict(base, merge=merge, parallel=par))
     if use_cache:
         cache = _load_cache()
         cache[key] = {"tuning": best, "us_per_step": best_ms * 1e3}

@@ -146,12 +146,16 @@ def test_density_slab_zcpml_class():
     plan.close()
 
 
-def test_density_batch_matches_plain_runs():
+@pytest.mark.parametrize("cache_mb", [0, 1])
+def test_density_batch_matches_plain_runs(cache_mb):
+    """Two density-matrix lasing boxes stepped as a batch (cache_mb 1: each in a
+    member group of its own, stepped through the call before the other) equal
+    the same plans stepped alone, bit for bit."""
     import torch
     from paper_0802_3775_amd import fdtd as F
     cfgs = [W.lasing(model="density", res=8, cells=(2, 2, 2), pml=4, steps=200, noise=1e-3, seed=s)
             for s in (1, 2)]
-    tune = {"block": 128, "zchunk": 8, "graph_steps": 0}
+    tune = {"block": 128, "zchunk": 8, "graph_steps": 0, "cache_mb": cache_mb}
     alone = []
     for c in cfgs:
         p = F.Plan(c, max_steps=200, tuning=tune)
