@@ -275,7 +275,7 @@ def measure_cpu(workload, budget_s):
             "sample": "steps 3..%d of %s, FP64 oracle, %.1f s of stepping" % (n + 2, what, dt)}
 
 
-def measure_batched(args, steps=300, kernel_steps=30):
+def measure_batched(args, kernel_steps=30):
     """The batched ensemble (64 uneven realizations) against the same
     realizations stepped one after another, each alone; the batch's dominant
     kernel class is timed per launch (hipEvents bound to the launches) against
@@ -283,6 +283,7 @@ def measure_batched(args, steps=300, kernel_steps=30):
     import torch
     from paper_0802_3775_amd import fdtd, tune
     from paper_0802_3775_amd import workloads as W
+    steps = args.batch_steps
     cfgs = W.ensemble(count=64, steps=10000)
     if args.batch_tuning:
         v = [int(q) for q in args.batch_tuning.split(",")]
@@ -307,11 +308,14 @@ def measure_batched(args, steps=300, kernel_steps=30):
     b = fdtd.Batch(plans)
     b.step(100)
     torch.cuda.synchronize()
+    log("batched: warm")
     t0 = time.perf_counter()
     b.step(steps)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    log("batched: %d steps in %.3f s" % (steps, tb))
     ms, cnt = b.time_kernels(kernel_steps)
+    log("batched: kernel table")
     nbytes, ncells = b.class_bytes(), b.class_cells()
     kern = {}
     for c, name in enumerate(fdtd.Plan.CLASSES):
@@ -406,6 +410,7 @@ def main():
     ap.add_argument("--tuning", default="", help="fixed tile_x,block,zchunk,graph_steps[,merge,parallel] (skip the autotuner)")
     ap.add_argument("--batch-tuning", default="",
                     help="fixed batch tuning tile_x,block,zchunk,graph_steps,merge,parallel,cache_mb (profiling)")
+    ap.add_argument("--batch-steps", type=int, default=300, help="batched: timed steps")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batched: skip the members-one-after-another baseline (profiling)")
     ap.add_argument("--skip-plain", action="store_true",

@@ -134,10 +134,10 @@ struct fdtd_plan {
   fdtd_grid_desc g{};
   double dx = 0, dt = 0;
   int64_t ncell = 0;   // cells of the grid
-  // Device layout: rows of px >= nx cells (nx rounded up to 32 cells, 128 bytes,
-  // so that every row of every per-cell array starts on a cache line), nstore =
-  // px ny nz cells per array; the padding cells are never written.  Host-side
-  // arrays (material map, fields read and written) are dense.
+  // Device layout: rows of px >= nx cells (row_pitch: nx rounded up to 32
+  // cells, 128 bytes, where that pads by at most an eighth), nstore = px ny nz
+  // cells per array; the padding cells are never written.  Host-side arrays
+  // (material map, fields read and written) are dense.
   int px = 0;
   int64_t nstore = 0;
   std::vector<fdtd_material> mats;
@@ -371,11 +371,17 @@ double source_sigma_t(const fdtd_source_desc& s) {
 }
 
 int axis_n(const fdtd_plan* p, int w) { return w == 0 ? p->g.nx : (w == 1 ? p->g.ny : p->g.nz); }
-// Row pitch of the device arrays: x extents above 32 cells are padded to a
-// multiple of 32 (128-byte rows).  With unpadded rows of, say, 200 cells a
-// 32-wide tile row straddles two cache lines in three rows of four; padded, the
-// all-axes CPML kernel on a 200^3 box measured 106 -> 77 us.
-int row_pitch(int nx) { return nx <= 32 ? nx : (nx + 31) / 32 * 32; }
+// Row pitch of the device arrays.  Rows padded to a multiple of 32 cells (128
+// bytes) start every tile row on a cache line: unpadded rows of 200 cells
+// straddle lines in three rows of four, and padding took the step of the
+// paper's 200^3 boxes from 162 to 154 us (beam) and 172 to 148 us (lasing).
+// But the padding's partial line at the end of every row is moved too, so a
+// row is padded only when that costs at most an eighth of it: the 80-cell rows
+// of the transmission slab padded to 96 moved 11% more bytes and ran 8% slower.
+int row_pitch(int nx) {
+  const int p = (nx + 31) / 32 * 32;
+  return (nx > 32 && 8 * (p - nx) <= p) ? p : nx;
+}
 // Device (padded) index of host (dense) cell o.
 size_t pitched(const fdtd_plan* p, size_t o) { return (o / (size_t)p->g.nx) * (size_t)p->px + o % (size_t)p->g.nx; }
 // Copies between a dense host array of ncell elements of elem bytes and the

@@ -45,7 +45,7 @@ struct fd_mat {
 // One realization on the device (lives in its plan's arena).
 struct fd_desc {
   int nx, ny, nz, plane;       // extents; plane = px * ny
-  int px;                      // row pitch: cells from (i, j, k) to (i, j+1, k), nx rounded up to 32
+  int px;                      // row pitch: cells from (i, j, k) to (i, j+1, k) (nx, or nx padded to 32)
 
   int per[3];                  // periodic axis flags
   int ncell;                   // cells per array (px ny nz), the stride of per-cell planes

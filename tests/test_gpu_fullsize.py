@@ -123,8 +123,15 @@ def test_slab_full_size_full_length_with_transmission():
     Se = empty.flux(0)[1]
     assert rel_l2(empty.flux(0)[0], efx["T0"]) <= 1e-3
     assert rel_l2(Se, efx["S0"]) <= 1e-3
-    tr_g, tr_o = spec[0] / Se, fx["S0"] / efx["S0"]
-    _say("transmission", rel_l2(tr_g, tr_o))
+    # the transmission ratio over the pulse's band: the bins where the empty
+    # run's spectrum is at least 1e-6 of its peak (outside it the 30 fs pulse
+    # carries 1e-14 of its peak power, the rounding floor of either run, while
+    # the slab's still-ringing field leaks power there, so the ratio would be
+    # leakage over rounding noise)
+    band = efx["S0"] >= 1e-6 * efx["S0"].max()
+    tr_g, tr_o = spec[0][band] / Se[band], fx["S0"][band] / efx["S0"][band]
+    _say("transmission over %d bins" % band.sum(), rel_l2(tr_g, tr_o))
+    assert band.sum() >= 20
     assert rel_l2(tr_g, tr_o) <= 1e-3
     empty.close()
 
