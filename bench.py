@@ -185,6 +185,11 @@ def _roofline(kern, kname, workload, copy_gbs=None):
     out = {"bound": "hbm", "kernel": kname, "achieved": k["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": k["GBps"] / HBM_PEAK_GBS, "avg_launch_ms": k["avg_ms"], "alg_bytes_per_launch": k["alg_bytes"],
            "traffic": recorded_traffic(workload, kname)}
+    if out["traffic"]:
+        # the counted HBM bytes of a launch over the same live duration: the
+        # rocprofv3-counted rate beside the algorithmic one
+        out["hbm_GBps"] = out["traffic"] / (k["avg_ms"] * 1e-3) / 1e9
+        out["hbm_frac"] = out["hbm_GBps"] / HBM_PEAK_GBS
     if copy_gbs:
         out["copy_GBps"] = copy_gbs
         out["frac_of_copy"] = k["GBps"] / copy_gbs
