@@ -226,9 +226,13 @@ def test_slab_full_size_random_fields():
     ((17, 13, 11), (0, 1, 0), (3, 0, 2)),
     ((23, 19, 21), (0, 0, 0), (4, 5, 3)),
     ((33, 30, 5), (1, 0, 1), (0, 6, 0)),
+    ((60, 9, 13), (1, 0, 0), (0, 3, 2)),
+    ((58, 7, 9), (0, 0, 0), (4, 2, 0)),
 ])
 def test_edge_shapes_random_fields(shape, periodic, pml):
-    """Ragged blocks, one-cell axes, PEC boxes, CPML on each axis, random materials."""
+    """Ragged blocks, one-cell axes, PEC boxes, CPML on each axis, random materials;
+    the last two have device rows padded (60 and 58 cells to 64: periodic x
+    wrapping at nx inside padded rows, and x-CPML slabs beside the padding)."""
     steps = 60
     cfg = W.homogeneous_box(n=shape, periodic=periodic, res=10, pml=pml, steps=steps,
                             materials=[{"eps": 1.0}, {"eps": 3.0}, {"eps": 11.9}])
