@@ -253,7 +253,9 @@ int64_t fdtd_cell_count(const fdtd_plan* p);
 double fdtd_dt(const fdtd_plan* p);
 
 /* Field component comp (0..5) of the current step, nx*ny*nz floats in host
-   memory (caller-owned); write sets initial conditions.  Synchronize. */
+   memory (caller-owned, dense [nz][ny][nx]; on the device rows may be padded
+   for alignment, which the copies undo); write sets initial conditions.
+   Synchronize. */
 int fdtd_read_field(fdtd_plan* p, int32_t comp, float* host, void* stream);
 int fdtd_write_field(fdtd_plan* p, int32_t comp, const float* host, void* stream);
 /* Probe samples 0..n-1 (n = steps taken) into host floats (max_steps room). */
