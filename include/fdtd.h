@@ -8,8 +8,8 @@
  *   - Disorder r = r0 (1 + gamma xi), xi uniform in [-1/2, 1/2]: same section.
  *   - Pumped gain medium in the spheres with a stochastic spontaneous-emission
  *     source: same section and the lasing section ("3+1D simulation of lasing").
- *   - Transmitted power T(t), the transversely integrated Poynting vector at the
- *     output face: section "Dynamical diffusion and localization".
+ *   - Transmitted power T(t), the Poynting flux through the output plane summed
+ *     over that plane: section "Dynamical diffusion and localization".
  * Gain media: a Lorentz polarization driven by four-level rate equations, or
  * the paper's density-matrix (su(4)) model of a ground level coupled to three
  * degenerate upper levels (fdtd_material, gain = 2).
@@ -217,7 +217,7 @@ int fdtd_add_source(fdtd_plan* p, const fdtd_source_desc* s, int32_t* id);
    at (i,j,k), recorded after every step (E^{n+1}, H^{n+1/2}). */
 int fdtd_add_probe(fdtd_plan* p, int32_t comp, int32_t i, int32_t j, int32_t k, int32_t* id);
 /* Flux plane ("Dynamical diffusion and localization": the transmitted power
-   T(t), the transversely integrated Poynting vector at the output face) normal
+   T(t): the Poynting flux through the output plane, summed over it) normal
    to axis (only 2, z, the launch direction; 0 and 1 give FDTD_EUNSUPPORTED) at
    index k: T(t_{n+1/2}) = sum over the plane of the time-centred S_z dx^2 every
    step, and the running DFT of Ex, Ey (time n) and the z-averaged Hx, Hy (time

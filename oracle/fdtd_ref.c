@@ -27,11 +27,11 @@
  * edge's own voxel, and J the spontaneous-emission noise current
  * sigma_N sqrt(rho_cc) g_c / sqrt(dt dx^3) at the centre.
  *   6. diagnostics: probes E^{n+1}; transmitted power T at the flux plane
- *      (paper, section "Dynamical diffusion and localization": transversely
- *      integrated Poynting vector); running DFT of the plane fields; energy.
- * Every reading of a point the paper leaves open (the gain model, coupling
- * constant, noise form, absorber parameters, source shapes) is listed in
- * the design doc.
+ *      (paper, section "Dynamical diffusion and localization": the Poynting
+ *      flux summed over the plane); running DFT of the plane fields; energy.
+ * Where the paper leaves a point open (the gain model, coupling constant,
+ * noise form, absorber parameters, source shapes) the choice made is the one
+ * stated at the function that implements it.
  */
 #include <math.h>
 #include <stdint.h>

@@ -15,12 +15,11 @@
  *     disorder r = r0 (1 + gamma xi), xi uniform in [-1/2, 1/2]: same section.
  *   - Gain medium pumped externally, spontaneous emission as a stochastic
  *     source: same section and the lasing section.
- *   - Transmitted power T(t) = transversely integrated Poynting vector at the
- *     output face: section "Dynamical diffusion and localization".
+ *   - Transmitted power T(t): the Poynting flux through the output plane,
+ *     summed over that plane; section "Dynamical diffusion and localization".
  * Two gain models: a Lorentz polarization driven by four-level population
  * rate equations (gain = 1), and the paper's density-matrix model of a ground
- * level coupled to three degenerate upper levels (gain = 2, bloch_ref.h);
- * every reading of a point the paper leaves open is listed in the design doc.
+ * level coupled to three degenerate upper levels (gain = 2, bloch_ref.h).
  *
  * Units: c = eps0 = mu0 = 1; lengths in a, time in a/c, frequency in c/a.
  * Grid pitch dx = 1/res, time step dt = courant * dx.  Arrays are [nz][ny][nx],

@@ -1,7 +1,7 @@
 """Pins of the oracle's sources, absorbing boundary and flux diagnostics (CPU only).
 
 Paper: pulsed plane-wave excitation and the transmitted power T(t), the
-transversely integrated Poynting vector at the output face (section
+Poynting flux through the output plane summed over that plane (section
 "Dynamical diffusion and localization"); absorbing walls around the box
 (section "Sample and numerical approach").  A 1x1xN periodic column is an
 exact 1-D Yee line (x and y differences vanish), which gives closed forms.
