@@ -12,8 +12,8 @@
  *   5. four-level populations by Crank-Nicolson with the stimulated transfer
  *        u = sum_c (E_c^n + E_c^{n+1})/2 (P_c^{n+1} - P_c^n)/dt   (-u from n1, +u to n2).
  * Density-matrix gain cells (bloch_ref.h) hold their density matrix at the
- * cell centre (the paper solves the density-matrix equations in the middle of
- * the Yee cell) and replace 2-5 by: A = E^n + dt/(eps dx) (curl H - dx J) on
+ * cell centre (where the paper places the density-matrix solution, section
+ * "Sample and numerical approach") and replace 2-5 by: A = E^n + dt/(eps dx) (curl H - dx J) on
  * every edge; at each gain-cell centre the average <.> of the four edges of
  * each component; and one predictor-corrector pass of the implicit midpoint
  * coupling,

@@ -225,8 +225,8 @@ def _rotation_box(N=12, M=6, src=None, steps=0):
 
 
 def test_density_matrix_sits_at_the_cell_centre_rotation_isotropy():
-    """The density-matrix equations are solved in the middle of the Yee cell
-    (section "Sample and numerical approach"): a gain cell couples to the
+    """The density matrix lives at the cell centre (the placement of section
+    "Sample and numerical approach"): a gain cell couples to the
     average of the four edges of each field component around its centre and
     hands its polarization change back to them.  Turning the whole setup by 90
     degrees about z through a gain cell's centre, (x, y) -> (2c+1-y, x), maps
