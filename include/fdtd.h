@@ -334,7 +334,8 @@ int fdtd_tune(const fdtd_plan* p, const fdtd_tuning* cand, int32_t ncand, int64_
    gain cells; 6 the running-DFT update; 7-10 the passes of the density-matrix
    medium (predictor, corrector, edges, diagnostics).  cells[c] = cells covered
    by the plan's tiles of class c (c < 6), flux-plane points (6), gain cells (7,
-   8), cells of the edge pass (9), flux-plane points and probes (10). */
+   8), cells whose edges a gain cell shares (9), flux-plane points and probes
+   (10). */
 #define FDTD_NKERNEL 11
 int fdtd_class_cells(const fdtd_plan* p, int64_t* cells /* FDTD_NKERNEL */);
 /* Algorithmic bytes one launch of each kernel moves (FDTD_NKERNEL entries):
@@ -347,8 +348,8 @@ int fdtd_class_cells(const fdtd_plan* p, int64_t* cells /* FDTD_NKERNEL */);
    accumulators read + written per plane point and frequency plus the sample
    ring read; per density-matrix gain cell 113 (predictor: 18 state floats, the
    cell's share of E^n and A, map and list, Q*) and 197 (corrector: the state
-   read and written, fields, neighbours' Q*, Q), 12 per cell of the edge range
-   (Q) + 25 per cell whose edges touch gain (A in, E out, map), 32 per
+   read and written, fields, neighbours' Q*, Q), 41 per cell whose edges a gain
+   cell shares (its list entry, the sharers' Q, A in, E out, map), 32 per
    flux-plane point + 8 per probe for the diagnostics. */
 int fdtd_class_bytes(const fdtd_plan* p, double* bytes /* FDTD_NKERNEL */);
 /* Advance n steps without graphs, launching every kernel with a pair of hipEvents

@@ -72,7 +72,7 @@ struct Layout {
   size_t tiles[FD_NCLASS];
   size_t dft;
   size_t sites;
-  size_t glist, dmq[2], dmunits;  // density-matrix plans: gain-cell list, Q buffers, pass work units
+  size_t glist, elist, dmq[2], dmunits;  // density-matrix plans: gain-cell list, Q buffers, pass work units
 };
 
 struct GraphEntry {
@@ -481,6 +481,7 @@ int compute_layout(fdtd_plan* p, int64_t max_steps, Layout& L) {
   L.pop = gm ? take(nc * 4 * (gm == 2 ? 18 : 6)) : 0;
   L.gidx = gm ? take(nc * 4) : 0;
   L.glist = gm == 2 ? take(nc * 4) : 0;
+  L.elist = gm == 2 ? take(nc * 4) : 0;
   for (int q = 0; q < 2; ++q) L.dmq[q] = gm == 2 ? take(nc * 4 * 3) : 0;
   for (int w = 0; w < 3; ++w) {
     const bool on = pml_t(p, w) > 0;
@@ -582,11 +583,10 @@ int build_dm_units(fdtd_plan* p) {
         }
     const bool perz = p->g.bc[2] == FDTD_BC_PERIODIC;
     const int k0 = perz ? 0 : kmin, k1 = perz ? nz : std::min(nz, kmax + 2);
-    const int64_t first = (int64_t)k0 * plane, last = (int64_t)k1 * plane;
-    for (int64_t o = first; o < last; o += FD_DM_EDGES)
-      p->dmu[1].push_back({p->ddesc, (int)o, (int)std::min<int64_t>(FD_DM_EDGES, last - o), 0});
-    // cells of the edge range whose own edges have a gain cell among their sharers
-    int64_t touched = 0;
+    // the edge list: cells whose own edges have a gain cell among their sharers
+    // (the planes from the lowest gain plane to one past the highest), in cell
+    // order, by their padded index
+    std::vector<uint32_t> elist;
     const int nx = p->g.nx, ny = p->g.ny;
     auto gain_at = [&](int i, int j, int k) {
       const int n3[3] = {nx, ny, nz};
@@ -605,17 +605,21 @@ int build_dm_units(fdtd_plan* p) {
           for (int u = 0; u < 2 && !any; ++u)
             for (int v = 0; v < 2 && !any; ++v)
               any = gain_at(i, j - u, k - v) || gain_at(i - v, j, k - u) || gain_at(i - u, j - v, k);
-          touched += any ? 1 : 0;
+          if (any) elist.push_back((uint32_t)((size_t)k * plane + (size_t)j * p->px + i));
         }
+    const int ne = (int)elist.size();
+    if (ne)
+      HIPCHK(hipMemcpy(p->arena + p->L.elist, elist.data(), sizeof(uint32_t) * elist.size(), hipMemcpyHostToDevice));
+    for (int e0 = 0; e0 < ne; e0 += FD_DM_EDGES) p->dmu[1].push_back({p->ddesc, e0, std::min(FD_DM_EDGES, ne - e0), 0});
     p->dm_cells[0] = p->dm_cells[1] = ng;
-    p->dm_cells[2] = (int64_t)(k1 - k0) * hplane;  // the range's cells (its padding is skipped)
+    p->dm_cells[2] = ne;
     // predictor: state 72 + E^n and A of the cell's edges 24 + map and list 5
     // + Q* 12; corrector: state 72 + 72, fields 24, neighbours' Q* 12, Q 12,
-    // map and list 5; edges: Q of the range 12, and for a cell whose edges touch
-    // gain A in and E out 24 + its map 1
+    // map and list 5; edges, per listed cell: its entry 4, the sharers' Q 12,
+    // A in and E out 24, its map 1
     p->dm_bytes[0] = 113.0 * ng;
     p->dm_bytes[1] = 197.0 * ng;
-    p->dm_bytes[2] = 12.0 * (double)p->dm_cells[2] + 25.0 * (double)touched;
+    p->dm_bytes[2] = 41.0 * (double)ne;
   }
   for (int f = 0; f < (int)p->flux.size(); ++f)
     for (int b = 0; b < p->nblk; ++b) p->dmu[2].push_back({p->ddesc, f, b, 0});
@@ -1017,6 +1021,7 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
   d.pop = p->has_gain ? at<float>(p, L.pop) : nullptr;
   d.gidx = p->has_gain ? at<uint32_t>(p, L.gidx) : nullptr;
   d.glist = p->gm == 2 ? at<uint32_t>(p, L.glist) : nullptr;
+  d.elist = p->gm == 2 ? at<uint32_t>(p, L.elist) : nullptr;
   for (int q = 0; q < 2; ++q) d.dmq[q] = p->gm == 2 ? at<float>(p, L.dmq[q]) : nullptr;
   d.tile_x = p->tune.tile_x;
   d.key0 = p->g.seed;

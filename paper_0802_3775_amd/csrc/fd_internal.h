@@ -75,6 +75,7 @@ struct fd_desc {
   // corrector (dmq[1]), 3 planes each, both including the noise current's dt J
   // (cells without gain keep the arena's zeros)
   const uint32_t* glist;
+  const uint32_t* elist;  // the (padded) cells with an edge that a gain cell shares, in cell order
   float* dmq[2];
   int ngain;
   int tile_x;  // xy tile width of the plan's step tiles (the T(t) partial slots)
@@ -134,9 +135,9 @@ struct fd_dft_tile {
   int pad;
 };
 
-// Work unit of the density-matrix passes: cells [first, first + count) of one
-// plan (gain ordinals for the cell passes, flattened cell indices for the edge
-// pass); for the diagnostics pass first = flux plane (-1: probes), count = xy tile.
+// Work unit of the density-matrix passes: entries [first, first + count) of one
+// plan's gain ordinals (cell passes) or of its edge list elist (edge pass); for
+// the diagnostics pass first = flux plane (-1: probes), count = xy tile.
 struct fd_dm_unit {
   const fd_desc* d;
   int first, count;

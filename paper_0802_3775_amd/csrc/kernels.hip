@@ -1598,10 +1598,10 @@ __global__ __launch_bounds__(FD_DM_CELLS) void dm_correct_kernel(const fd_dm_uni
   }
 }
 
-// E^{n+1} = A - [Q]/eps on the edges next to gain cells, one cell per thread:
-// the twelve Q values first (cells without gain hold Q = 0, so an edge with no
-// gain neighbour keeps A and is not written), then, for a cell with a changed
-// edge, its A and the new E.
+// E^{n+1} = A - [Q]/eps on the edges next to gain cells, one listed cell per
+// thread (the cells whose edges a gain cell shares): the twelve Q values first
+// (cells without gain hold Q = 0), then, for a cell with a changed edge, its A
+// and the new E.
 __global__ __launch_bounds__(FD_DM_EDGES) void dm_edges_kernel(const fd_dm_unit* __restrict__ units, int s) {
   __shared__ DmMats sm;
   const fd_dm_unit u = units[blockIdx.x];
@@ -1613,10 +1613,8 @@ __global__ __launch_bounds__(FD_DM_EDGES) void dm_edges_kernel(const fd_dm_unit*
   const int par = (int)(n & 1);
   const gf* Q = G((const float*)d->dmq[1]);
   const size_t ncs = (size_t)d->ncell;
-  const uint32_t o = (uint32_t)(u.first + t);
-  const Ijk pc = ijk_of(d, o);
-  if (pc.i >= d->nx) return;  // row padding
-  const Nbr b = neighbours(d, pc);
+  const uint32_t o = ((const __attribute__((address_space(1))) uint32_t*)d->elist)[u.first + t];
+  const Nbr b = neighbours(d, ijk_of(d, o));
   float acc[3];
   bool held[3];
   bool any = false;
