@@ -60,6 +60,7 @@ RUNS = {
     "slab_empty_full": (lambda: W.slab(delta=0.05, seed=13, steps=20000, nf=100, decim=8, empty=True),
                         (20000,)),
     "slab_d00_4k": (lambda: W.slab(delta=0.0, seed=11, steps=4000, nf=100, decim=8), (4000,)),
+    "slab_d02_4k": (lambda: W.slab(delta=0.02, seed=12, steps=4000, nf=100, decim=8), (4000,)),
     "slab_d10_4k": (lambda: W.slab(delta=0.10, seed=14, steps=4000, nf=100, decim=8), (4000,)),
     # the Maxwell-Bloch lasing box (Lorentz medium), pump 1e10 s^-1, seeded noise
     "lasing168_p1e10": (lambda: W.lasing(pump=1e10, steps=2000, energy_interval=100), (500, 1000, 2000)),

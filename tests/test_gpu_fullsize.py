@@ -136,7 +136,7 @@ def test_slab_full_size_full_length_with_transmission():
     empty.close()
 
 
-@pytest.mark.parametrize("name", ["slab_d00_4k", "slab_d10_4k"])
+@pytest.mark.parametrize("name", ["slab_d00_4k", "slab_d02_4k", "slab_d10_4k"])
 def test_slab_full_size_other_disorder_strengths(name):
     plan, fx = _run_checkpoints(name, 1e-4)
     for f in range(2):
