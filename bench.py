@@ -100,10 +100,18 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(workload, kernel):
+def launch_shape(tuning):
+    """The launch parameters a kernel's memory traffic depends on (tile, z-chunk,
+    class grouping, member-group size)."""
+    t = tuning or {}
+    return {k: int(t.get(k, 0)) for k in ("tile_x", "block", "zchunk", "merge", "cache_mb")}
+
+
+def recorded_traffic(workload, kernel, tuning):
     """HBM bytes per launch from the committed rocprofv3 counter runs (FETCH_SIZE,
     WRITE_SIZE, each scaled by the same counter's reading for a copy of known
-    size), or None if the kernel source changed since they were taken."""
+    size), or None if the kernel source changed since they were taken or they
+    were taken in another launch shape than this run's."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
@@ -111,6 +119,8 @@ def recorded_traffic(workload, kernel):
     except (OSError, ValueError):
         return None
     if not rec or rec.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    if rec.get("launch") != launch_shape(tuning):
         return None
     return rec["hbm_bytes_per_launch"]
 
@@ -180,11 +190,11 @@ def timed_run(plan, steps):
     return time.perf_counter() - t0
 
 
-def _roofline(kern, kname, workload, copy_gbs=None):
+def _roofline(kern, kname, workload, tuning, copy_gbs=None):
     k = kern[kname]
     out = {"bound": "hbm", "kernel": kname, "achieved": k["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": k["GBps"] / HBM_PEAK_GBS, "avg_launch_ms": k["avg_ms"], "alg_bytes_per_launch": k["alg_bytes"],
-           "traffic": recorded_traffic(workload, kname)}
+           "traffic": recorded_traffic(workload, kname, tuning)}
     if out["traffic"]:
         # the counted HBM bytes of a launch over the same live duration: the
         # rocprofv3-counted rate beside the algorithmic one
@@ -238,7 +248,7 @@ def measure_side(args, workload, steps, warm, kernel_steps, copy_gbs):
     plan.close()
     return {"workload": WORKLOADS[workload], "cells": n, "steps_timed": steps, "cell_updates_per_s": n * steps / wall,
             "ms_per_step": 1e3 * wall / steps, "tuning": tuning,
-            "roofline": _roofline(kern, _dominant(kern), workload, copy_gbs), "kernels": kern}
+            "roofline": _roofline(kern, _dominant(kern), workload, tuning, copy_gbs), "kernels": kern}
 
 
 def measure_lasing_density(args, steps=1000):
@@ -253,7 +263,7 @@ def measure_lasing_density(args, steps=1000):
     plan.close()
     return {"workload": WORKLOADS["lasing_density"], "cells": n, "steps_timed": steps,
             "cell_updates_per_s": n * steps / wall, "ms_per_step": 1e3 * wall / steps, "tuning": tuning,
-            "roofline": _roofline(kern, _dominant(kern), "lasing_density"), "kernels": kern}
+            "roofline": _roofline(kern, _dominant(kern), "lasing_density", tuning), "kernels": kern}
 
 
 def measure_cpu(workload, budget_s):
@@ -343,7 +353,7 @@ def measure_batched(args, kernel_steps=30):
             "realizations_per_hour": 3600.0 * len(cfgs) / (tb * scale),
             "sequential_realizations_per_hour": 3600.0 * len(cfgs) / (seq * scale) if seq else None,
             "speedup_vs_sequential": seq / tb if seq else None,
-            "roofline": _roofline(kern, _dominant(kern), "batched"),
+            "roofline": _roofline(kern, _dominant(kern), "batched", tuning),
             "step_alg_GBps": step_bytes / (tb / steps) / 1e9,
             "step_frac": step_bytes / (tb / steps) / 1e9 / HBM_PEAK_GBS,
             "kernels": kern,
@@ -482,7 +492,7 @@ def headline(args, copy_gbs):
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload],
                    "cells": plain["ncell"], "tuning": plain["tuning"]},
-        "roofline": _roofline(plain["kernels"], plain["dominant"], args.workload, copy_gbs),
+        "roofline": _roofline(plain["kernels"], plain["dominant"], args.workload, plain["tuning"], copy_gbs),
         "kernels": plain["kernels"],
     }
     if not args.no_cpu:

@@ -15,7 +15,7 @@ import json
 import os
 import time
 
-CACHE_VERSION = 7
+CACHE_VERSION = 8
 
 
 def _cache_path():
@@ -115,11 +115,13 @@ def autotune(cfg, budget_s=20.0, quick=False, use_cache=True, graph_steps=(50, 2
             if ms < best_ms:
                 best, best_ms = tune, ms
     # launch grouping: classes folded into fewer launches, or launches as
-    # parallel graph branches
-    base = dict(best)
-    for merge, par in ((0, 0), (0, 1), (1, 1), (2, 0)):
-        tune = dict(base, merge=merge, parallel=par)
-        ms = _time_candidate(dict(cfg, steps=steps + 4), tune, steps, 4)
+    # parallel graph branches, for the three fastest shapes (the grouping and
+    # the shape interact: on boxes with CPML on every face the all-in-one
+    # launch favours wider tiles than the per-class launches do)
+    results.sort(key=lambda r: r[0])
+    groupings = [dict(t, merge=merge, parallel=par) for _, t in results[:3]
+                 for merge, par in ((0, 0), (0, 1), (1, 1), (2, 0))]
+    for tune, ms in zip(groupings, _time_candidates(dict(cfg, steps=steps + 4), groupings, steps, 4)):
         if verbose:
             print("tune %s: %.2f us/step" % (tune, ms * 1e3), flush=True)
         if ms < best_ms:
