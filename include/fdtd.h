@@ -229,7 +229,8 @@ int fdtd_add_flux_plane(fdtd_plan* p, int32_t axis, int32_t k, const double* f, 
    density) W^n = 1/2 sum (eps |E^n|^2 + H^{n-1/2} . H^{n+1/2}) dx^3 every ke
    steps (0: off). */
 int fdtd_set_energy_interval(fdtd_plan* p, int32_t ke);
-/* Tuning is fixed at bind: call before fdtd_required_bytes / fdtd_bind_arena. */
+/* Launch tuning (no passage of the paper; fdtd_tuning above).  Fixed at bind:
+   call before fdtd_required_bytes / fdtd_bind_arena. */
 int fdtd_set_tuning(fdtd_plan* p, const fdtd_tuning* t);
 int fdtd_get_tuning(const fdtd_plan* p, fdtd_tuning* t);
 
@@ -237,7 +238,8 @@ int fdtd_get_tuning(const fdtd_plan* p, fdtd_tuning* t);
    no passage of the paper: the run length of "Wide-band excitation" is 10^5
    steps). */
 int fdtd_required_bytes(fdtd_plan* p, int64_t max_steps, size_t* bytes);
-/* Bind the caller's device arena dev (>= fdtd_required_bytes, 256-byte aligned,
+/* Bind the caller's device arena (no passage of the paper: device memory) dev
+   (>= fdtd_required_bytes, 256-byte aligned,
    owned by the caller and alive until destroy): fixes the layout, zero-fills,
    uploads tables, voxelizes.  After this the plan's configuration is frozen.
    FDTD_ENOMEM if bytes is too small; synchronizes the stream. */
@@ -252,13 +254,15 @@ int64_t fdtd_step_count(const fdtd_plan* p);
 int64_t fdtd_cell_count(const fdtd_plan* p);
 double fdtd_dt(const fdtd_plan* p);
 
-/* Field component comp (0..5) of the current step, nx*ny*nz floats in host
+/* The Yee fields ("Sample and numerical approach"): component comp (0..5) of
+   the current step, nx*ny*nz floats in host
    memory (caller-owned, dense [nz][ny][nx]; on the device rows may be padded
    for alignment, which the copies undo); write sets initial conditions.
    Synchronize. */
 int fdtd_read_field(fdtd_plan* p, int32_t comp, float* host, void* stream);
 int fdtd_write_field(fdtd_plan* p, int32_t comp, const float* host, void* stream);
-/* Probe samples 0..n-1 (n = steps taken) into host floats (max_steps room). */
+/* Probe samples (the probe of "Wide-band excitation and gap filling") 0..n-1
+   (n = steps taken) into host floats (max_steps room). */
 int fdtd_read_probe(fdtd_plan* p, int32_t id, float* host, int64_t* n, void* stream);
 /* T(t) samples (n = steps taken, may be NULL) and the flux spectrum
    P(f) = Re sum (Ex Hy* - Ey Hx*) dx^2 (nf values, may be NULL) of flux plane id
@@ -277,7 +281,8 @@ int fdtd_read_polarization(fdtd_plan* p, float* host, void* stream);
    Re rho_13, Re rho_23, Im rho_12, Im rho_13, Im rho_23 (zero outside gain
    cells).  FDTD_ESTATE for plans without such a medium. */
 int fdtd_read_density(fdtd_plan* p, float* host, void* stream);
-/* Energy samples W^0, W^ke, ... (n returned) into host doubles. */
+/* Energy samples ("3+1D simulation of lasing": the stored energy) W^0, W^ke,
+   ... (n returned) into host doubles. */
 int fdtd_read_energy(fdtd_plan* p, double* host, int64_t* n, void* stream);
 
 /* Batches ("Wide-band excitation and gap filling": results averaged over 10
@@ -318,7 +323,8 @@ int fdtd_time_steps(fdtd_plan* p, int64_t n, void* stream, double* ms);
 /* Same for a batch. */
 int fdtd_batch_time_steps(fdtd_batch* b, int64_t n, void* stream, double* ms);
 
-/* Autotuning: time ncand candidate tunings of plan p (bound or not; p itself is
+/* Autotuning (no passage of the paper: launch tuning): time ncand candidate
+   tunings of plan p (bound or not; p itself is
    not touched) on scratch plans with p's description and each candidate's
    tuning, bound in turn to the caller's scratch arena (device memory, 256-byte
    aligned, bytes long): warmup untimed steps, then steps timed ones on the
