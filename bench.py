@@ -100,14 +100,51 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def launch_shape(tuning):
+def launch_shape(tuning, cfg=None):
     """The launch parameters a kernel's memory traffic depends on (tile, z-chunk,
-    class grouping, member-group size)."""
+    class grouping, member-group size).  Without x / y CPML and gain, grouping 2
+    (every tile in the most general kernel) launches what grouping 1 does."""
     t = tuning or {}
-    return {k: int(t.get(k, 0)) for k in ("tile_x", "block", "zchunk", "merge", "cache_mb")}
+    out = {k: int(t.get(k, 0)) for k in ("tile_x", "block", "zchunk", "merge", "cache_mb")}
+    if cfg is not None:
+        g = cfg["grid"]
+        xy = any(int(v) > 0 for v in tuple(g.get("pml_lo", (0, 0, 0)))[:2] + tuple(g.get("pml_hi", (0, 0, 0)))[:2])
+        gain = any(int(m.get("gain") or 0) for m in cfg["materials"])
+        if not xy and not gain:
+            out["merge"] = min(out["merge"], 1)
+    return out
 
 
-def recorded_traffic(workload, kernel, tuning):
+# Launch shapes of the side measurements: the fastest of the full tuning sweeps
+# (every tile, z-chunk and class grouping) on these workloads, fixed so that the
+# committed counter profiles, taken in the same shapes, apply (--tune-side runs
+# the quick autotuner instead).
+SIDE_TUNING = {
+    "slab": (32, 256, 8, 50, 1, 0),
+    "paper_beam": (32, 256, 8, 200, 2, 0),
+    "lasing168": (64, 256, 8, 200, 2, 0),
+    "lasing_density": (32, 256, 8, 200, 2, 0),
+    "paper_lasing": (32, 256, 8, 200, 2, 0),
+}
+BATCH_TUNING = (64, 256, 16, 50, 2, 0, 224)
+# the realizations stepped one after another, each alone: the fastest shape of a
+# sweep of those runs (tiles 16/32/64, 128/256 threads, z-chunks 4-16, groupings)
+SEQ_TUNING = (32, 256, 8, 50, 1, 0)
+
+
+def fixed_tuning(v):
+    """Tuning dict from (tile_x, block, zchunk, graph_steps[, merge, parallel[, cache_mb]])."""
+    v = list(v)
+    if len(v) < 6:
+        v += [1, 0][len(v) - 4:]  # merge 1, parallel 0
+    t = {"tile_x": v[0], "block": v[1], "zchunk": v[2], "graph_steps": v[3], "max_blocks": 0,
+         "merge": v[4], "parallel": v[5]}
+    if len(v) > 6:
+        t["cache_mb"] = v[6]
+    return t
+
+
+def recorded_traffic(workload, kernel, tuning, cfg):
     """HBM bytes per launch from the committed rocprofv3 counter runs (FETCH_SIZE,
     WRITE_SIZE, each scaled by the same counter's reading for a copy of known
     size), or None if the kernel source changed since they were taken or they
@@ -120,7 +157,7 @@ def recorded_traffic(workload, kernel, tuning):
         return None
     if not rec or rec.get("kernel_source_sha") != kernel_source_sha():
         return None
-    if rec.get("launch") != launch_shape(tuning):
+    if launch_shape(rec.get("launch"), cfg) != launch_shape(tuning, cfg):
         return None
     return rec["hbm_bytes_per_launch"]
 
@@ -190,11 +227,11 @@ def timed_run(plan, steps):
     return time.perf_counter() - t0
 
 
-def _roofline(kern, kname, workload, tuning, copy_gbs=None):
+def _roofline(kern, kname, workload, tuning, cfg, copy_gbs=None):
     k = kern[kname]
     out = {"bound": "hbm", "kernel": kname, "achieved": k["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": k["GBps"] / HBM_PEAK_GBS, "avg_launch_ms": k["avg_ms"], "alg_bytes_per_launch": k["alg_bytes"],
-           "traffic": recorded_traffic(workload, kname, tuning)}
+           "traffic": recorded_traffic(workload, kname, tuning, cfg)}
     if out["traffic"]:
         # the counted HBM bytes of a launch over the same live duration: the
         # rocprofv3-counted rate beside the algorithmic one
@@ -216,9 +253,7 @@ def measure_plain(args):
     cfg = headline_config(total, args.workload)
     t0 = time.perf_counter()
     if args.tuning:
-        v = [int(q) for q in args.tuning.split(",")] + [1, 0]
-        tuning = {"tile_x": v[0], "block": v[1], "zchunk": v[2], "graph_steps": v[3], "max_blocks": 0,
-                  "merge": v[4], "parallel": v[5]}
+        tuning = fixed_tuning([int(q) for q in args.tuning.split(",")])
     else:
         tuning = tune.autotune(dict(cfg), budget_s=args.tune_seconds)
     log("plain: tuning %s (%.1f s)" % (tuning, time.perf_counter() - t0))
@@ -239,7 +274,8 @@ def measure_side(args, workload, steps, warm, kernel_steps, copy_gbs):
     from paper_0802_3775_amd import fdtd, tune
     total = warm + steps + kernel_steps
     cfg = headline_config(total, workload)
-    tuning = tune.autotune(dict(cfg), budget_s=args.tune_seconds, quick=True)
+    tuning = (tune.autotune(dict(cfg), budget_s=args.tune_seconds, quick=True) if args.tune_side
+              else fixed_tuning(SIDE_TUNING[workload]))
     plan = fdtd.Plan(cfg, max_steps=total, tuning=tuning)
     plan.step(warm)
     wall = timed_run(plan, steps)
@@ -248,13 +284,14 @@ def measure_side(args, workload, steps, warm, kernel_steps, copy_gbs):
     plan.close()
     return {"workload": WORKLOADS[workload], "cells": n, "steps_timed": steps, "cell_updates_per_s": n * steps / wall,
             "ms_per_step": 1e3 * wall / steps, "tuning": tuning,
-            "roofline": _roofline(kern, _dominant(kern), workload, tuning, copy_gbs), "kernels": kern}
+            "roofline": _roofline(kern, _dominant(kern), workload, tuning, cfg, copy_gbs), "kernels": kern}
 
 
 def measure_lasing_density(args, steps=1000):
     from paper_0802_3775_amd import fdtd, tune
     cfg = headline_config(steps + 300, "lasing_density")
-    tuning = tune.autotune(dict(cfg), budget_s=args.tune_seconds, quick=True)
+    tuning = (tune.autotune(dict(cfg), budget_s=args.tune_seconds, quick=True) if args.tune_side
+              else fixed_tuning(SIDE_TUNING["lasing_density"]))
     plan = fdtd.Plan(cfg, max_steps=steps + 300, tuning=tuning)
     plan.step(100)
     wall = timed_run(plan, steps)
@@ -263,7 +300,7 @@ def measure_lasing_density(args, steps=1000):
     plan.close()
     return {"workload": WORKLOADS["lasing_density"], "cells": n, "steps_timed": steps,
             "cell_updates_per_s": n * steps / wall, "ms_per_step": 1e3 * wall / steps, "tuning": tuning,
-            "roofline": _roofline(kern, _dominant(kern), "lasing_density", tuning), "kernels": kern}
+            "roofline": _roofline(kern, _dominant(kern), "lasing_density", tuning, cfg), "kernels": kern}
 
 
 def measure_cpu(workload, budget_s):
@@ -301,16 +338,17 @@ def measure_batched(args, kernel_steps=30):
     steps = args.batch_steps
     cfgs = W.ensemble(count=64, steps=10000)
     if args.batch_tuning:
-        v = [int(q) for q in args.batch_tuning.split(",")]
-        tuning = {"tile_x": v[0], "block": v[1], "zchunk": v[2], "graph_steps": v[3], "max_blocks": 0,
-                  "merge": v[4], "parallel": v[5], "cache_mb": v[6]}
-    else:
+        tuning = fixed_tuning([int(q) for q in args.batch_tuning.split(",")])
+    elif args.tune_side:
         tuning = tune.tune_batch(cfgs, budget_s=args.tune_seconds)
+    else:
+        tuning = fixed_tuning(BATCH_TUNING)
     cells = sum(c["grid"]["n"][0] * c["grid"]["n"][1] * c["grid"]["n"][2] for c in cfgs)
     seq = None
     seq_tuning = None
     if not args.no_sequential:
-        seq_tuning = tune.common_tuning(cfgs, budget_s=args.tune_seconds)  # tuned for plain runs
+        seq_tuning = (tune.common_tuning(cfgs, budget_s=args.tune_seconds) if args.tune_side
+                      else fixed_tuning(SEQ_TUNING))
         seq = 0.0
         for c in cfgs:           # sequential plain: each realization alone
             p = fdtd.Plan(c, max_steps=steps + 50, tuning=seq_tuning)
@@ -353,7 +391,7 @@ def measure_batched(args, kernel_steps=30):
             "realizations_per_hour": 3600.0 * len(cfgs) / (tb * scale),
             "sequential_realizations_per_hour": 3600.0 * len(cfgs) / (seq * scale) if seq else None,
             "speedup_vs_sequential": seq / tb if seq else None,
-            "roofline": _roofline(kern, _dominant(kern), "batched", tuning),
+            "roofline": _roofline(kern, _dominant(kern), "batched", tuning, None),
             "step_alg_GBps": step_bytes / (tb / steps) / 1e9,
             "step_frac": step_bytes / (tb / steps) / 1e9 / HBM_PEAK_GBS,
             "kernels": kern,
@@ -416,6 +454,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tune-seconds", type=float, default=15.0)
+    ap.add_argument("--tune-side", action="store_true",
+                    help="autotune the side measurements instead of their fixed launch shapes")
     ap.add_argument("--serve-requests", type=int, default=8)
     ap.add_argument("--serve-chunk", type=int, default=1000)
     ap.add_argument("--workload", choices=tuple(WORKLOADS), default="big320",
@@ -492,7 +532,7 @@ def headline(args, copy_gbs):
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload],
                    "cells": plain["ncell"], "tuning": plain["tuning"]},
-        "roofline": _roofline(plain["kernels"], plain["dominant"], args.workload, plain["tuning"], copy_gbs),
+        "roofline": _roofline(plain["kernels"], plain["dominant"], args.workload, plain["tuning"], plain["cfg"], copy_gbs),
         "kernels": plain["kernels"],
     }
     if not args.no_cpu:
