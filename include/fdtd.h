@@ -270,9 +270,12 @@ int fdtd_read_probe(fdtd_plan* p, int32_t id, float* host, int64_t* n, void* str
 int fdtd_read_flux(fdtd_plan* p, int32_t id, double* T, double* spec, int64_t* n, void* stream);
 /* Populations n0..n3 of the four-level medium ("Sample and numerical approach":
    the four-level system; the density matrix's diagonal for gain = 2), 4 * cells
-   floats, zero outside gain cells.  n0 is not stored: it is 1 - (n1 + n2 + n3),
-   so the sum of the four is 1 by construction. */
-int fdtd_read_populations(fdtd_plan* p, float* host, void* stream);
+   doubles, zero outside gain cells.  The device holds n1..n3 as FP32 (hi, lo)
+   pairs, so that the small per-step changes of a weak pump are not rounded
+   away; each level is returned as the exact sum of its pair.  n0 is not
+   stored: it is 1 - (n1 + n2 + n3), so the sum of the four is 1 by
+   construction. */
+int fdtd_read_populations(fdtd_plan* p, double* host, void* stream);
 /* Polarization P^n of the gain cells (same passage), 3 * cells floats. */
 int fdtd_read_polarization(fdtd_plan* p, float* host, void* stream);
 /* Density matrix ("Sample and numerical approach": the su(4) real form of the

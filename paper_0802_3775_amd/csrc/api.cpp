@@ -470,7 +470,7 @@ int compute_layout(fdtd_plan* p, int64_t max_steps, Layout& L) {
   const int gm = gain_model_of(p->mats);
   L.desc = take(sizeof(fd_desc));
   L.mats = take(sizeof(fd_mat) * FD_MAXMAT);
-  L.ninit = take(sizeof(float) * 4 * FD_MAXMAT);
+  L.ninit = take(sizeof(float) * 8 * FD_MAXMAT);
   for (int b = 0; b < 2; ++b)
     for (int c = 0; c < 3; ++c) L.E[b][c] = take(nc * 4);
   for (int b = 0; b < 2; ++b)
@@ -978,7 +978,9 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
 
   // materials
   std::vector<fd_mat> mt(FD_MAXMAT);
-  std::vector<float> ninit(4 * FD_MAXMAT, 0.0f);
+  // initial populations per material as FP32 (hi, lo) pairs: hi + lo is n_init
+  // to about 48 bits, as the state stores them
+  std::vector<float> ninit(8 * FD_MAXMAT, 0.0f);
   p->has_gain = false;
   p->gm = gain_model_of(p->mats);
   for (size_t q = 0; q < p->mats.size(); ++q) {
@@ -986,7 +988,11 @@ int fdtd_bind_arena(fdtd_plan* p, void* dev, size_t bytes, int64_t max_steps, vo
     if (r) return r;
     if (p->mats[q].gain) {
       p->has_gain = true;
-      for (int l = 0; l < 4; ++l) ninit[4 * q + l] = (float)p->mats[q].n_init[l];
+      for (int l = 0; l < 4; ++l) {
+        const float hi = (float)p->mats[q].n_init[l];
+        ninit[8 * q + l] = hi;
+        ninit[8 * q + 4 + l] = (float)(p->mats[q].n_init[l] - (double)hi);
+      }
     }
   }
   HIPCHK(hipMemcpyAsync(p->arena + L.mats, mt.data(), sizeof(fd_mat) * FD_MAXMAT, hipMemcpyHostToDevice, st));
@@ -1482,7 +1488,7 @@ int fdtd_read_flux(fdtd_plan* p, int32_t id, double* T, double* spec, int64_t* n
   return FDTD_OK;
 }
 
-int fdtd_read_populations(fdtd_plan* p, float* host, void* stream) {
+int fdtd_read_populations(fdtd_plan* p, double* host, void* stream) {
   if (!p || !host) return fail(FDTD_EINVAL, "null argument");
   if (!p->bound) return fail(FDTD_ESTATE, "plan not bound");
   if (!p->has_gain) return fail(FDTD_ESTATE, "no gain material");
@@ -1493,14 +1499,14 @@ int fdtd_read_populations(fdtd_plan* p, float* host, void* stream) {
   HIPCHK(hipStreamSynchronize(st));
   for (size_t o = 0; o < nc; ++o) {
     if (!p->mats[p->host_map[o]].gain) {
-      for (int l = 0; l < 4; ++l) host[l * nc + o] = 0.0f;
+      for (int l = 0; l < 4; ++l) host[l * nc + o] = 0.0;
       continue;
     }
     const size_t q = p->gidx[o];  // state index of the cell
-    double lv[3];
+    double lv[3];  // hi + lo of each pair: exact in FP64
     for (int l = 0; l < 3; ++l) lv[l] = (double)pop[l * ns + q] + (double)pop[(3 + l) * ns + q];
-    host[0 * nc + o] = (float)(1.0 - (lv[0] + lv[1] + lv[2]));
-    for (int l = 0; l < 3; ++l) host[(1 + l) * nc + o] = (float)lv[l];
+    host[0 * nc + o] = 1.0 - (lv[0] + lv[1] + lv[2]);
+    for (int l = 0; l < 3; ++l) host[(1 + l) * nc + o] = lv[l];
   }
   return FDTD_OK;
 }

@@ -189,6 +189,7 @@ hipError_t fd_launch_voxelize(const int64_t* sites, int ex, int ey, int ez, cons
 hipError_t fd_launch_dm(const fd_dm_unit* cells, int ncells, const fd_dm_unit* edges, int nedges,
                         const fd_dm_unit* diag, int ndiag, int block, int s, hipStream_t st,
                         hipEvent_t* ev = nullptr);
+// n_init_by_mat: per material 8 floats, n0..n3 as FP32 (hi[4], lo[4]) pairs
 hipError_t fd_launch_init_pop(const uint8_t* map, const float* n_init_by_mat, const uint32_t* gidx, unsigned gainmask,
                               float* pop, int ncell, int nx, int px, hipStream_t st);
 

@@ -631,6 +631,10 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   // all-axes CPML: slab indices of the own column and of the halo-duty cell along
   // x and y (fixed over the march), and the tile's x / y grading tables in LDS
   int sxo = -1, syo = -1, sxh = -1, syh = -1;
+  // uniform: the tile's columns (with the halo column i0-1) reach an x slab,
+  // its rows (with the halo row j0-1) a y slab
+  const bool uxs = AX && x.t[0] > 0 && (i0 - 1 < x.lo[0] || i0 + TX > x.nx - x.hi[0]);
+  const bool uys = AX && x.t[1] > 0 && (j0 - 1 < x.lo[1] || j0 + TY > x.ny - x.hi[1]);
   if (AX) {
     sxo = slab(x, 0, i);
     syo = slab(x, 1, j);
@@ -668,20 +672,36 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       ohx = (hact && sxh >= 0) ? (uint32_t)((k * x.ny + hgj) * x.t[0] + sxh) : 0u;
       ohy = (hact && syh >= 0) ? (uint32_t)((k * x.t[1] + syh) * x.nx + hgi) : 0u;
       ohz = (hact && sz >= 0) ? (uint32_t)(sz * x.plane + h_off) : 0u;
-      // own H: Hx(y, z), Hy(z, x), Hz(x, y); own E in the same order
-      aH[0] = x.psiHin[1][1][oy]; aH[1] = x.psiHin[2][0][oz];
-      aH[2] = x.psiHin[2][1][oz]; aH[3] = x.psiHin[0][0][ox];
-      aH[4] = x.psiHin[0][1][ox]; aH[5] = x.psiHin[1][0][oy];
-      aE[0] = x.psiE[1][1][oy]; aE[1] = x.psiE[2][0][oz];
-      aE[2] = x.psiE[2][1][oz]; aE[3] = x.psiE[0][0][ox];
-      aE[4] = x.psiE[0][1][ox]; aE[5] = x.psiE[1][0][oy];
+      // own H: Hx(y, z), Hy(z, x), Hz(x, y); own E in the same order.  The
+      // reads of an axis whose slabs neither the tile (x, y) nor the plane (z)
+      // touches are skipped (uniform branches; the values stay 0 and unused)
       // halo: column cells (lh) need Hy(z, x), row cells Hx(y, z); both need Hz(x, y)
-      const gf* pc1z = lh ? x.psiHin[2][1].p : x.psiHin[2][0].p;
-      const gf* pc1o = lh ? x.psiHin[0][0].p : x.psiHin[1][1].p;
-      aHh[0] = pc1z[ohz];
-      aHh[1] = pc1o[lh ? ohx : ohy];
-      aHh[2] = x.psiHin[0][1][ohx];
-      aHh[3] = x.psiHin[1][0][ohy];
+      if (uxs) {
+        aH[3] = x.psiHin[0][0][ox];
+        aH[4] = x.psiHin[0][1][ox];
+        aE[3] = x.psiE[0][0][ox];
+        aE[4] = x.psiE[0][1][ox];
+        aHh[2] = x.psiHin[0][1][ohx];
+      }
+      if (uys) {
+        aH[0] = x.psiHin[1][1][oy];
+        aH[5] = x.psiHin[1][0][oy];
+        aE[0] = x.psiE[1][1][oy];
+        aE[5] = x.psiE[1][0][oy];
+        aHh[3] = x.psiHin[1][0][ohy];
+      }
+      if (uxs | uys) {
+        const gf* pc1o = lh ? x.psiHin[0][0].p : x.psiHin[1][1].p;
+        aHh[1] = pc1o[lh ? ohx : ohy];
+      }
+      if (sz >= 0) {
+        aH[1] = x.psiHin[2][0][oz];
+        aH[2] = x.psiHin[2][1][oz];
+        aE[1] = x.psiE[2][0][oz];
+        aE[2] = x.psiE[2][1][oz];
+        const gf* pc1z = lh ? x.psiHin[2][1].p : x.psiHin[2][0].p;
+        aHh[0] = pc1z[ohz];
+      }
       if (sz >= 0) {  // uniform: the z grading exists only with z slabs
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
@@ -1348,8 +1368,9 @@ __global__ void voxelize_kernel(const int64_t* __restrict__ sites, int ex, int e
   }
 }
 
-// Initial upper-level populations of the gain cells at their gain ordinals (the
-// low parts and every other state variable start at zero with the arena).
+// Initial upper-level populations of the gain cells at their gain ordinals, as
+// (hi, lo) pairs whose sum is n_init to about 48 bits (every other state
+// variable starts at zero with the arena).
 __global__ void init_pop_kernel(const uint8_t* __restrict__ map, const float* __restrict__ ninit,
                                 const uint32_t* __restrict__ gidx, unsigned gainmask, float* pop, int ncell,
                                 int nx, int px) {
@@ -1360,7 +1381,10 @@ __global__ void init_pop_kernel(const uint8_t* __restrict__ map, const float* __
     if (!((gainmask >> m) & 1u)) continue;
     const uint32_t g = gidx[o];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) pop[(size_t)q * ncell + g] = ninit[4 * m + 1 + q];
+    for (int q = 0; q < 3; ++q) {
+      pop[(size_t)q * ncell + g] = ninit[8 * m + 1 + q];        // hi
+      pop[(size_t)(3 + q) * ncell + g] = ninit[8 * m + 5 + q];  // lo
+    }
   }
 }
 

@@ -102,7 +102,7 @@ SIGNATURES = {
     "fdtd_write_field": ([VP, C.c_int32, P(C.c_float), VP], C.c_int),
     "fdtd_read_probe": ([VP, C.c_int32, P(C.c_float), P(C.c_int64), VP], C.c_int),
     "fdtd_read_flux": ([VP, C.c_int32, P(C.c_double), P(C.c_double), P(C.c_int64), VP], C.c_int),
-    "fdtd_read_populations": ([VP, P(C.c_float), VP], C.c_int),
+    "fdtd_read_populations": ([VP, P(C.c_double), VP], C.c_int),
     "fdtd_read_polarization": ([VP, P(C.c_float), VP], C.c_int),
     "fdtd_read_density": ([VP, P(C.c_float), VP], C.c_int),
     "fdtd_read_energy": ([VP, P(C.c_double), P(C.c_int64), VP], C.c_int),
@@ -378,8 +378,9 @@ class Plan:
         return T[: n.value], spec[: self.nf[fid]]
 
     def populations(self, stream=None):
-        out = np.zeros((4,) + self.n[::-1], dtype=np.float32)
-        _check(lib().fdtd_read_populations(self.h, _ptr(out, C.c_float), _stream(stream)))
+        """n0..n3 of the gain cells (FP64: the exact sums of the stored pairs)."""
+        out = np.zeros((4,) + self.n[::-1], dtype=np.float64)
+        _check(lib().fdtd_read_populations(self.h, _ptr(out, C.c_double), _stream(stream)))
         return out
 
     def density(self, stream=None):

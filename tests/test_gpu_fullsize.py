@@ -84,9 +84,8 @@ def _run_checkpoints(name, tol_fields, tuning_extra=None, fields=True):
 
 def _check_populations(plan, fx, cp):
     gi = fx["gain_idx"]
-    g = plan.populations().reshape(4, -1)[:, gi].astype(np.float64)
-    # n0 from the stored upper levels, in FP64 (the read rounds each level to FP32)
-    g[0] = 1.0 - (g[1] + g[2] + g[3])
+    # FP64: each level the exact sum of its stored pair, n0 = 1 - (n1 + n2 + n3)
+    g = plan.populations().reshape(4, -1)[:, gi]
     dg = g - fx["pop_init"]
     do = fx["pop_%d" % cp] - fx["pop_init"]
     scale = np.abs(do).max()
@@ -163,6 +162,18 @@ def test_density_lasing_box_168():
     shape: fields, the 15 state values, populations and polarization at sampled
     gain cells at two checkpoints; probe and energy."""
     plan, fx = _run_checkpoints("lasing_density168", 1e-3)
+    assert rel_l2(plan.probe(0), fx["probe0"]) <= 1e-3
+    assert rel_l2(plan.energy(), fx["energy"]) <= 1e-3
+    plan.close()
+
+
+def test_paper_lasing_box_200():
+    """The paper's lasing box (200^3: 8^3 cells of the eps-12 inverted opal at 16
+    cells/a, gamma 0.1, the density-matrix dye in the voids, inverted start, pump
+    1e10 s^-1, seeded noise) for 400 steps in the autotuned launch shape: fields,
+    the 15 state values, populations and polarization at sampled gain cells at two
+    checkpoints; probe and energy."""
+    plan, fx = _run_checkpoints("paper_lasing_400", 1e-3)
     assert rel_l2(plan.probe(0), fx["probe0"]) <= 1e-3
     assert rel_l2(plan.energy(), fx["energy"]) <= 1e-3
     plan.close()
