@@ -498,8 +498,9 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
     float ge[3];  // z-slab planes: E-side grading (uniform)
     uint32_t gi;  // gain cells: the cell's gain ordinal (index of its gain state)
   };
-  // Every global load of the z march is issued unconditionally (a lane with
-  // nothing to load reads element 0 and discards it), and the march stores to
+  // Every global load of the z march is issued whatever the lane's own cell (a
+  // lane with nothing to load reads element 0 and discards it; only uniform
+  // conditions -- the all-axes tile's slabs -- skip loads), and the march stores to
   // global memory only the fields and CPML memory: the loads in flight per
   // iteration are then the same on every path, so the compiler waits for
   // exactly the Stage it consumes and leaves the other one in flight.
@@ -661,7 +662,7 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
     const int zo = k * x.plane;
     const int o = zo + c;
     const int sz = (ZP || AX) ? slab(x, 2, k) : -1;
-    // all-axes CPML: every old psi the plane needs, issued before the barriers
+    // all-axes CPML: the old psi the plane needs, issued before the barriers
     // (lanes outside a slab read element 0); z grading is uniform over the plane
     float aH[6] = {}, aE[6] = {}, aHh[4] = {}, gzE[3] = {}, gzH[3] = {};
     uint32_t ox = 0, oy = 0, oz = 0, ohx = 0, ohy = 0, ohz = 0;
