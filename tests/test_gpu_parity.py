@@ -469,3 +469,22 @@ def test_nontemporal_stores_are_bit_identical(which):
     err = field_rel_l2(runs[1][0], orc.fields())
     _say(which, "non-temporal vs oracle", err)
     assert err <= (1e-4 if which == "slab" else 1e-3)
+
+
+@pytest.mark.parametrize("model", ["lorentz", "density"])
+def test_initial_populations_are_n_init(model):
+    """The stored (hi, lo) pairs start as n_init to ~48 bits and read back as their
+    exact FP64 sum: before any step every gain cell holds n_init (1/3 and 0.1 are
+    not FP32 numbers; FP32 alone would be off by up to 1e-8)."""
+    n_init = (1.0 / 3.0, 0.1, 0.5 - 1.0 / 3.0 + 0.3, 0.1)
+    n_init = (1.0 - sum(n_init[1:]),) + n_init[1:]
+    cfg = W.lasing(res=10, cells=(2, 2, 2), pml=6, steps=10, noise=0.0, model=model, n_init=n_init)
+    gpu = run_gpu(cfg, 0)
+    gain = gpu.material_map() == 1
+    got = gpu.populations()[:, gain]
+    want = np.array(n_init)[:, None]
+    err = np.abs(got - want).max()
+    _say(model, "initial populations vs n_init: max |diff| %.3e" % err)
+    assert gain.sum() > 0
+    assert err <= 1e-14
+    gpu.close()
