@@ -251,6 +251,34 @@ __device__ __forceinline__ float h_from(const Ctx& x, int c, int w1, int p1, int
   return fmaf(-x.ch, d1 - d2, hold);
 }
 
+// The H-side stretch of a difference of the plane below a tile (the prologue
+// of the all-axes march; no psi store), in two parts so that the loads go out
+// with the prologue's other loads, whatever the lane's slab membership (index 0
+// outside a slab; the result is selected): pre_load issues them, pre_apply is
+// stretch<true, PM>(.., own = false) bit for bit.
+struct PreStretch {
+  float kinv, b, cc, po;
+  bool in;
+};
+template <int PM>
+__device__ __forceinline__ PreStretch pre_load(const Ctx& x, int c, int w, int p, int i, int j, int k, bool live) {
+  PreStretch r{1.0f, 0.0f, 0.0f, 0.0f, false};
+  if (!((PM >> w) & 1) || x.t[w] == 0) return r;  // uniform: no slab code on this axis
+  const int sp = slab(x, w, p);
+  r.in = live && sp >= 0;
+  const cfloat* pr = x.prof[w] + 3 * x.n[w];
+  const int pc = r.in ? p : 0;
+  r.kinv = pr[pc];
+  r.b = pr[x.n[w] + pc];
+  r.cc = pr[2 * x.n[w] + pc];
+  r.po = x.psiHin[w][fam(c, w)][r.in ? psi_off(x, w, sp, i, j, k) : 0];
+  return r;
+}
+__device__ __forceinline__ float pre_apply(const PreStretch& r, float d) {
+  const float psi = fmaf(r.b, r.po, r.cc * d);
+  return r.in ? fmaf(d, r.kinv, psi) : d;
+}
+
 // Workgroup barrier for LDS traffic only.  Within a step no workgroup reads
 // global memory that another thread of the step writes (inputs and outputs are
 // separate buffers), so the barrier waits for outstanding LDS operations but
@@ -607,6 +635,30 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
     pHx = x.Hin[0][om];
     pHy = x.Hin[1][om];
   }
+  // all-axes tiles: the CPML inputs of H at plane k0-1 and this thread's first
+  // entry of the x / y grading tables, issued now so that their latency
+  // overlaps the loads above instead of following them
+  PreStretch px1{}, px2{}, py1{}, py2{};
+  float gxv = 0.0f, gyv = 0.0f;
+  if (AX) {
+    px1 = pre_load<PM>(x, 0, 1, j, i, j, km, pro);
+    px2 = pre_load<PM>(x, 0, 2, km, i, j, km, pro);
+    py1 = pre_load<PM>(x, 1, 2, km, i, j, km, pro);
+    py2 = pre_load<PM>(x, 1, 0, i, i, j, km, pro);
+    if (x.t[0] > 0) {
+      const int r = t / (TX + 1), ii = i0 - 1 + t % (TX + 1);
+      const bool ok = t < 6 * (TX + 1) && ii >= 0 && ii < x.nx && slab(x, 0, ii) >= 0;
+      const float v = x.prof[0][ok ? r * x.nx + ii : 0];
+      gxv = ok ? v : 0.0f;
+    }
+    if (x.t[1] > 0) {
+      constexpr int GY = Lds<TX>::TYM + 1;
+      const int r = t / GY, jj = j0 - 1 + t % GY;
+      const bool ok = t < 6 * GY && jj >= 0 && jj < x.ny && slab(x, 1, jj) >= 0;
+      const float v = x.prof[1][ok ? r * x.ny + jj : 0];
+      gyv = ok ? v : 0.0f;
+    }
+  }
   float ecur[3];  // E^n of the own cell at the plane being marched
   store_e(0, SA, ecur);
   load_e(k0 + 1, SA, true);
@@ -615,7 +667,14 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
   load_h(k0 + 1, SB, k0 + 1 < k1);
   // H^{n+1/2} at (i, j, k0-1); E^n at (i, j, k0) is already in LDS buffer 0
   float hxm = 0.0f, hym = 0.0f;
-  if (pro) {
+  if (AX) {
+    const float ey1 = ecur[1], ex1 = ecur[0];
+    const float ezj = jp >= 0 ? pEzj : 0.0f, ezi = ip >= 0 ? pEzi : 0.0f;
+    const float hx = fmaf(-x.ch, pre_apply(px1, ezj - pEz) - pre_apply(px2, ey1 - pEy), pHx);
+    const float hy = fmaf(-x.ch, pre_apply(py1, ex1 - pEx) - pre_apply(py2, ezi - pEz), pHy);
+    hxm = pro ? hx : 0.0f;
+    hym = pro ? hy : 0.0f;
+  } else if (pro) {
     const float ey1 = ecur[1], ex1 = ecur[0];
     const float ezj = jp >= 0 ? pEzj : 0.0f, ezi = ip >= 0 ? pEzi : 0.0f;
     hxm = h_from<PM>(x, 0, 1, j, 2, km, i, j, km, ezj, pEz, ey1, pEy, pHx, false);
@@ -643,11 +702,13 @@ __device__ void run_tile(const fd_tile& tl, int s_rel, Lds<TX>& s) {
       sxh = slab(x, 0, hgi);
       syh = slab(x, 1, hgj);
     }
-    for (int q = t; q < 6 * (TX + 1); q += (int)blockDim.x) {
+    if (t < 6 * (TX + 1)) s.gx[t / (TX + 1)][t % (TX + 1)] = gxv;
+    for (int q = t + (int)blockDim.x; q < 6 * (TX + 1); q += (int)blockDim.x) {
       const int r = q / (TX + 1), ii = i0 - 1 + q % (TX + 1);
       s.gx[r][q % (TX + 1)] = (ii >= 0 && ii < x.nx && slab(x, 0, ii) >= 0) ? x.prof[0][r * x.nx + ii] : 0.0f;
     }
-    for (int q = t; q < 6 * (Lds<TX>::TYM + 1); q += (int)blockDim.x) {
+    if (t < 6 * (Lds<TX>::TYM + 1)) s.gy[t / (Lds<TX>::TYM + 1)][t % (Lds<TX>::TYM + 1)] = gyv;
+    for (int q = t + (int)blockDim.x; q < 6 * (Lds<TX>::TYM + 1); q += (int)blockDim.x) {
       const int r = q / (Lds<TX>::TYM + 1), jj = j0 - 1 + q % (Lds<TX>::TYM + 1);
       s.gy[r][q % (Lds<TX>::TYM + 1)] = (jj >= 0 && jj < x.ny && slab(x, 1, jj) >= 0) ? x.prof[1][r * x.ny + jj] : 0.0f;
     }
