@@ -424,7 +424,7 @@ def measure_serving(args, plain_rate):
         reqs = [dict(r, arrival=r["arrival"] / lam) for r in base]
         backend = serve.GpuBackend()
         free, _ = torch.cuda.mem_get_info()
-        srv = serve.Server(backend, budget_bytes=int(0.8 * free), chunk=args.serve_chunk)
+        srv = serve.Server(backend, budget_bytes=int(0.8 * free), chunk=args.serve_chunk, policy=args.serve_policy)
         wall = srv.run(reqs)
         s_b = serve.summarize(reqs, wall, srv.results, srv.failed)
         backend.close()
@@ -439,6 +439,7 @@ def measure_serving(args, plain_rate):
         log("serving rho %.1f: served p50 %.2f s p99 %.2f s, FIFO p50 %.2f s p99 %.2f s" %
             (rho, s_b["p50_s"], s_b["p99_s"], s_s["p50_s"], s_s["p99_s"]))
     out["chunk_steps"] = args.serve_chunk
+    out["policy"] = args.serve_policy
     out["note"] = ("%d requests per load (the stream has 200) at the stream's sizes (1M-33M crystal cells) and "
                    "lengths (10k linear / 20k lasing steps)" % args.serve_requests)
     return out
@@ -458,6 +459,8 @@ def main():
                     help="autotune the side measurements instead of their fixed launch shapes")
     ap.add_argument("--serve-requests", type=int, default=8)
     ap.add_argument("--serve-chunk", type=int, default=1000)
+    ap.add_argument("--serve-policy", choices=("fifo", "srpt", "all"), default="fifo",
+                    help="serving: which admitted requests each launch steps")
     ap.add_argument("--workload", choices=tuple(WORKLOADS), default="big320",
                     help="headline 320^3 grid (default); the others for profiling")
     ap.add_argument("--only", default="", help="comma list of side measurements to run (profiling): "

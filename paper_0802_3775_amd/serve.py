@@ -11,13 +11,17 @@ older work is still running.  Each request keeps its own step counter, source
 timing and DFT phase, so its result is bit-identical to a run of the same
 request alone.
 
-Which admitted requests a launch steps: with policy "srpt" (the default), the
-group whose remaining work (cells x remaining steps, lasing cells weighted by
-their higher per-cell cost) is within `group_factor` of the smallest -- the
-shortest-remaining-work-first order, which minimises mean latency on one
-device, with similar requests batched together; with policy "all", every
-admitted request.  Requests outside the group stay resident and continue when
-they become the smallest.
+Which admitted requests a launch steps: with policy "fifo" (the default), the
+oldest admitted request, joined by the smallest others as long as their
+remaining work (cells x remaining steps, lasing cells weighted by their higher
+per-cell cost) together stays within `ride_frac` of its own -- first come first
+served, the order that minimises the largest latency on one device, with small
+requests progressing alongside instead of waiting behind it; with policy
+"srpt", the group whose remaining work is within `group_factor` of the
+smallest -- the shortest-remaining-work-first order, which minimises mean
+latency when requests are small and starves the large ones when they are not;
+with policy "all", every admitted request.  Requests outside the group stay resident and continue when
+their turn comes.
 
 The scheduling policy (Server) is independent of the device: a Backend does
 the work.  GpuBackend drives libfdtd; tests drive the same policy with a host
@@ -154,12 +158,13 @@ class GpuBackend:
 class Server:
     """Arrival-ordered admission by footprint; batched stepping in chunks."""
 
-    def __init__(self, backend, budget_bytes, chunk=400, max_active=64, clock=None, sleep=None, policy="srpt",
-                 group_factor=4.0):
-        if policy not in ("srpt", "all"):
-            raise ValueError("policy must be 'srpt' or 'all'")
+    def __init__(self, backend, budget_bytes, chunk=400, max_active=64, clock=None, sleep=None, policy="fifo",
+                 group_factor=4.0, ride_frac=0.125):
+        if policy not in ("srpt", "fifo", "all"):
+            raise ValueError("policy must be 'srpt', 'fifo' or 'all'")
         self.policy = policy
         self.group_factor = float(group_factor)
+        self.ride_frac = float(ride_frac)
         self.backend = backend
         self.budget = int(budget_bytes)
         self.chunk = int(chunk)
@@ -220,6 +225,16 @@ class Server:
         if self.policy == "all" or len(self.active) == 1 or not hasattr(self.backend, "work"):
             return list(self.active)
         w = [self.backend.work(e["h"], e["req"]["steps"] - e["done"]) for e in self.active]
+        if self.policy == "fifo":
+            head = min(range(len(self.active)), key=lambda q: (self.active[q]["req"]["arrival"],
+                                                                self.active[q]["req"]["id"]))
+            group, ride = [self.active[head]], 0.0
+            for q in sorted((q for q in range(len(self.active)) if q != head), key=lambda q: w[q]):
+                if ride + w[q] > self.ride_frac * w[head]:
+                    break
+                ride += w[q]
+                group.append(self.active[q])
+            return group
         wmin = min(w)
         return [e for e, x in zip(self.active, w) if x <= self.group_factor * wmin]
 

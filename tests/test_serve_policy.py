@@ -173,6 +173,39 @@ def test_shortest_remaining_work_first_groups_similar_requests():
     assert s_srpt["p50_s"] < s_all["p50_s"]
 
 
+def test_fifo_with_small_riders():
+    """With policy fifo the oldest admitted request is stepped first, and small
+    requests ride along while their remaining work together stays within
+    ride_frac of its remaining work: the large requests finish in arrival order,
+    the oldest no later than its own work plus the riders' (on a device that is
+    busy with every member of a launch), and a request too large to ride waits
+    its turn."""
+    reqs = [_sized(0, 0.0, 1000, 100), _sized(1, 0.01, 1000, 5), _sized(2, 0.01, 1000, 6),
+            _sized(3, 0.02, 1000, 100)]
+    clk = FakeClock()
+    be = SizedBackend(clk, step_cost=1e-6)
+    srv = Server(be, budget_bytes=1000, chunk=100, clock=clk, sleep=clk.sleep, policy="fifo", ride_frac=0.25)
+    srv.run(reqs)
+    assert set(srv.results) == {0, 1, 2, 3} and not srv.failed
+    assert all(srv.results[r["id"]]["steps"] == r["steps"] for r in reqs)
+    done = {rid: t for ev, rid, t in srv.log if ev == "done"}
+    # both small requests rode with the head once admitted
+    assert any(b == [0, 1, 2] for b in be.batches)
+    # first come, first served among the large ones; 3 never shared a launch with 0
+    assert done[0] < done[3]
+    assert not any(3 in b and 0 in b for b in be.batches)
+    # the head took at most its own work plus the riders' (1000 steps x (100 + 5 + 6) cells)
+    assert done[0] <= 1000 * 1e-6 * (100 + 5 + 6) + 1e-9
+    # a rider too large for the share (20 x 1000 > 0.125 x 100 x 1000) waits its turn
+    clk2 = FakeClock()
+    be2 = SizedBackend(clk2, step_cost=1e-6)
+    big = [_sized(0, 0.0, 1000, 100), _sized(1, 0.01, 1000, 20)]
+    srv2 = Server(be2, budget_bytes=1000, chunk=100, clock=clk2, sleep=clk2.sleep, policy="fifo", ride_frac=0.125)
+    srv2.run(big)
+    assert set(srv2.results) == {0, 1}
+    assert not any(0 in b and 1 in b for b in be2.batches)
+
+
 def test_percentile():
     assert percentile([1, 2, 3, 4], 50) == 2.5
     assert percentile([5], 99) == 5
