@@ -269,8 +269,9 @@ def measure_plain(args):
 
 
 def measure_side(args, workload, steps, warm, kernel_steps, copy_gbs):
-    """A side workload: autotuned (quick), warmed up, steps timed, then the kernel
-    table with the dominant kernel's roofline."""
+    """A side workload in its fixed launch shape (SIDE_TUNING; quick autotuning
+    with --tune-side), warmed up, steps timed, then the kernel table with the
+    dominant kernel's roofline."""
     from paper_0802_3775_amd import fdtd, tune
     total = warm + steps + kernel_steps
     cfg = headline_config(total, workload)
@@ -328,8 +329,8 @@ def measure_cpu(workload, budget_s):
 
 
 def measure_batched(args, kernel_steps=30):
-    """The batched ensemble (64 uneven realizations) against the same
-    realizations stepped one after another, each alone; the batch's dominant
+    """The batched ensemble (64 uneven realizations, BATCH_TUNING) against the same
+    realizations stepped one after another, each alone (SEQ_TUNING); the batch's dominant
     kernel class is timed per launch (hipEvents bound to the launches) against
     the summed algorithmic bytes of its members' tiles."""
     import torch
