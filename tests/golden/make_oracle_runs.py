@@ -67,6 +67,9 @@ RUNS = {
     # the same box with the density-matrix dye (inverted start, pump 1e10 s^-1, seeded noise)
     "lasing_density168": (lambda: W.lasing(pump=1e10, steps=600, energy_interval=100, model="density"),
                           (200, 600)),
+    # the paper's linear box (200^3, 8^3 cells at 16 cells/a, gamma 0.05, TEM00
+    # beam, CPML on all faces) until the pulse has crossed it
+    "paper_beam_3k": (lambda: W.paper_beam(0.05, seed=9, steps=3000), (1000, 3000)),
     # the paper's lasing box (200^3, 8^3 cells of inverted opal at 16 cells/a,
     # gamma 0.1, density-matrix dye in the voids, pump 1e10 s^-1, seeded noise)
     "paper_lasing_400": (lambda: W.paper_lasing(0.1, steps=400, energy_interval=100), (100, 400)),

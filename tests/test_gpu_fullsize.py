@@ -167,6 +167,20 @@ def test_density_lasing_box_168():
     plan.close()
 
 
+def test_paper_beam_box_200():
+    """The paper's linear box (200^3: 8^3 cells of the inverted opal at 16
+    cells/a, gamma 0.05, the TEM00 beam, CPML on all faces) for 3,000 steps, as
+    the pulse crosses it, in the autotuned launch shape: fields at 1,000 and 3,000
+    steps, the probe and T(t) at the output plane."""
+    plan, fx = _run_checkpoints("paper_beam_3k", 1e-4)
+    probe_err = rel_l2(plan.probe(0), fx["probe0"])
+    T_err = rel_l2(plan.flux(0)[0], fx["T0"])
+    _say("probe", probe_err, "T(t)", T_err, "peak T", float(np.abs(fx["T0"]).max()))
+    assert probe_err <= 1e-4
+    assert T_err <= 1e-3
+    plan.close()
+
+
 def test_paper_lasing_box_200():
     """The paper's lasing box (200^3: 8^3 cells of the eps-12 inverted opal at 16
     cells/a, gamma 0.1, the density-matrix dye in the voids, inverted start, pump
