@@ -64,6 +64,9 @@ RUNS = {
     "slab_d10_4k": (lambda: W.slab(delta=0.10, seed=14, steps=4000, nf=100, decim=8), (4000,)),
     # the Maxwell-Bloch lasing box (Lorentz medium), pump 1e10 s^-1, seeded noise
     "lasing168_p1e10": (lambda: W.lasing(pump=1e10, steps=2000, energy_interval=100), (500, 1000, 2000)),
+    # ... at the weakest pump of the workload's range, 1e7 s^-1: per step the
+    # populations move ~1e-9, below half an FP32 ulp of the larger levels
+    "lasing168_p1e7": (lambda: W.lasing(pump=1e7, steps=2000, energy_interval=100), (1000, 2000)),
     # the same box with the density-matrix dye (inverted start, pump 1e10 s^-1, seeded noise)
     "lasing_density168": (lambda: W.lasing(pump=1e10, steps=600, energy_interval=100, model="density"),
                           (200, 600)),

@@ -156,6 +156,18 @@ def test_lasing_box_168_at_pump_1e10():
     plan.close()
 
 
+def test_lasing_box_168_at_pump_1e7():
+    """The same box at the weakest pump of the workload's range, 1e7 s^-1, for
+    2000 steps: each step moves the populations by ~3e-10, below half an FP32
+    ulp of the ground level, so only the (hi, lo) pairs keep the change, and the
+    FP64 readout of the pairs shows it: population changes against the oracle's
+    at two checkpoints, with fields, polarization, probe and energy."""
+    plan, fx = _run_checkpoints("lasing168_p1e7", 1e-3)
+    assert rel_l2(plan.probe(0), fx["probe0"]) <= 1e-3
+    assert rel_l2(plan.energy(), fx["energy"]) <= 1e-3
+    plan.close()
+
+
 def test_density_lasing_box_168():
     """The same 168^3 box with the density-matrix dye in the voids (inverted
     start, pump 1e10 s^-1, seeded noise) for 600 steps in the autotuned launch
