@@ -2,8 +2,8 @@
 
 The FP64 oracle takes minutes to hours for the full-size workloads (the slab
 for femtosecond-pulse transmission at 80x80x224 for its full 20,000 steps, the
-168^3 lasing box, the 320^3 grid), too long to run beside the GPU inside the
-test suite.  This script runs them on the CPU once and stores what the tests
+168^3 lasing boxes, the paper's 200^3 beam and lasing boxes, the 320^3 grid),
+too long to run beside the GPU inside the test suite.  This script runs them on the CPU once and stores what the tests
 compare: every field component at a seeded sample of cells at a few
 checkpoints, the transmitted power T(t), the flux spectra, the probe and energy
 records, and for gain runs the populations and polarization (and for the
