@@ -1701,6 +1701,11 @@ __global__ __launch_bounds__(FD_DM_EDGES) void dm_edges_kernel(const fd_dm_unit*
   const size_t ncs = (size_t)d->ncell;
   const uint32_t o = ((const __attribute__((address_space(1))) uint32_t*)d->elist)[u.first + t];
   const Nbr b = neighbours(d, ijk_of(d, o));
+  // the cell's A and material go out with the sharers' Q (one round trip)
+  float ev[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) ev[c] = G((const float*)d->E[par ^ 1][c])[o];
+  const uint32_t mo = ((const gu8*)d->mat)[o];
   float acc[3];
   bool held[3];
   bool any = false;
@@ -1721,10 +1726,7 @@ __global__ __launch_bounds__(FD_DM_EDGES) void dm_edges_kernel(const fd_dm_unit*
     any = any | (!held[c] & (acc[c] != 0.0f));
   }
   if (!any) return;
-  const float ie = sm.m[((const gu8*)d->mat)[o]].inv_eps;
-  float ev[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) ev[c] = G((const float*)d->E[par ^ 1][c])[o];
+  const float ie = sm.m[mo].inv_eps;
 #pragma unroll
   for (int c = 0; c < 3; ++c)
     if (!held[c] && acc[c] != 0.0f) G(d->E[par ^ 1][c])[o] = ev[c] - 0.25f * acc[c] * ie;
